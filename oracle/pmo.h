@@ -1,0 +1,115 @@
+/*
+ * pmo.h -- CPU oracle for hierarchical process mapping (test infrastructure).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, single-threaded C
+ * implementation of what the GPU path computes, written from the paper
+ * "GPU-Accelerated Algorithms for Process Mapping" (arXiv 2510.12196).  It is
+ * used by tests/, by the smoke check and by the benchmark's CPU-baseline leg,
+ * and by nothing else.  It shares no code with the GPU library.
+ *
+ * Conventions (the same for every function):
+ *   graph   : CSR with both directions of every undirected edge stored
+ *             (Section 2, "CSR Graph Format"): xadj int64[n+1], adjncy
+ *             int32[nnz], adjwgt int32[nnz] (> 0, symmetric), vwgt int32[n]
+ *             (> 0).  All pointers are host pointers.
+ *   hierarchy: levels l in [1,8], a[0] = a_1 (PEs per processor, innermost)
+ *             ... a[l-1] = a_l; d[i] = d_{i+1}.  k = a_1 * ... * a_l.
+ *   part    : int32[n] block (PE) ids in [0,k).
+ *   eps_ppm : imbalance in parts per million (eps = 0.03 -> 30000).
+ * All arithmetic is integer: int64 for costs, gains and block weights.
+ */
+#ifndef PMO_H
+#define PMO_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* statistics of one refinement run (Algorithm 6) */
+typedef struct {
+  int64_t j_initial;        /* J of the input mapping                      */
+  int64_t j_final;          /* J of the returned mapping                   */
+  int64_t maxw_initial;     /* heaviest block of the input mapping         */
+  int64_t maxw_final;       /* heaviest block of the returned mapping      */
+  int32_t iterations;       /* loop bodies executed                        */
+  int32_t lp_iterations;
+  int32_t weak_iterations;
+  int32_t strong_iterations;
+  int32_t feasible;         /* returned mapping satisfies L_max            */
+  int32_t pad_;
+} pmo_refine_stats;
+
+#define PMO_MAX_LEVELS 64
+/* statistics of one multilevel run */
+typedef struct {
+  int32_t levels;                         /* graphs in the hierarchy (>= 1) */
+  int32_t feasible;
+  int64_t j_final;
+  int64_t lmax;
+  int32_t level_n[PMO_MAX_LEVELS];
+  int64_t level_nnz[PMO_MAX_LEVELS];
+  int32_t level_iterations[PMO_MAX_LEVELS];  /* refinement loop bodies      */
+  int32_t level_hem_rounds[PMO_MAX_LEVELS];  /* rounds that built level t+1 */
+  double refine_seconds;                     /* time inside refinement      */
+  double total_seconds;
+} pmo_map_stats;
+
+/* ---- hierarchy and objective (Section 2) ---- */
+int64_t pmo_num_pes(int32_t levels, const int32_t *a);
+int32_t pmo_distance(int32_t levels, const int32_t *a, const int32_t *d,
+                     int32_t x, int32_t y);
+int64_t pmo_comm_cost(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                      const int32_t *adjwgt, const int32_t *part,
+                      int32_t levels, const int32_t *a, const int32_t *d);
+void pmo_block_weights(int32_t n, const int32_t *vwgt, const int32_t *part,
+                       int64_t k, int64_t *w_out);
+int64_t pmo_lmax(int64_t total_weight, int64_t k, int64_t eps_ppm);
+int64_t pmo_gain(const int64_t *xadj, const int32_t *adjncy,
+                 const int32_t *adjwgt, const int32_t *part,
+                 int32_t levels, const int32_t *a, const int32_t *d,
+                 int32_t v, int32_t b);
+
+/* ---- counter-based hash (splitmix64 output function) ---- */
+uint64_t pmo_hash(uint64_t seed, uint64_t word);
+
+/* ---- refinement (Section 3.2, Algorithms 4, 5 and 6) ---- */
+void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                  const int32_t *adjwgt, int32_t levels, const int32_t *a,
+                  const int32_t *d, int32_t *part, uint8_t *lock,
+                  int32_t *target_out, int64_t *gain_out, uint8_t *moved_out);
+void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                   const int32_t *adjwgt, const int32_t *vwgt, int64_t k,
+                   int32_t strong, int64_t lmax, int64_t sigma, uint64_t seed,
+                   int32_t level, int32_t iter, int32_t *part,
+                   uint8_t *moved_out);
+int64_t pmo_sigma(int64_t lmax, int64_t total_weight, int64_t k);
+int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                   const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                   const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                   uint64_t seed, int32_t level, int32_t *part,
+                   pmo_refine_stats *stats);
+
+/* ---- coarsening (Section 3.2: matching, contraction) ---- */
+int32_t pmo_hem(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                const int32_t *adjwgt, const int32_t *vwgt, int64_t lmax,
+                uint64_t seed, int32_t level, int32_t *match_out);
+int32_t pmo_coarse_map(int32_t n, const int32_t *match, int32_t *cmap_out);
+int64_t pmo_contract(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                     const int32_t *adjwgt, const int32_t *vwgt,
+                     const int32_t *cmap, int32_t nc, int64_t *cxadj,
+                     int32_t *cadjncy, int32_t *cadjwgt, int32_t *cvwgt);
+
+/* ---- initial partitioning and the multilevel driver ---- */
+void pmo_initial_partition(int32_t n, const int64_t *xadj,
+                           const int32_t *adjncy, const int32_t *vwgt,
+                           int32_t levels, const int32_t *a, int32_t *part_out);
+int32_t pmo_map(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                uint64_t seed, int32_t *part_out, pmo_map_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

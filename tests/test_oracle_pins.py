@@ -1,0 +1,508 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test states which definition it pins.  None of them re-derives an
+expected value by calling the oracle routine it checks: the expected values
+are hand-derived fixtures (tests/golden, each with its derivation), closed
+forms, brute force over tiny inputs, or invariants computed independently
+with numpy.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import gen
+from conftest import golden, graph_from_fixture
+
+
+# ----------------------------------------------------------------------------
+# independent helpers (numpy, written for the tests)
+# ----------------------------------------------------------------------------
+
+def digit_distance_matrix(a, d):
+    """D as a k x k matrix built top-down from mixed-radix digits (a_1 least
+    significant): two PEs are at distance d_j where j is the highest level at
+    which their digits differ."""
+    a = list(a)
+    k = int(np.prod(a))
+    ids = np.arange(k)
+    digits = []
+    p = 1
+    for ai in a:
+        digits.append((ids // p) % ai)
+        p *= ai
+    D = np.zeros((k, k), dtype=np.int64)
+    for j in range(len(a) - 1, -1, -1):
+        differ = digits[j][:, None] != digits[j][None, :]
+        D = np.where((D == 0) & differ, d[j], D)
+    return D
+
+
+def undirected_edges(g):
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    keep = src < g.adjncy
+    return src[keep], g.adjncy[keep].astype(np.int64), g.adjwgt[keep].astype(np.int64)
+
+
+def j_undirected(g, part, D):
+    u, v, w = undirected_edges(g)
+    return int((w * D[part[u], part[v]]).sum())
+
+
+def conn_table(g, part, k):
+    """conn[v, x] = sum of edge weights from v to block x (dense, small k)."""
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    c = np.zeros((g.n, k), dtype=np.int64)
+    np.add.at(c, (src, part[g.adjncy]), g.adjwgt.astype(np.int64))
+    return c
+
+
+def small_random_graph(n, p, seed, wmax=5, cmax=1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pairs = [(i, j) for i in range(n) for j in range(i + 1, n) if rng.random() < p]
+    if not pairs:
+        pairs = [(0, 1)]
+    e = np.array(pairs)
+    w = rng.integers(1, wmax + 1, size=len(pairs))
+    c = rng.integers(1, cmax + 1, size=n)
+    return gen.from_edges(n, e[:, 0], e[:, 1], w, c)
+
+
+HIERARCHIES = [((2, 2, 4), (1, 10, 100)), ((4, 8, 3), (1, 10, 100)),
+               ((3, 5), (2, 7)), ((4,), (1,)), ((2, 3, 1, 2), (1, 4, 9, 20))]
+
+
+# ----------------------------------------------------------------------------
+# splitmix64 counter-based hash
+# ----------------------------------------------------------------------------
+
+def test_hash_is_published_splitmix64_stream(pmo):
+    fx = golden("splitmix64.json")
+    s0 = fx["streams"][0]
+    assert [pmo.hash64(s0["seed"], i) for i in range(3)] == [int(h, 16) for h in s0["outputs_hex"]]
+    s1 = fx["streams"][1]
+    assert [pmo.hash64(s1["seed"], i) for i in range(5)] == s1["outputs"]
+
+
+# ----------------------------------------------------------------------------
+# D (Section 2, hierarchy and distances)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("a,d", HIERARCHIES)
+def test_distance_matches_digit_matrix(pmo, a, d):
+    D = digit_distance_matrix(a, d)
+    k = D.shape[0]
+    got = np.array([[pmo.distance(a, d, x, y) for y in range(k)] for x in range(k)])
+    assert np.array_equal(got, D)
+
+
+@pytest.mark.parametrize("a,d", [h for h in HIERARCHIES if list(h[1]) == sorted(h[1])])
+def test_distance_is_ultrametric(pmo, a, d):
+    k = pmo.num_pes(a)
+    D = np.array([[pmo.distance(a, d, x, y) for y in range(k)] for x in range(k)])
+    assert (np.diag(D) == 0).all()
+    assert np.array_equal(D, D.T)
+    # D(x,z) <= max(D(x,y), D(y,z)) for non-decreasing distances
+    assert (D[:, None, :] <= np.maximum(D[:, :, None], D[None, :, :])).all()
+
+
+def test_distance_row_sums_closed_form(pmo):
+    for case in golden("distance_row_sums.json")["cases"]:
+        a, d = case["a"], case["d"]
+        k = pmo.num_pes(a)
+        for x in {0, k // 2, k - 1}:
+            assert sum(pmo.distance(a, d, x, y) for y in range(k)) == case["row_sum"]
+
+
+# ----------------------------------------------------------------------------
+# J (Section 2, GPMP objective)
+# ----------------------------------------------------------------------------
+
+def test_comm_cost_grid_tiling_closed_form(pmo):
+    fx = golden("grid64_tiling.json")
+    g = gen.grid2d(64, 64)
+    i, j = np.arange(4096) // 64, np.arange(4096) % 64
+    r, c = i // 16, j // 16
+    pe = ((c & 1) + 2 * (r & 1) + 4 * (c >> 1) + 8 * (r >> 1)).astype(np.int32)
+    assert np.bincount(pe).tolist() == [fx["block_size"]] * 16
+    assert pmo.comm_cost(g, pe, (2, 2, 4), (1, 10, 100)) == fx["J_ordered"]
+    u, v, _ = undirected_edges(g)
+    assert int((pe[u] != pe[v]).sum()) == fx["cut_edges"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_comm_cost_is_twice_undirected_sum(pmo, seed):
+    a, d = (4, 8, 3), (1, 10, 100)
+    g = gen.get("rgg14").graph()
+    part = gen.random_mapping(g.n, 96, seed)
+    J = pmo.comm_cost(g, part, a, d)
+    assert J % 2 == 0
+    assert J == 2 * j_undirected(g, part, digit_distance_matrix(a, d))
+
+
+def test_unit_distances_reduce_to_edge_cut(pmo):
+    g = gen.get("rmat14").graph()
+    part = gen.random_mapping(g.n, 16, 5)
+    u, v, w = undirected_edges(g)
+    cut = int(w[part[u] != part[v]].sum())
+    assert pmo.comm_cost(g, part, (2, 2, 4), (1, 1, 1)) == 2 * cut
+
+
+# ----------------------------------------------------------------------------
+# gains (equation (1))
+# ----------------------------------------------------------------------------
+
+def test_single_move_changes_J_by_twice_the_gain(pmo):
+    a, d = (2, 2, 4), (1, 10, 100)
+    g = gen.get("rmat14").graph()
+    part = gen.random_mapping(g.n, 16, 9)
+    rng = np.random.Generator(np.random.PCG64(3))
+    J0 = pmo.comm_cost(g, part, a, d)
+    for v in rng.integers(0, g.n, size=40):
+        b = int(rng.integers(0, 16))
+        moved = part.copy()
+        moved[v] = b
+        assert pmo.comm_cost(g, moved, a, d) == J0 - 2 * pmo.gain(g, part, a, d, int(v), b)
+
+
+def test_gain_with_one_level_is_connectivity_difference(pmo):
+    g = gen.get("rgg14").graph()
+    part = gen.random_mapping(g.n, 8, 4)
+    C = conn_table(g, part, 8)
+    for v in range(0, g.n, 997):
+        for b in range(8):
+            expect = 3 * (C[v, b] - C[v, part[v]])
+            assert pmo.gain(g, part, (8,), (3,), v, b) == expect
+
+
+def level_projection_cost(C_row, b, a, d):
+    """sum_x conn(v,x) D(b,x) via group sums S_i(b) over the level-i group of b
+    (S_0 = conn(v,b), S_l = total): cost = sum_i d_i (S_i - S_{i-1})."""
+    k = C_row.shape[0]
+    S_prev = C_row[b]
+    cost = 0
+    p = 1
+    for ai, di in zip(a, d):
+        p *= ai
+        grp = (np.arange(k) // p) == (b // p)
+        S = C_row[grp].sum()
+        cost += di * (S - S_prev)
+        S_prev = S
+    return cost
+
+
+def test_gain_three_formulas_agree(pmo):
+    a, d = (4, 8, 3), (1, 10, 100)
+    k = 96
+    g = gen.get("rmat14").graph()
+    part = gen.random_mapping(g.n, k, 11)
+    C = conn_table(g, part, k)
+    # formula 2: the first-filter gains produced by a label-propagation round
+    _, _, target, gain, _ = pmo.lp_round(g, a, d, part, np.zeros(g.n, np.uint8))
+    checked = 0
+    for v in range(0, g.n, 61):
+        blocks = np.nonzero(C[v])[0]
+        cand = [b for b in blocks if b != part[v]]
+        if not cand:
+            assert gain[v] == np.iinfo(np.int64).min
+            continue
+        own = level_projection_cost(C[v], part[v], a, d)
+        g3 = {b: own - level_projection_cost(C[v], b, a, d) for b in cand}
+        for b in cand:
+            assert pmo.gain(g, part, a, d, v, int(b)) == g3[b]          # formula 1
+        best = max(cand, key=lambda b: (g3[b], -b))
+        if g3[best] >= 0:
+            assert (target[v], gain[v]) == (best, g3[best])
+            checked += 1
+        else:
+            assert gain[v] == np.iinfo(np.int64).min
+    assert checked > 10
+
+
+# ----------------------------------------------------------------------------
+# label propagation (Algorithm 4)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fixture", ["lp_round_p7.json", "lp_round_earlier_member.json"])
+def test_lp_round_hand_examples(pmo, fixture):
+    fx = golden(fixture)
+    g = graph_from_fixture(fx)
+    a, d = fx["a"], fx["d"]
+    part0 = np.array(fx["part_in"], np.int32)
+    assert pmo.comm_cost(g, part0, a, d) == fx["J_before"]
+    part, lock, target, gain, moved = pmo.lp_round(g, a, d, part0, np.zeros(g.n, np.uint8))
+    nin = np.iinfo(np.int64).min
+    assert [None if x == nin else int(x) for x in gain] == fx["gain"]
+    assert target.tolist() == fx["target"]
+    assert moved.tolist() == fx["moved"]
+    assert lock.tolist() == fx["moved"]
+    assert part.tolist() == fx["part_out"]
+    assert pmo.comm_cost(g, part, a, d) == fx["J_after"]
+
+
+def test_lp_locked_vertices_do_not_move(pmo):
+    fx = golden("lp_round_p7.json")
+    g = graph_from_fixture(fx)
+    lock = np.array([1, 0, 0, 0], np.uint8)
+    part, lock2, target, gain, moved = pmo.lp_round(g, fx["a"], fx["d"], fx["part_in"], lock)
+    # 0 is locked, so 1 is alone in X: it re-evaluates to 40 and moves to block 0
+    assert gain[0] == np.iinfo(np.int64).min and gain[1] == 40
+    assert moved.tolist() == [0, 1, 0, 0]
+    assert part.tolist() == [0, 0, 0, 2]
+
+
+def test_lp_round_sequential_replay_telescopes(pmo):
+    """Applying the moved set one vertex at a time in the implicit order, each
+    move's exact gain in the state before it adds up to the J difference."""
+    a, d = (4, 8, 8), (1, 10, 100)
+    g = gen.get("rgg14").graph()
+    part0 = gen.random_balanced_mapping(g.n, 256, 7)
+    part, _, target, gain, moved = pmo.lp_round(g, a, d, part0, np.zeros(g.n, np.uint8))
+    order = sorted(np.nonzero(moved)[0], key=lambda v: (-gain[v], v))
+    state = part0.copy()
+    total = 0
+    for v in order:
+        total += pmo.gain(g, state, a, d, int(v), int(target[v]))
+        state[v] = target[v]
+    assert np.array_equal(state, part)
+    assert pmo.comm_cost(g, part0, a, d) - pmo.comm_cost(g, part, a, d) == 2 * total
+
+
+# ----------------------------------------------------------------------------
+# rebalancing (Algorithm 5 and the text around it)
+# ----------------------------------------------------------------------------
+
+def test_weak_rebalance_hand_example(pmo):
+    fx = golden("weak_rebalance_buckets.json")
+    g = graph_from_fixture(fx)
+    total, k = int(g.vwgt.sum()), 2
+    lm = pmo.lmax(total, k, fx["eps"])
+    sg = pmo.sigma(lm, total, k)
+    assert (lm, sg) == (3, 3)
+    for seed in (1, 2, 3):
+        part, moved = pmo.rebalance(g, k, fx["part_in"], False, lm, sg, seed, 0, 1)
+        assert moved.tolist() == fx["moved"]
+        assert part.tolist() == fx["part_out"]
+
+
+def test_strong_rebalance_balances_unit_weights(pmo):
+    g = gen.get("rgg14").graph()
+    k, a, d = 64, (4, 4, 4), (1, 10, 100)
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    part = gen.random_mapping(g.n, k, 3)
+    part[: g.n // 8] = 0  # overload block 0 heavily
+    w0 = pmo.block_weights(g, part, k)
+    assert w0.max() > lm
+    p2, moved = pmo.rebalance(g, k, part, True, lm, sg, 1, 0, 1)
+    w1 = pmo.block_weights(g, p2, k)
+    assert w1.max() <= lm
+    assert w1.sum() == w0.sum()
+    # only vertices of overloaded blocks move
+    assert (w0[part[moved.astype(bool)]] > lm).all()
+
+
+def test_weak_rebalance_moves_only_from_overloaded(pmo):
+    g = gen.get("rmat14").graph()
+    k = 128
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    part = gen.random_mapping(g.n, k, 8)
+    w0 = pmo.block_weights(g, part, k)
+    p2, moved = pmo.rebalance(g, k, part, False, lm, sg, 1, 0, 1)
+    mv = moved.astype(bool)
+    assert (w0[part[mv]] > lm).all()
+    assert (w0[p2[mv]] <= sg).all()
+    # moved weight per source block covers the excess by less than one vertex
+    w1 = pmo.block_weights(g, p2, k)
+    out = np.bincount(part[mv], weights=g.vwgt[mv], minlength=k).astype(np.int64)
+    over = w0 > lm
+    # the moved prefix stops as soon as it covers the excess
+    assert (out[over] < (w0 - lm)[over] + g.vwgt.max()).all()
+    assert (out[over] > 0).all()
+    assert w1.sum() == w0.sum()
+
+
+# ----------------------------------------------------------------------------
+# refinement controller (Algorithm 6)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name,seed", [("grid64", 1), ("rgg14", 2), ("rmat14", 3)])
+def test_refine_balance_invariant_and_monotone(pmo, name, seed):
+    w = gen.get(name)
+    g = w.graph()
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, w.k, w.eps)
+    start = gen.random_balanced_mapping(g.n, w.k, seed)
+    if pmo.block_weights(g, start, w.k).max() > lm:
+        start = pmo.initial_partition(g, w.a)
+    rc, part, st = pmo.refine(g, w.a, w.d, w.eps, seed, start)
+    wb = pmo.block_weights(g, part, w.k)
+    J = pmo.comm_cost(g, part, w.a, w.d)
+    assert st.j_final == J and st.maxw_final == wb.max()
+    if pmo.block_weights(g, start, w.k).max() <= lm:
+        assert rc == 0 and wb.max() <= lm
+        assert J <= st.j_initial
+    assert np.bincount(part, minlength=w.k).sum() == g.n
+
+
+def test_refine_from_imbalanced_start_reaches_balance(pmo):
+    w = gen.get("rgg14")
+    g = w.graph()
+    start = gen.random_mapping(g.n, w.k, 1)
+    start[: g.n // 4] = 3
+    rc, part, st = pmo.refine(g, w.a, w.d, w.eps, 5, start)
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    assert rc == 0 and pmo.block_weights(g, part, w.k).max() <= lm
+    assert st.weak_iterations + st.strong_iterations > 0
+
+
+def brute_force(g, a, d, eps, pmo):
+    D = digit_distance_matrix(a, d)
+    k = D.shape[0]
+    n = g.n
+    lm = pmo.lmax(int(g.vwgt.sum()), k, eps)
+    u, v, w = undirected_edges(g)
+    all_maps = np.array(list(itertools.product(range(k), repeat=n)), dtype=np.int64)
+    J = 2 * (w[None, :] * D[all_maps[:, u], all_maps[:, v]]).sum(axis=1)
+    wts = np.zeros((all_maps.shape[0], k), np.int64)
+    for b in range(k):
+        wts[:, b] = ((all_maps == b) * g.vwgt[None, :]).sum(axis=1)
+    ok = wts.max(axis=1) <= lm
+    best = np.argmin(np.where(ok, J, np.iinfo(np.int64).max))
+    return int(J[best]), all_maps[best].astype(np.int32)
+
+
+@pytest.mark.parametrize("n,seed", [(6, 1), (7, 2), (8, 3), (8, 4)])
+def test_brute_force_optimum(pmo, n, seed):
+    a, d, eps = (2, 2), (1, 10), 0.03
+    g = small_random_graph(n, 0.5, seed, wmax=6)
+    Jstar, pstar = brute_force(g, a, d, eps, pmo)
+    rc, part, st = pmo.map_graph(g, a, d, eps, seed)
+    assert rc == 0
+    assert pmo.comm_cost(g, part, a, d) >= Jstar
+    # refining an optimal mapping returns it unchanged
+    rc2, part2, st2 = pmo.refine(g, a, d, eps, seed, pstar)
+    assert rc2 == 0 and np.array_equal(part2, pstar) and st2.j_final == Jstar
+
+
+# ----------------------------------------------------------------------------
+# order invariance (rows shuffled -> identical results)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14", "rmat14"])
+def test_row_order_invariance(pmo, name):
+    w = gen.get(name)
+    g = w.graph()
+    gs = gen.shuffle_rows(g, 99)
+    rc1, p1, s1 = pmo.map_graph(g, w.a, w.d, w.eps, 3)
+    rc2, p2, s2 = pmo.map_graph(gs, w.a, w.d, w.eps, 3)
+    assert rc1 == rc2 and np.array_equal(p1, p2) and s1.j_final == s2.j_final
+
+
+# ----------------------------------------------------------------------------
+# matching and contraction (Section 3.2)
+# ----------------------------------------------------------------------------
+
+def test_hem_hand_example(pmo):
+    fx = golden("hem_rating.json")
+    g = graph_from_fixture(fx)
+    rounds, match = pmo.hem(g, fx["lmax"], 1)
+    assert match.tolist() == fx["match"] and rounds == fx["rounds"]
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14", "rmat14"])
+def test_hem_matching_properties(pmo, name):
+    w = gen.get(name)
+    g = w.graph()
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    rounds, match = pmo.hem(g, lm, 7)
+    assert rounds < 64
+    v = np.arange(g.n)
+    assert np.array_equal(match[match], v)                      # an involution
+    paired = match != v
+    assert (g.vwgt[v[paired]] + g.vwgt[match[paired]] <= lm).all()
+    deg = np.diff(g.xadj)
+    # pairs are edges, except isolated twins
+    src = np.repeat(v, deg)
+    is_edge = set(zip(src.tolist(), g.adjncy.tolist()))
+    for x in v[paired]:
+        if deg[x] > 0:
+            assert (int(x), int(match[x])) in is_edge
+        else:
+            assert deg[match[x]] == 0
+    # maximality: no eligible edge joins two unmatched vertices
+    un = ~paired
+    both = un[src] & un[g.adjncy] & (g.vwgt[src] + g.vwgt[g.adjncy] <= lm)
+    assert not both.any()
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14", "rmat14"])
+def test_contraction_properties(pmo, name):
+    w = gen.get(name)
+    g = w.graph()
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    _, match = pmo.hem(g, lm, 7)
+    nc, cmap = pmo.coarse_map(match)
+    # coarse ids: ranks of the smaller member, so cmap is non-decreasing over leaders
+    leaders = np.nonzero(match >= np.arange(g.n))[0]
+    assert np.array_equal(cmap[leaders], np.arange(nc))
+    assert np.array_equal(cmap, cmap[match])
+    cx, ca, cw, cv = pmo.contract(g, cmap, nc)
+    cg = gen.Graph(cx, ca, cw, cv)
+    assert cv.sum() == g.vwgt.sum()
+    # arc weight: every matched edge (both arcs) disappears, nothing else
+    v = np.arange(g.n)
+    src = np.repeat(v, np.diff(g.xadj))
+    internal = g.adjwgt[(match[src] == g.adjncy)].sum()
+    assert cw.astype(np.int64).sum() == g.adjwgt.astype(np.int64).sum() - internal
+    # symmetric rows, no self-loops, no duplicates
+    csrc = np.repeat(np.arange(nc), np.diff(cx))
+    assert (csrc != ca).all()
+    fw = dict(zip(zip(csrc.tolist(), ca.tolist()), cw.tolist()))
+    assert len(fw) == len(ca)
+    assert all(fw[(y, x)] == wt for (x, y), wt in fw.items())
+    # the objective and block weights survive projection
+    for seed in (1, 2):
+        pc = gen.random_mapping(nc, w.k, seed)
+        pf = pc[cmap]
+        assert pmo.comm_cost(cg, pc, w.a, w.d) == pmo.comm_cost(g, pf, w.a, w.d)
+        assert np.array_equal(pmo.block_weights(cg, pc, w.k), pmo.block_weights(g, pf, w.k))
+
+
+# ----------------------------------------------------------------------------
+# initial partitioning and the multilevel driver
+# ----------------------------------------------------------------------------
+
+def test_initial_partition_path_closed_form(pmo):
+    fx = golden("ip_path16.json")
+    g = gen.path_graph(fx["n"])
+    part = pmo.initial_partition(g, fx["a"])
+    assert part.tolist() == fx["part"]
+    assert pmo.comm_cost(g, part, fx["a"], fx["d"]) == fx["J_ordered"]
+
+
+def test_initial_partition_balance(pmo):
+    g = gen.get("rgg14").graph()
+    a = (4, 8, 8)
+    part = pmo.initial_partition(g, a)
+    w = np.bincount(part, minlength=256)
+    # every split cuts at the exact proportional weight: within one vertex per level
+    assert w.max() - w.min() <= 2 * len(a)
+
+
+@pytest.mark.parametrize("name,seed", [("grid64", 1), ("grid64", 2), ("rgg14", 1), ("rmat14", 1)])
+def test_map_balance_and_levels(pmo, name, seed):
+    w = gen.get(name)
+    g = w.graph()
+    rc, part, st = pmo.map_graph(g, w.a, w.d, w.eps, seed)
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    assert st.lmax == lm
+    assert rc == 0 and pmo.block_weights(g, part, w.k).max() <= lm
+    assert st.j_final == pmo.comm_cost(g, part, w.a, w.d)
+    ns = list(st.level_n[: st.levels])
+    assert ns[0] == g.n and all(x > y for x, y in zip(ns, ns[1:]))
+    for x, y in zip(ns, ns[1:]):
+        assert 20 * y <= 19 * x
