@@ -1,0 +1,218 @@
+/*
+ * pm.h -- C ABI of the MI355X (gfx950) hierarchical process-mapping library.
+ *
+ * The library computes, on one GPU, the data-parallel hot path of the
+ * integrated multilevel process-mapping method of "GPU-Accelerated Algorithms
+ * for Process Mapping" (arXiv 2510.12196, Section 3.2): refinement of a
+ * mapping Pi of a task graph onto the PEs of a hierarchical machine under the
+ * communication cost J (Section 2), heavy-edge-matching coarsening, CSR
+ * contraction, initial partitioning of the coarsest graph, and projection of
+ * Pi through the levels.
+ *
+ * Common conventions
+ * ------------------
+ * Graph (pm_graph): undirected, both directions of every edge stored (CSR as
+ *   in Section 2 "CSR Graph Format").  All arrays live in DEVICE memory owned
+ *   by the caller and are only read:
+ *     xadj   int64[n+1], xadj[0] = 0, non-decreasing, xadj[n] = nnz
+ *     adjncy int32[nnz]  neighbour ids in [0,n), no self-loops, no duplicate
+ *                        neighbour within a row, symmetric
+ *     adjwgt int32[nnz]  edge weights > 0, w(u,v) = w(v,u)
+ *     vwgt   int32[n]    vertex weights > 0
+ *   Row order inside xadj ranges is irrelevant: every result is identical
+ *   for any order of the entries of a row.
+ *   Limits: n < 2^31, nnz < 2^31, sum(vwgt) < 2^31, sum(adjwgt) < 2^31.
+ * Hierarchy (pm_hierarchy): a[0] = a_1 (PEs per processor, innermost level)
+ *   ... a[levels-1] = a_l; d[i] = distance d_{i+1} of level i+1.  k = prod a.
+ *   PE ids are mixed-radix numbers with a_1 the least significant digit;
+ *   PEs x != y first share a component at level j (the smallest j with
+ *   floor(x/P_j) == floor(y/P_j), P_j = a_1*...*a_j) and are at distance d_j;
+ *   D(x,x) = 0.  Limits: 1 <= levels <= 8, a_i >= 1, 0 <= d_i < 2^30,
+ *   sum over i of ceil(log2 a_i) <= 13 (k <= 8192 when all a_i are powers of
+ *   two).
+ * Mapping: int32[n] PE ids in [0,k), device memory.
+ * eps: imbalance; L_max = ceil((1+eps) c(V) / k) evaluated exactly with eps
+ *   rounded to parts per million.
+ * stream: a hipStream_t passed as void*; NULL is the default stream.  Every
+ *   function enqueues its work on that stream and returns after the results
+ *   are complete (it synchronises the stream).
+ * Scratch memory is allocated by the library (hipMalloc, cached per device and
+ *   reused across calls, released by pm_release).  Calls may come from
+ *   several host threads; each call uses its own scratch.
+ * Return codes: PM_OK (0), PM_WARN_IMBALANCED (1, result written but not
+ *   within L_max), negative on error (nothing written to outputs):
+ *   PM_EINVAL (bad argument), PM_EGRAPH (graph fails validation, only checked
+ *   when PM_FLAG_VALIDATE is given), PM_EOVERFLOW (a limit above is
+ *   exceeded), PM_ENOMEM, PM_EHIP (HIP runtime error), PM_ENODEVICE.
+ */
+#ifndef PM_H
+#define PM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PM_OK 0
+#define PM_WARN_IMBALANCED 1
+#define PM_EINVAL (-1)
+#define PM_EGRAPH (-2)
+#define PM_EOVERFLOW (-3)
+#define PM_ENOMEM (-4)
+#define PM_EHIP (-5)
+#define PM_ENODEVICE (-6)
+
+#define PM_FLAG_VALIDATE 1u
+/* pm_map: time every launch of the kernels listed under pm_map_stats with
+ * start/stop events (adds a little host work per launch) */
+#define PM_FLAG_KERNEL_TIMES 2u
+#define PM_TIMED_KERNELS 4
+
+#define PM_MAX_LEVELS 8
+#define PM_MAX_GRAPH_LEVELS 64
+
+typedef struct pm_graph {
+  int32_t n;
+  int64_t nnz;
+  const int64_t *xadj;
+  const int32_t *adjncy;
+  const int32_t *adjwgt;
+  const int32_t *vwgt;
+} pm_graph;
+
+typedef struct pm_hierarchy {
+  int32_t levels;
+  int32_t a[PM_MAX_LEVELS];
+  int32_t d[PM_MAX_LEVELS];
+} pm_hierarchy;
+
+/* Statistics of one refinement run (Algorithm 6).  Host struct. */
+typedef struct pm_refine_stats {
+  int64_t j_initial;         /* J of the input mapping                    */
+  int64_t j_final;           /* J of the returned mapping                 */
+  int64_t maxw_initial;      /* heaviest block of the input mapping       */
+  int64_t maxw_final;        /* heaviest block of the returned mapping    */
+  int32_t iterations;        /* loop bodies executed                      */
+  int32_t lp_iterations;
+  int32_t weak_iterations;
+  int32_t strong_iterations;
+  int32_t feasible;          /* returned mapping within L_max             */
+  int32_t pad_;
+  double refine_ms;          /* device time of the refinement kernels     */
+  int64_t arcs_processed;    /* iterations x nnz (logical arcs)           */
+} pm_refine_stats;
+
+/* Statistics of one multilevel run.  Host struct. */
+typedef struct pm_map_stats {
+  int32_t levels;                               /* graphs incl. the input */
+  int32_t feasible;
+  int64_t j_final;
+  int64_t lmax;
+  int32_t level_n[PM_MAX_GRAPH_LEVELS];
+  int64_t level_nnz[PM_MAX_GRAPH_LEVELS];
+  int32_t level_iterations[PM_MAX_GRAPH_LEVELS];
+  int32_t level_hem_rounds[PM_MAX_GRAPH_LEVELS];
+  double coarsen_ms;       /* matching rounds                             */
+  double contract_ms;      /* coarse numbering + contraction              */
+  double initial_ms;       /* coarsest graph to host, partition, back     */
+  double uncoarsen_ms;     /* projections                                 */
+  double refine_ms;        /* refinement incl. rebalancing, all levels    */
+  double total_ms;         /* whole call, host wall clock                 */
+  int64_t refine_arcs;     /* sum over levels of iterations x nnz         */
+  /* With PM_FLAG_KERNEL_TIMES: per timed kernel -- [0] label propagation
+   * phase 1, [1] phase 2, [2] move accounting, [3] matching preference --
+   * the launches, their summed device time (start/stop events of each
+   * launch) and, for [0], the algorithmic bytes (12 per arc + 25 per
+   * vertex: neighbour id, edge weight and neighbour block per arc; row
+   * offset, block, lock, target and gain per vertex). */
+  int64_t kernel_launches[PM_TIMED_KERNELS];
+  double kernel_ms[PM_TIMED_KERNELS];
+  double kernel_bytes[PM_TIMED_KERNELS];
+} pm_map_stats;
+
+/* Library version string. */
+const char *pm_version(void);
+/* Message for a return code. */
+const char *pm_strerror(int code);
+/* Frees cached scratch memory of every device.  Not to be called while any
+ * other pm_* call is running. */
+void pm_release(void);
+
+/* J(Pi) = sum over all arcs (u,v) of w(u,v) * D(Pi(u),Pi(v)) (Section 2,
+ * GPMP objective; both directions of each edge count, so J is twice the sum
+ * over undirected edges).  part: device int32[n].  j_out: HOST int64. */
+int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part,
+                 int64_t *j_out, uint32_t flags, void *stream);
+
+/* Block weights c(V_b) for b in [0,k) (Section 2).  w_out: device int64[k]. */
+int pm_block_weights(const pm_graph *g, const pm_hierarchy *h,
+                     const int32_t *part, int64_t *w_out, void *stream);
+
+/* One round of unconstrained label propagation (Section 3.2, Algorithm 4,
+ * equation (1), implicit order by (gain desc, id asc), second filter under
+ * the approximate future state, moved vertices locked).
+ * part: device int32[n], in/out.  lock: device uint8[n], in/out (nonzero =
+ * locked; on return exactly the moved vertices are locked).  target_out:
+ * device int32[n] (best block, or own block when not in the first-filter
+ * set).  gain_out: device int64[n] (INT64_MIN when not in that set).
+ * moved_out: device uint8[n]. */
+int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part,
+                uint8_t *lock, int32_t *target_out, int64_t *gain_out,
+                uint8_t *moved_out, void *stream);
+
+/* One weak (strong = 0) or strong (strong = 1) rebalancing round (Section
+ * 3.2, Rebalancing, Algorithm 5) with the edge-cut loss; lmax and sigma as
+ * host integers; (seed, level, iter) select the pseudo-random fallback
+ * destinations.  part: device int32[n], in/out.  moved_out: device uint8[n]. */
+int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong,
+                 int64_t lmax, int64_t sigma, uint64_t seed, int32_t level,
+                 int32_t iter, int32_t *part, uint8_t *moved_out, void *stream);
+
+/* Refinement (Section 3.2, Algorithm 6): label propagation while balanced,
+ * otherwise up to two weak then one strong rebalancing; keeps the best
+ * mapping; stops after 12 loop bodies without sufficient improvement.
+ * part: device int32[n], in/out (input mapping, returned best mapping).
+ * level: tag mixed into the pseudo-random choices (0 for a single graph).
+ * stats: host, may be NULL.  Returns PM_OK or PM_WARN_IMBALANCED. */
+int pm_refine(const pm_graph *g, const pm_hierarchy *h, double eps,
+              uint64_t seed, int32_t level, int32_t *part,
+              pm_refine_stats *stats, void *stream);
+
+/* Heavy-edge matching rounds (Section 3.2, Matching): rating w^2/(c(u)c(v)),
+ * exact comparison with a hash tie-break, mutual preference, rounds until no
+ * new match; then, if at most 75 % of the vertices are matched, isolated
+ * vertices are paired in id order.  match_out: device int32[n] (partner, or
+ * the vertex itself).  rounds_out: host int32, may be NULL. */
+int pm_hem(const pm_graph *g, int64_t lmax, uint64_t seed, int32_t level,
+           int32_t *match_out, int32_t *rounds_out, void *stream);
+
+/* Coarse numbering and contraction (Section 3.2, Contraction): coarse id =
+ * rank of the smaller member; coarse vertex weight = sum; arcs mapped, self
+ * loops dropped, parallel arcs fused with summed weights.  Outputs (device,
+ * caller-allocated at the fine sizes): cmap int32[n], cxadj int64[n+1],
+ * cadjncy int32[nnz], cadjwgt int32[nnz], cvwgt int32[n]; nc_out and
+ * nnz_out are host.  Coarse rows come out sorted by neighbour id. */
+int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap,
+                int64_t *cxadj, int32_t *cadjncy, int32_t *cadjwgt,
+                int32_t *cvwgt, int32_t *nc_out, int64_t *nnz_out,
+                void *stream);
+
+/* Initial partitioning (Section 3.2): hierarchical multisection (Section
+ * 3.1, Algorithm 2) with a breadth-first split as the simple partitioner,
+ * run on the host on a copy of the graph.  part_out: device int32[n]. */
+int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h,
+                         int32_t *part_out, void *stream);
+
+/* The whole multilevel mapping (Section 3.2): coarsen while n >= 8k (stop
+ * when a level would keep more than 95 % of the vertices, at most 64
+ * graphs), initial partitioning, then project and refine level by level.
+ * part_out: device int32[n].  stats: host, may be NULL. */
+int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps,
+           uint64_t seed, int32_t *part_out, pm_map_stats *stats,
+           uint32_t flags, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

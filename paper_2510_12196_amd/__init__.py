@@ -1,0 +1,319 @@
+"""MI355X (gfx950) hierarchical process mapping -- Python binding.
+
+A thin ctypes layer over ``libpm.so`` (C ABI declared in ``include/pm.h``).
+Every function has the name of its C entry point and only marshals
+arguments: device arrays are torch tensors on a ROCm device, passed by
+``data_ptr()``, with torch's current stream.  All computation runs in the
+library's HIP kernels; there is no CPU fallback -- if ``libpm.so`` is missing
+or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpm.so")
+
+PM_OK = 0
+PM_WARN_IMBALANCED = 1
+PM_EINVAL = -1
+PM_EGRAPH = -2
+PM_EOVERFLOW = -3
+PM_ENOMEM = -4
+PM_EHIP = -5
+PM_ENODEVICE = -6
+PM_FLAG_VALIDATE = 1
+PM_FLAG_KERNEL_TIMES = 2
+TIMED_KERNELS = ("lp_phase1", "lp_phase2", "apply_moves", "hem_prefer")
+MAX_LEVELS = 8
+MAX_GRAPH_LEVELS = 64
+
+
+class PmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {_strerror(code)} ({code})")
+
+
+class PmGraph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("xadj", ctypes.c_void_p), ("adjncy", ctypes.c_void_p),
+                ("adjwgt", ctypes.c_void_p), ("vwgt", ctypes.c_void_p)]
+
+
+class PmHierarchy(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("a", ctypes.c_int32 * MAX_LEVELS),
+                ("d", ctypes.c_int32 * MAX_LEVELS)]
+
+
+class PmRefineStats(ctypes.Structure):
+    _fields_ = [("j_initial", ctypes.c_int64), ("j_final", ctypes.c_int64),
+                ("maxw_initial", ctypes.c_int64), ("maxw_final", ctypes.c_int64),
+                ("iterations", ctypes.c_int32), ("lp_iterations", ctypes.c_int32),
+                ("weak_iterations", ctypes.c_int32), ("strong_iterations", ctypes.c_int32),
+                ("feasible", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("refine_ms", ctypes.c_double), ("arcs_processed", ctypes.c_int64)]
+
+
+class PmMapStats(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("feasible", ctypes.c_int32),
+                ("j_final", ctypes.c_int64), ("lmax", ctypes.c_int64),
+                ("level_n", ctypes.c_int32 * MAX_GRAPH_LEVELS),
+                ("level_nnz", ctypes.c_int64 * MAX_GRAPH_LEVELS),
+                ("level_iterations", ctypes.c_int32 * MAX_GRAPH_LEVELS),
+                ("level_hem_rounds", ctypes.c_int32 * MAX_GRAPH_LEVELS),
+                ("coarsen_ms", ctypes.c_double), ("contract_ms", ctypes.c_double),
+                ("initial_ms", ctypes.c_double), ("uncoarsen_ms", ctypes.c_double),
+                ("refine_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("refine_arcs", ctypes.c_int64),
+                ("kernel_launches", ctypes.c_int64 * 4), ("kernel_ms", ctypes.c_double * 4),
+                ("kernel_bytes", ctypes.c_double * 4)]
+
+
+_P = ctypes.c_void_p
+_I32, _I64, _U32, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+_SIGS = {
+    "pm_version": (ctypes.c_char_p, []),
+    "pm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pm_release": (None, []),
+    "pm_comm_cost": (ctypes.c_int, [_P, _P, _P, _P, _U32, _P]),
+    "pm_block_weights": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "pm_lp_round": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
+    "pm_rebalance": (ctypes.c_int, [_P, _P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _P]),
+    "pm_refine": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P]),
+    "pm_hem": (ctypes.c_int, [_P, _I64, _U64, _I32, _P, _P, _P]),
+    "pm_contract": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pm_initial_partition": (ctypes.c_int, [_P, _P, _P, _P]),
+    "pm_map": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P]),
+}
+_lib = None
+
+
+def lib():
+    """Load libpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2510_12196_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().pm_strerror(code).decode()
+    except Exception:  # library not loadable: still produce a message
+        return "error"
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise PmError(rc, where)
+    return rc
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def hierarchy(a, d) -> PmHierarchy:
+    a = list(a)
+    d = list(d)
+    if not (1 <= len(a) <= MAX_LEVELS) or len(a) != len(d):
+        raise ValueError("hierarchy needs 1..8 levels and one distance per level")
+    h = PmHierarchy()
+    h.levels = len(a)
+    for i, (x, y) in enumerate(zip(a, d)):
+        h.a[i] = int(x)
+        h.d[i] = int(y)
+    return h
+
+
+@dataclass
+class DeviceGraph:
+    """CSR graph in device memory (torch tensors)."""
+    xadj: object      # int64[n+1]
+    adjncy: object    # int32[nnz]
+    adjwgt: object    # int32[nnz]
+    vwgt: object      # int32[n]
+
+    @property
+    def n(self) -> int:
+        return int(self.vwgt.shape[0])
+
+    @property
+    def nnz(self) -> int:
+        return int(self.adjncy.shape[0])
+
+    @classmethod
+    def from_host(cls, g, device="cuda") -> "DeviceGraph":
+        torch = _torch()
+
+        def t(x, dt):
+            return torch.from_numpy(np.ascontiguousarray(np.asarray(x, dtype=dt))).to(device)
+        return cls(t(g.xadj, np.int64), t(g.adjncy, np.int32), t(g.adjwgt, np.int32),
+                   t(g.vwgt, np.int32))
+
+    def struct(self) -> PmGraph:
+        for x in (self.xadj, self.adjncy, self.adjwgt, self.vwgt):
+            if not x.is_cuda or not x.is_contiguous():
+                raise ValueError("graph arrays must be contiguous device tensors")
+        s = PmGraph()
+        s.n = self.n
+        s.nnz = self.nnz
+        s.xadj = self.xadj.data_ptr()
+        s.adjncy = self.adjncy.data_ptr() if self.nnz else None
+        s.adjwgt = self.adjwgt.data_ptr() if self.nnz else None
+        s.vwgt = self.vwgt.data_ptr() if self.n else None
+        return s
+
+
+def _dev(t, dtype_name, n=None):
+    if not t.is_cuda or not t.is_contiguous() or str(t.dtype) != f"torch.{dtype_name}":
+        raise ValueError(f"expected a contiguous device tensor of {dtype_name}")
+    if n is not None and t.shape[0] != n:
+        raise ValueError("array length does not match the graph")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def pm_version() -> str:
+    return lib().pm_version().decode()
+
+
+def pm_release() -> None:
+    lib().pm_release()
+
+
+def pm_comm_cost(g: DeviceGraph, a, d, part, validate: bool = False) -> int:
+    """J = sum over all arcs of w * D(part[u], part[v])."""
+    out = ctypes.c_int64(0)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_comm_cost(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
+                              ctypes.byref(out), PM_FLAG_VALIDATE if validate else 0, _stream()),
+           "pm_comm_cost")
+    return int(out.value)
+
+
+def pm_block_weights(g: DeviceGraph, a, d, part):
+    torch = _torch()
+    k = int(np.prod(a))
+    w = torch.empty(k, dtype=torch.int64, device=part.device)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_block_weights(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
+                                  _dev(w, "int64"), _stream()), "pm_block_weights")
+    return w
+
+
+def pm_lp_round(g: DeviceGraph, a, d, part, lock):
+    """One label-propagation round; part and lock are updated in place.
+    Returns (target, gain, moved)."""
+    torch = _torch()
+    target = torch.empty(g.n, dtype=torch.int32, device=part.device)
+    gain = torch.empty(g.n, dtype=torch.int64, device=part.device)
+    moved = torch.empty(g.n, dtype=torch.uint8, device=part.device)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_lp_round(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
+                             _dev(lock, "uint8", g.n), _dev(target, "int32"), _dev(gain, "int64"),
+                             _dev(moved, "uint8"), _stream()), "pm_lp_round")
+    return target, gain, moved
+
+
+def pm_rebalance(g: DeviceGraph, a, d, part, strong: bool, lmax: int, sigma: int, seed: int,
+                 level: int, it: int):
+    """One rebalancing round; part is updated in place.  Returns moved flags."""
+    torch = _torch()
+    moved = torch.empty(g.n, dtype=torch.uint8, device=part.device)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_rebalance(ctypes.byref(gs), ctypes.byref(hs), int(bool(strong)), int(lmax),
+                              int(sigma), seed & (2**64 - 1), int(level), int(it),
+                              _dev(part, "int32", g.n), _dev(moved, "uint8"), _stream()),
+           "pm_rebalance")
+    return moved
+
+
+def pm_refine(g: DeviceGraph, a, d, eps: float, seed: int, part, level: int = 0):
+    """Refinement (Algorithm 6) in place.  Returns (status, PmRefineStats)."""
+    st = PmRefineStats()
+    gs, hs = g.struct(), hierarchy(a, d)
+    rc = _check(lib().pm_refine(ctypes.byref(gs), ctypes.byref(hs), float(eps),
+                                seed & (2**64 - 1), int(level), _dev(part, "int32", g.n),
+                                ctypes.byref(st), _stream()), "pm_refine")
+    return rc, st
+
+
+def pm_hem(g: DeviceGraph, lmax: int, seed: int, level: int = 0):
+    """Heavy-edge matching.  Returns (match, rounds)."""
+    torch = _torch()
+    match = torch.empty(g.n, dtype=torch.int32, device=g.vwgt.device)
+    rounds = ctypes.c_int32(0)
+    gs = g.struct()
+    _check(lib().pm_hem(ctypes.byref(gs), int(lmax), seed & (2**64 - 1), int(level),
+                        _dev(match, "int32"), ctypes.byref(rounds), _stream()), "pm_hem")
+    return match, int(rounds.value)
+
+
+def pm_contract(g: DeviceGraph, match):
+    """Coarse numbering + contraction.  Returns (cmap, coarse DeviceGraph)."""
+    torch = _torch()
+    dev = g.vwgt.device
+    n, nnz = g.n, g.nnz
+    cmap = torch.empty(n, dtype=torch.int32, device=dev)
+    cx = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    ca = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    cw = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    nc = ctypes.c_int32(0)
+    cnnz = ctypes.c_int64(0)
+    gs = g.struct()
+    _check(lib().pm_contract(ctypes.byref(gs), _dev(match, "int32", n), _dev(cmap, "int32"),
+                             _dev(cx, "int64"), _dev(ca, "int32"), _dev(cw, "int32"),
+                             _dev(cv, "int32"), ctypes.byref(nc), ctypes.byref(cnnz), _stream()),
+           "pm_contract")
+    k, m = int(nc.value), int(cnnz.value)
+    return cmap, DeviceGraph(cx[: k + 1].clone(), ca[:m].clone(), cw[:m].clone(), cv[:k].clone())
+
+
+def pm_initial_partition(g: DeviceGraph, a, d):
+    torch = _torch()
+    part = torch.empty(g.n, dtype=torch.int32, device=g.vwgt.device)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_initial_partition(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32"),
+                                      _stream()), "pm_initial_partition")
+    return part
+
+
+def pm_map(g: DeviceGraph, a, d, eps: float, seed: int, part=None, validate: bool = False,
+           kernel_times: bool = False):
+    """Full multilevel mapping.  Returns (status, part, PmMapStats)."""
+    torch = _torch()
+    if part is None:
+        part = torch.empty(g.n, dtype=torch.int32, device=g.vwgt.device)
+    st = PmMapStats()
+    gs, hs = g.struct(), hierarchy(a, d)
+    rc = _check(lib().pm_map(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
+                             _dev(part, "int32", g.n), ctypes.byref(st),
+                             (PM_FLAG_VALIDATE if validate else 0)
+                             | (PM_FLAG_KERNEL_TIMES if kernel_times else 0), _stream()), "pm_map")
+    return rc, part, st
+
+
+__all__ = ["DeviceGraph", "PmError", "PmGraph", "PmHierarchy", "PmMapStats", "PmRefineStats",
+           "hierarchy", "lib", "pm_version", "pm_release", "pm_comm_cost", "pm_block_weights",
+           "pm_lp_round", "pm_rebalance", "pm_refine", "pm_hem", "pm_contract",
+           "pm_initial_partition", "pm_map"]

@@ -1,0 +1,384 @@
+// coarsen.hip -- heavy-edge matching, coarse numbering, contraction and
+// projection for gfx950 (Section 3.2: Matching, Contraction, Uncontraction).
+#include <hip/hip_ext.h>
+
+#include "device_util.h"
+#include "kernels.h"
+
+namespace pm {
+
+static inline unsigned grid_for(int64_t n, int per = kThreads) {
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ===========================================================================
+// Heavy-edge matching.  Edge rating w^2 / (c(u) c(v)); within v's row c(v)
+// cancels, so candidate a beats b iff w_a^2 c_b > w_b^2 c_a (exact, 128-bit).
+// Equal ratings: smaller hash of the unordered pair, then smaller lower
+// endpoint, then smaller upper endpoint.  This is a total order on edges, so
+// the best remaining edge is always mutually preferred.
+// ===========================================================================
+struct Cand {
+  int32_t u;   // -1: none
+  int32_t w;
+  int32_t cu;
+  uint64_t h;
+};
+
+__device__ __forceinline__ bool cand_better(const Cand &a, const Cand &b, int32_t v) {
+  if (b.u < 0) return a.u >= 0;
+  if (a.u < 0) return false;
+  const unsigned __int128 l = (unsigned __int128)((uint64_t)a.w * (uint64_t)a.w) * (uint64_t)b.cu;
+  const unsigned __int128 r = (unsigned __int128)((uint64_t)b.w * (uint64_t)b.w) * (uint64_t)a.cu;
+  if (l != r) return l > r;
+  if (a.h != b.h) return a.h < b.h;
+  const int32_t alo = a.u < v ? a.u : v, blo = b.u < v ? b.u : v;
+  if (alo != blo) return alo < blo;
+  const int32_t ahi = a.u < v ? v : a.u, bhi = b.u < v ? v : b.u;
+  return ahi < bhi;
+}
+
+template <int G>
+__device__ __forceinline__ Cand cand_xor(const Cand &c, int m) {
+  Cand o;
+  o.u = __shfl_xor(c.u, m, G);
+  o.w = __shfl_xor(c.w, m, G);
+  o.cu = __shfl_xor(c.cu, m, G);
+  o.h = (uint64_t)gxor64<G>((int64_t)c.h, m);
+  return o;
+}
+
+template <int G>
+__device__ __forceinline__ void cand_reduce(Cand &c, int32_t v) {
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) {
+    const Cand o = cand_xor<G>(c, m);
+    if (cand_better(o, c, v)) c = o;
+  }
+}
+
+struct HemArgs {
+  DGraph g;
+  Classes cl;
+  int64_t lmax;
+  uint64_t hseed;
+  const int32_t *match;
+  int32_t *pref;
+};
+
+__device__ __forceinline__ Cand hem_arc(const HemArgs &A, int32_t v, int32_t cv, int64_t e) {
+  Cand c{-1, 0, 1, 0};
+  const int32_t u = A.g.adj[e];
+  if (A.match[u] >= 0) return c;
+  const int32_t cu = A.g.c[u];
+  if ((int64_t)cu + cv > A.lmax) return c;
+  const uint32_t lo = (uint32_t)(u < v ? u : v), hi = (uint32_t)(u < v ? v : u);
+  c.u = u;
+  c.w = A.g.w[e];
+  c.cu = cu;
+  c.h = mix_hash(A.hseed, ((uint64_t)lo << 32) | hi);
+  return c;
+}
+
+template <int G>
+__device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return;
+  const int lane = threadIdx.x % G;
+  if (A.match[v] >= 0) {
+    if (lane == 0) A.pref[v] = -1;
+    return;
+  }
+  const int64_t e = A.g.xadj[v] + lane;
+  Cand c{-1, 0, 1, 0};
+  if (e < A.g.xadj[v + 1]) c = hem_arc(A, v, A.g.c[v], e);
+  cand_reduce<G>(c, v);
+  if (lane == 0) A.pref[v] = c.u;
+}
+
+struct CandScratch {
+  Cand c[kThreads / 64];
+};
+
+__global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
+  __shared__ CandScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
+        A.pref[A.cl.list[A.cl.off[CLS_ISO] + idx]] = -1;
+      break;
+    }
+    case CLS_G8: hem_group<8>(A, cls, local); break;
+    case CLS_G16: hem_group<16>(A, cls, local); break;
+    case CLS_G32: hem_group<32>(A, cls, local); break;
+    case CLS_G64: hem_group<64>(A, cls, local); break;
+    default: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      if (A.match[v] >= 0) {
+        if (threadIdx.x == 0) A.pref[v] = -1;
+        break;
+      }
+      const int32_t cv = A.g.c[v];
+      Cand best{-1, 0, 1, 0};
+      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads) {
+        const Cand c = hem_arc(A, v, cv, e);
+        if (cand_better(c, best, v)) best = c;
+      }
+      cand_reduce<64>(best, v);
+      const int wave = threadIdx.x >> 6;
+      if ((threadIdx.x & 63) == 0) sc.c[wave] = best;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        Cand b = sc.c[0];
+        for (int i = 1; i < kThreads / 64; ++i)
+          if (cand_better(sc.c[i], b, v)) b = sc.c[i];
+        A.pref[v] = b.u;
+      }
+      break;
+    }
+  }
+}
+
+void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
+                const int32_t *match, int32_t *pref, hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  HemArgs A{g, cl, lmax, hseed, match, pref};
+  if (tl_timer) {
+    hipEvent_t a, b;
+    tl_timer->pair(KT_HEM, a, b);
+    hipExtLaunchKernelGGL(k_hem_prefer, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+  } else {
+    hipLaunchKernelGGL(k_hem_prefer, dim3(nwg), dim3(kThreads), 0, s, A);
+  }
+  PM_LAUNCH_CHECK();
+}
+
+// v and pref[v] are matched iff they prefer each other.
+__global__ void k_hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool hit = false;
+  if (v < n && match[v] < 0) {
+    const int32_t u = pref[v];
+    if (u >= 0 && pref[u] == (int32_t)v) {
+      match[v] = u;
+      hit = true;
+    }
+  }
+  const unsigned long long b = __ballot(hit);
+  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&st->count, (int32_t)__popcll(b));
+}
+
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_hem_commit, dim3(grid_for(n)), dim3(kThreads), 0, s, n, pref, match, st);
+  PM_LAUNCH_CHECK();
+}
+
+// unmatched vertices without neighbours (they share the empty neighbourhood)
+__global__ void k_iso_flags(DGraph g, const int32_t *match, uint8_t *flag) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < g.n) flag[v] = (match[v] < 0 && g.xadj[v + 1] == g.xadj[v]) ? 1 : 0;
+}
+void hem_isolated_flags(const DGraph &g, const int32_t *match, uint8_t *flag, hipStream_t s) {
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(k_iso_flags, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, match, flag);
+  PM_LAUNCH_CHECK();
+}
+
+// pairs (iso[2j], iso[2j+1]) when their weight fits
+__global__ void k_pair_iso(const int32_t *iso, int32_t npairs, const int32_t *vwgt,
+                           int64_t lmax, int32_t *match) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= npairs) return;
+  const int32_t a = iso[2 * j], b = iso[2 * j + 1];
+  if ((int64_t)vwgt[a] + vwgt[b] <= lmax) {
+    match[a] = b;
+    match[b] = a;
+  }
+}
+void hem_pair_isolated(const int32_t *iso, int32_t niso, const int32_t *vwgt, int64_t lmax,
+                       int32_t *match, hipStream_t s) {
+  const int32_t np = niso / 2;
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_pair_iso, dim3(grid_for(np)), dim3(kThreads), 0, s, iso, np, vwgt, lmax,
+                     match);
+  PM_LAUNCH_CHECK();
+}
+
+// unmatched -> self; leader flag (the smaller member of a pair, or a single)
+__global__ void k_hem_finish(int32_t n, int32_t *match, int32_t *leader) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  int32_t m = match[v];
+  if (m < 0) {
+    m = (int32_t)v;
+    match[v] = m;
+  }
+  leader[v] = m >= v ? 1 : 0;
+}
+void hem_finish(int32_t n, int32_t *match, int32_t *leader, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_hem_finish, dim3(grid_for(n)), dim3(kThreads), 0, s, n, match, leader);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Coarse numbering: coarse id = rank of the pair's smaller member.
+// `rank` holds, for every leader, the number of leaders before it.
+// ===========================================================================
+__global__ void k_coarse_ids(int32_t n, const int32_t *match, const int32_t *rank,
+                             int32_t *cmap) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t m = match[v];
+  cmap[v] = rank[m < v ? m : (int32_t)v];
+}
+void coarse_ids(int32_t n, const int32_t *match, const int32_t *rank, int32_t *cmap,
+                hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_coarse_ids, dim3(grid_for(n)), dim3(kThreads), 0, s, n, match, rank, cmap);
+  PM_LAUNCH_CHECK();
+}
+
+__global__ void k_coarse_vwgt(int32_t n, const int32_t *match, const int32_t *cmap,
+                              const int32_t *vwgt, int32_t *cvwgt) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t m = match[v];
+  if (m < v) return;
+  cvwgt[cmap[v]] = vwgt[v] + (m != v ? vwgt[m] : 0);
+}
+void coarse_vwgt(int32_t n, const int32_t *match, const int32_t *cmap, const int32_t *vwgt,
+                 int32_t *cvwgt, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_coarse_vwgt, dim3(grid_for(n)), dim3(kThreads), 0, s, n, match, cmap,
+                     vwgt, cvwgt);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Contraction: every arc e = (v, u, w) becomes the key (M(v) << B | M(u)),
+// arcs inside one coarse vertex get the all-ones key and sort to the end.
+// After a radix sort of the keys, runs of equal keys are fused with their
+// weights summed; rows come out in ascending neighbour order.
+// ===========================================================================
+struct KeyArgs {
+  DGraph g;
+  Classes cl;
+  const int32_t *cmap;
+  int bits;
+  uint64_t *key;
+  int32_t *val;
+  Status *st;
+};
+
+__device__ __forceinline__ int32_t key_arc(const KeyArgs &A, uint64_t cv, int64_t e) {
+  const uint64_t cu = (uint64_t)A.cmap[A.g.adj[e]];
+  A.val[e] = A.g.w[e];
+  if (cu == cv) {
+    A.key[e] = (A.bits >= 32) ? ~0ull : ((1ull << (2 * A.bits)) - 1ull);
+    return 1;
+  }
+  A.key[e] = (cv << A.bits) | cu;
+  return 0;
+}
+
+template <int G>
+__device__ __forceinline__ int32_t key_group(const KeyArgs &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return 0;
+  const int lane = threadIdx.x % G;
+  const int64_t e = A.g.xadj[v] + lane;
+  if (e >= A.g.xadj[v + 1]) return 0;
+  return key_arc(A, (uint64_t)A.cmap[v], e);
+}
+
+__global__ __launch_bounds__(kThreads) void k_contract_keys(KeyArgs A) {
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  int32_t self = 0;
+  switch (cls) {
+    case CLS_ISO: break;
+    case CLS_G8: self = key_group<8>(A, cls, local); break;
+    case CLS_G16: self = key_group<16>(A, cls, local); break;
+    case CLS_G32: self = key_group<32>(A, cls, local); break;
+    case CLS_G64: self = key_group<64>(A, cls, local); break;
+    default: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const uint64_t cv = (uint64_t)A.cmap[v];
+      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+        self += key_arc(A, cv, e);
+      break;
+    }
+  }
+  // per-lane counts may exceed one in the big class: reduce through a wave sum
+  int32_t x = self;
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
+  if ((threadIdx.x & 63) == 0 && x) atomicAdd(&A.st->count, x);
+}
+
+void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int bits,
+                   uint64_t *key, int32_t *val, Status *st, hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  KeyArgs A{g, cl, cmap, bits, key, val, st};
+  hipLaunchKernelGGL(k_contract_keys, dim3(nwg), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+}
+
+__global__ void k_contract_heads(int64_t m, const uint64_t *key, int32_t *head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) head[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_contract_heads, dim3(grid_for(m)), dim3(kThreads), 0, s, m, key, head);
+  PM_LAUNCH_CHECK();
+}
+
+// one thread per run head: fuse the run (at most 4 arcs: two members per side)
+__global__ void k_contract_emit(int64_t m, const uint64_t *key, const int32_t *val,
+                                const int32_t *head, const int32_t *pos, int bits,
+                                int32_t *cadj, int32_t *cw, int32_t *rowcnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m || !head[i]) return;
+  const uint64_t k = key[i];
+  int64_t sum = 0;
+  for (int64_t j = i; j < m && key[j] == k; ++j) sum += val[j];
+  const int32_t o = pos[i];
+  cadj[o] = (int32_t)(k & ((1ull << bits) - 1ull));
+  cw[o] = (int32_t)sum;
+  atomicAdd(&rowcnt[k >> bits], 1);
+}
+
+void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,
+                   const int32_t *pos, int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt,
+                   hipStream_t s) {
+  if (m <= 0) return;
+  hipLaunchKernelGGL(k_contract_emit, dim3(grid_for(m)), dim3(kThreads), 0, s, m, key, val, head,
+                     pos, bits, cadj, cw, rowcnt);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Projection (uncontraction): Pi_fine(v) = Pi_coarse(M(v)).
+// ===========================================================================
+__global__ void k_project(int32_t n, const int32_t *cmap, const int32_t *coarse,
+                          int32_t *fine) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) fine[v] = coarse[cmap[v]];
+}
+void project(int32_t n, const int32_t *cmap, const int32_t *coarse, int32_t *fine,
+             hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_project, dim3(grid_for(n)), dim3(kThreads), 0, s, n, cmap, coarse, fine);
+  PM_LAUNCH_CHECK();
+}
+
+}  // namespace pm

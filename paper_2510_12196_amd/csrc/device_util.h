@@ -1,0 +1,142 @@
+// device_util.h -- wave/group/workgroup helpers for gfx950 (wave64).
+#pragma once
+
+#include "pm_internal.h"
+
+namespace pm {
+
+// ---- lane groups of G consecutive lanes inside a wave64 -------------------
+template <int G>
+__device__ __forceinline__ int32_t gshfl(int32_t x, int j) {
+  return __shfl(x, j, G);
+}
+template <int G>
+__device__ __forceinline__ int64_t gshfl64(int64_t x, int j) {
+  int32_t lo = __shfl((int32_t)(uint32_t)(uint64_t)x, j, G);
+  int32_t hi = __shfl((int32_t)((uint64_t)x >> 32), j, G);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int G>
+__device__ __forceinline__ int64_t gxor64(int64_t x, int m) {
+  int32_t lo = __shfl_xor((int32_t)(uint32_t)(uint64_t)x, m, G);
+  int32_t hi = __shfl_xor((int32_t)((uint64_t)x >> 32), m, G);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int G>
+__device__ __forceinline__ int64_t gsum64(int64_t x) {
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) x += gxor64<G>(x, m);
+  return x;
+}
+template <int G>
+__device__ __forceinline__ int32_t gor(int32_t x) {
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) x |= __shfl_xor(x, m, G);
+  return x;
+}
+// (value desc, key asc) argmax over the group; every lane gets the result.
+template <int G>
+__device__ __forceinline__ void gargmax(int64_t &val, uint32_t &key) {
+#pragma unroll
+  for (int m = G / 2; m > 0; m >>= 1) {
+    int64_t ov = gxor64<G>(val, m);
+    uint32_t ok = (uint32_t)__shfl_xor((int32_t)key, m, G);
+    if (ov > val || (ov == val && ok < key)) {
+      val = ov;
+      key = ok;
+    }
+  }
+}
+
+// ---- whole workgroup (kThreads = 256, four waves) --------------------------
+// LDS scratch for the block-level reductions below: 4 waves x 2 words.
+struct BlockScratch {
+  int64_t v[kThreads / 64];
+  uint32_t k[kThreads / 64];
+  uint32_t u[kThreads / 64];
+};
+
+__device__ __forceinline__ int64_t block_sum64(int64_t x, BlockScratch &sc) {
+  x = gsum64<64>(x);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sc.v[wave] = x;
+  __syncthreads();
+  int64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kThreads / 64; ++i) t += sc.v[i];
+  return t;
+}
+
+__device__ __forceinline__ void block_argmax(int64_t &val, uint32_t &key, BlockScratch &sc) {
+  gargmax<64>(val, key);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+    sc.v[wave] = val;
+    sc.k[wave] = key;
+  }
+  __syncthreads();
+  val = sc.v[0];
+  key = sc.k[0];
+#pragma unroll
+  for (int i = 1; i < kThreads / 64; ++i)
+    if (sc.v[i] > val || (sc.v[i] == val && sc.k[i] < key)) {
+      val = sc.v[i];
+      key = sc.k[i];
+    }
+}
+
+// exclusive scan of one uint32 per thread over the workgroup
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, BlockScratch &sc) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = (uint32_t)__shfl_up((int32_t)incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();
+  if (lane == 63) sc.u[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int i = 0; i < wave; ++i) off += sc.u[i];
+  return off + incl - x;
+}
+
+// In-place inclusive scan of a[0..m) held in LDS.
+__device__ __forceinline__ void block_scan_lds(uint32_t *a, int m, BlockScratch &sc) {
+  const int per = (m + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < m ? lo + per : m;
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) {
+    s += a[i];
+    a[i] = s;
+  }
+  uint32_t off = block_excl_scan(s, sc);
+  for (int i = lo; i < hi; ++i) a[i] += off;
+  __syncthreads();
+}
+
+// ---- classed launches --------------------------------------------------------
+__device__ __forceinline__ int find_class(const Classes &cl, int b) {
+  int c = 0;
+  while (c < NCLS - 1 && b >= cl.wg[c + 1]) ++c;
+  return c;
+}
+
+// Vertex handled by this lane group (G lanes per vertex) in class cls.
+template <int G>
+__device__ __forceinline__ bool group_vertex(const Classes &cl, int cls, int local, int32_t &v) {
+  const int idx = local * (kThreads / G) + (int)threadIdx.x / G;
+  const int cnt = cl.off[cls + 1] - cl.off[cls];
+  if (idx >= cnt) return false;
+  v = cl.list[cl.off[cls] + idx];
+  return true;
+}
+
+// Sum over the arcs of one vertex weighted by the lane group convention:
+// inside a G-group lane j owns arc xadj[v]+j (deg <= G by construction).
+
+}  // namespace pm

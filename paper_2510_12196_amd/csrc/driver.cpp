@@ -1,0 +1,760 @@
+// driver.cpp -- host orchestration and the C ABI of the process-mapping library.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "host_ip.h"
+#include "kernels.h"
+#include "prim.h"
+
+namespace pm {
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+Hier make_hier(const pm_hierarchy *ph) {
+  if (!ph) throw Error(PM_EINVAL, "hierarchy is NULL");
+  if (ph->levels < 1 || ph->levels > PM_MAX_LEVELS)
+    throw Error(PM_EINVAL, "hierarchy levels must be in [1,8]");
+  Hier h{};
+  h.levels = ph->levels;
+  h.P[0] = 1;
+  h.shift[0] = 0;
+  h.pow2 = 1;
+  for (int i = 0; i < h.levels; ++i) {
+    const int32_t a = ph->a[i], d = ph->d[i];
+    if (a < 1) throw Error(PM_EINVAL, "a_i must be >= 1");
+    if (d < 0 || d >= (1 << 30)) throw Error(PM_EINVAL, "d_i must be in [0, 2^30)");
+    int width = 0;
+    while ((1 << width) < a) ++width;
+    h.a[i] = a;
+    h.d[i] = d;
+    h.shift[i + 1] = h.shift[i] + width;
+    h.P[i + 1] = h.P[i] * a;
+    if (h.P[i + 1] > INT32_MAX) throw Error(PM_EOVERFLOW, "k exceeds 2^31");
+    if (a & (a - 1)) h.pow2 = 0;
+  }
+  h.bits = h.shift[h.levels];
+  if (h.bits > kMaxCodeBits)
+    throw Error(PM_EOVERFLOW, "hierarchy needs more than 13 code bits");
+  h.k = h.P[h.levels];
+  return h;
+}
+
+namespace {
+
+int64_t lmax_of(int64_t total, int64_t k, double eps) {
+  if (!(eps >= 0.0) || eps > 1e6) throw Error(PM_EINVAL, "eps must be >= 0");
+  const int64_t ppm = (int64_t)std::llround(eps * 1e6);
+  const int64_t num = (1000000 + ppm) * total;
+  const int64_t den = 1000000 * k;
+  return (num + den - 1) / den;
+}
+
+int64_t sigma_of(int64_t lmax, int64_t total, int64_t k) {
+  const int64_t avg = (total + k - 1) / k;
+  return lmax - 100 > avg ? lmax - 100 : avg;
+}
+
+DGraph view(const pm_graph *g) {
+  if (!g) throw Error(PM_EINVAL, "graph is NULL");
+  if (g->n < 0 || g->nnz < 0) throw Error(PM_EINVAL, "negative graph size");
+  if (g->nnz > INT32_MAX) throw Error(PM_EOVERFLOW, "nnz exceeds 2^31 - 1");
+  if (!g->xadj || (g->n > 0 && !g->vwgt) || (g->nnz > 0 && (!g->adjncy || !g->adjwgt)))
+    throw Error(PM_EINVAL, "graph array is NULL");
+  DGraph d{g->n, g->nnz, g->xadj, g->adjncy, g->adjwgt, g->vwgt};
+  return d;
+}
+
+// Device-side status block + host mirror for one call.
+struct Ctx {
+  Arena &ar;
+  hipStream_t s;
+  Status *dev;
+  Status *host;
+  explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
+    dev = ar.alloc_n<Status>(1);
+    host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
+    PM_HIP(hipMemsetAsync(dev, 0, sizeof(Status), s));
+  }
+  void pull() {
+    PM_HIP(hipMemcpyAsync(host, dev, sizeof(Status), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+  }
+};
+
+}  // namespace
+
+// Structure and overflow validation kernels live in validate.hip.
+void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Refinement (Algorithm 6)
+// ---------------------------------------------------------------------------
+struct RefineResult {
+  int32_t status;
+  pm_refine_stats st;
+};
+
+static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, const Hier &h,
+                                 int64_t lmax, int64_t sigma, int64_t total, uint64_t seed,
+                                 int32_t level, int32_t *best) {
+  Arena &ar = cx.ar;
+  hipStream_t s = cx.s;
+  const size_t mark = ar.mark();
+  const int64_t n = g.n;
+  const int32_t ncodes = 1 << h.bits;
+  int32_t *cur = ar.alloc_n<int32_t>(n);
+  int32_t *target = ar.alloc_n<int32_t>(n);
+  int64_t *gain = ar.alloc_n<int64_t>(n);
+  uint8_t *moved = ar.alloc_n<uint8_t>(n);
+  uint8_t *lock = ar.alloc_n<uint8_t>(n);
+  int64_t *w = ar.alloc_n<int64_t>(ncodes);
+  RebalanceBuffers rb;
+  rb.key = ar.alloc_n<int32_t>(n);
+  rb.dest = ar.alloc_n<int32_t>(n);
+  rb.flag = ar.alloc_n<uint8_t>(n);
+  rb.list = ar.alloc_n<int32_t>(n);
+  rb.list2 = ar.alloc_n<int32_t>(n);
+  rb.skey = ar.alloc_n<uint32_t>(n);
+  rb.skey2 = ar.alloc_n<uint32_t>(n);
+  rb.pre = ar.alloc_n<int64_t>(n);
+  rb.seg = ar.alloc_n<int32_t>(ncodes);
+  rb.elig = ar.alloc_n<int32_t>(ncodes);
+  rb.acc = ar.alloc_n<int64_t>(ncodes);
+  rb.rstart = ar.alloc_n<int64_t>(ncodes);
+  rb.rblock = ar.alloc_n<int32_t>(ncodes);
+
+  hipEvent_t ev0, ev1;
+  PM_HIP(hipEventCreate(&ev0));
+  PM_HIP(hipEventCreate(&ev1));
+  PM_HIP(hipEventRecord(ev0, s));
+
+  if (n > 0) PM_HIP(hipMemcpyAsync(cur, best, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+  fill_u8(lock, 0, n, s);
+  block_weights(g, h, cur, w, s);
+  comm_cost(g, cl, h, cur, cx.dev, s);
+  max_block(h, w, cx.dev, s);
+  cx.pull();
+  int64_t j_cur = cx.host->j, imb_cur = cx.host->maxw;
+  if (n == 0) imb_cur = 0;
+  int64_t j_best = j_cur, imb_best = imb_cur;
+  bool feas_best = imb_best <= lmax;
+
+  RefineResult R{};
+  R.st.j_initial = j_cur;
+  R.st.maxw_initial = imb_cur;
+  const uint64_t reb_seed = mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level);
+
+  int32_t i = 0, iw = 0, bodies = 0;
+  while (i < 12 && bodies < 4096) {
+    ++i;
+    ++bodies;
+    PM_HIP(hipMemsetAsync(&cx.dev->dj, 0, sizeof(int64_t), s));
+    if (imb_cur <= lmax) {
+      lp_phase1(g, cl, h, cur, lock, target, gain, s);
+      lp_phase2(g, cl, h, cur, target, gain, moved, s);
+      apply_moves(g, cl, h, cur, target, moved, lock, w, cx.dev, s);
+      iw = 0;
+      ++R.st.lp_iterations;
+    } else {
+      const bool strong = iw >= 2;
+      const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
+      rebalance_select(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
+                       cx.dev, cx.host, s);
+      apply_moves(g, cl, h, cur, target, moved, nullptr, w, cx.dev, s);
+      if (strong) {
+        iw = 0;
+        ++R.st.strong_iterations;
+      } else {
+        ++iw;
+        ++R.st.weak_iterations;
+      }
+    }
+    max_block(h, w, cx.dev, s);
+    cx.pull();
+    j_cur += cx.host->dj;
+    imb_cur = cx.host->maxw;
+    if (imb_cur <= lmax) {
+      const bool improve = !feas_best || j_cur < j_best;
+      const bool reset = !feas_best || 1000 * j_cur < 999 * j_best;
+      if (improve) {
+        PM_HIP(hipMemcpyAsync(best, cur, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        j_best = j_cur;
+        imb_best = imb_cur;
+        feas_best = true;
+      }
+      if (reset) i = 0;
+    } else if (imb_cur < imb_best) {
+      PM_HIP(hipMemcpyAsync(best, cur, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+      j_best = j_cur;
+      imb_best = imb_cur;
+      i = 0;
+    }
+  }
+  PM_HIP(hipEventRecord(ev1, s));
+  PM_HIP(hipEventSynchronize(ev1));
+  float ms = 0.f;
+  PM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+
+  R.st.iterations = bodies;
+  R.st.j_final = j_best;
+  R.st.maxw_final = imb_best;
+  R.st.feasible = feas_best ? 1 : 0;
+  R.st.refine_ms = ms;
+  R.st.arcs_processed = (int64_t)bodies * g.nnz;
+  R.status = feas_best ? PM_OK : PM_WARN_IMBALANCED;
+  ar.rewind(mark);
+  return R;
+}
+
+// ---------------------------------------------------------------------------
+// Coarsening: one level of matching + contraction
+// ---------------------------------------------------------------------------
+struct Level {
+  DGraph g;
+  int32_t *list = nullptr;
+  Classes cl{};
+  int32_t *cmap = nullptr;  // to the next coarser level
+  int32_t hem_rounds = 0;
+};
+
+static int32_t bitlen(uint64_t x) {
+  int32_t b = 0;
+  while (x) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+// HEM on level L; returns rounds, fills match (device, n).
+static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int32_t level,
+                       int32_t *match, int32_t *pref) {
+  const DGraph &g = L.g;
+  hipStream_t s = cx.s;
+  fill_i32(match, -1, g.n, s);
+  const uint64_t hseed = mix_hash(seed ^ kTagMatch, (uint64_t)(int64_t)level);
+  int32_t rounds = 0;
+  int64_t matched = 0;
+  while (rounds < 64) {
+    ++rounds;
+    PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), s));
+    hem_prefer(g, L.cl, lmax, hseed, match, pref, s);
+    hem_commit(g.n, pref, match, cx.dev, s);
+    cx.pull();
+    const int32_t added = cx.host->count;
+    matched += added;
+    if (added == 0) break;
+  }
+  if (4 * matched <= 3 * (int64_t)g.n) {
+    const size_t m = cx.ar.mark();
+    uint8_t *flag = cx.ar.alloc_n<uint8_t>(g.n);
+    int32_t *iso = cx.ar.alloc_n<int32_t>(g.n);
+    hem_isolated_flags(g, match, flag, s);
+    select_indices(cx.ar, flag, iso, &cx.dev->count, g.n, s);
+    cx.pull();
+    hem_pair_isolated(iso, cx.host->count, g.c, lmax, match, s);
+    cx.ar.rewind(m);
+  }
+  return rounds;
+}
+
+// Coarse numbering + contraction into pre-allocated coarse arrays.
+static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap, int32_t nc,
+                         int64_t *cxadj, int32_t *cadj, int32_t *cw, int32_t *cvwgt,
+                         int64_t *nnz_out) {
+  const DGraph &g = L.g;
+  hipStream_t s = cx.s;
+  Arena &ar = cx.ar;
+  (void)match;
+  coarse_vwgt(g.n, match, cmap, g.c, cvwgt, s);
+  const size_t m = ar.mark();
+  const int64_t nnz = g.nnz;
+  const int bits = bitlen((uint64_t)(nc > 1 ? nc - 1 : 1));
+  uint64_t *key = ar.alloc_n<uint64_t>(nnz);
+  uint64_t *key2 = ar.alloc_n<uint64_t>(nnz);
+  int32_t *val = ar.alloc_n<int32_t>(nnz);
+  int32_t *val2 = ar.alloc_n<int32_t>(nnz);
+  PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), s));
+  contract_keys(g, L.cl, cmap, bits, key, val, cx.dev, s);
+  sort_pairs(ar, key, key2, val, val2, nnz, 2 * bits, s);
+  cx.pull();
+  const int64_t mvalid = nnz - cx.host->count;
+  int32_t *head = ar.alloc_n<int32_t>(mvalid + 1);
+  int32_t *pos = ar.alloc_n<int32_t>(mvalid + 1);
+  int32_t *rowcnt = ar.alloc_n<int32_t>((size_t)nc + 1);
+  fill_i32(rowcnt, 0, (int64_t)nc + 1, s);
+  contract_heads(mvalid, key2, head, s);
+  scan_excl(ar, head, pos, mvalid, s);
+  contract_emit(mvalid, key2, val2, head, pos, bits, cadj, cw, rowcnt, s);
+  scan_excl_widen(ar, rowcnt, cxadj, (int64_t)nc + 1, s);
+  PM_HIP(hipMemcpyAsync(&cx.host->j, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  *nnz_out = cx.host->j;
+  ar.rewind(m);
+}
+
+// number of coarse vertices from the leader flags; fills cmap
+static int32_t run_coarse_ids(Ctx &cx, int32_t n, int32_t *match, int32_t *cmap) {
+  Arena &ar = cx.ar;
+  hipStream_t s = cx.s;
+  const size_t m = ar.mark();
+  int32_t *leader = ar.alloc_n<int32_t>((size_t)n + 1);
+  int32_t *rank = ar.alloc_n<int32_t>((size_t)n + 1);
+  hem_finish(n, match, leader, s);
+  fill_i32(leader + n, 0, 1, s);
+  scan_excl(ar, leader, rank, (int64_t)n + 1, s);
+  coarse_ids(n, match, rank, cmap, s);
+  PM_HIP(hipMemcpyAsync(&cx.host->count, rank + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  const int32_t nc = cx.host->count;
+  ar.rewind(m);
+  return nc;
+}
+
+// Initial partition of level L on the host; writes codes into part (device).
+static void run_initial(Ctx &cx, const DGraph &g, const Hier &h, int32_t *part) {
+  hipStream_t s = cx.s;
+  std::vector<int64_t> xadj(g.n + 1);
+  std::vector<int32_t> adj(g.nnz), vw(g.n), ids(g.n);
+  PM_HIP(hipMemcpyAsync(xadj.data(), g.xadj, sizeof(int64_t) * (g.n + 1), hipMemcpyDeviceToHost, s));
+  if (g.nnz)
+    PM_HIP(hipMemcpyAsync(adj.data(), g.adj, sizeof(int32_t) * g.nnz, hipMemcpyDeviceToHost, s));
+  if (g.n) PM_HIP(hipMemcpyAsync(vw.data(), g.c, sizeof(int32_t) * g.n, hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  host_initial_partition(g.n, xadj.data(), adj.data(), vw.data(), h, ids.data());
+  for (int32_t v = 0; v < g.n; ++v) ids[v] = (int32_t)id_to_code(h, ids[v]);
+  if (g.n) {
+    PM_HIP(hipMemcpyAsync(part, ids.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice, s));
+    PM_HIP(hipStreamSynchronize(s));
+  }
+}
+
+}  // namespace pm
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace pm;
+
+namespace {
+
+template <class F>
+int guarded(F f) {
+  try {
+    return f();
+  } catch (const Error &e) {
+    (void)hipGetLastError();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    return PM_ENOMEM;
+  } catch (...) {
+    return PM_EHIP;
+  }
+}
+
+void check_device() {
+  int cnt = 0;
+  if (hipGetDeviceCount(&cnt) != hipSuccess || cnt <= 0) {
+    (void)hipGetLastError();
+    throw Error(PM_ENODEVICE, "no HIP device");
+  }
+}
+
+// Rejects mappings with ids outside [0,k): block ids index device arrays.
+void require_ids(Ctx &cx, const Hier &h, const int32_t *part, int32_t n) {
+  PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), cx.s));
+  check_ids(h, part, n, cx.dev, cx.s);
+  cx.pull();
+  if (cx.host->count) throw Error(PM_EINVAL, "mapping holds ids outside [0,k)");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pm_version(void) { return "pm 0.1.0 (gfx950)"; }
+
+const char *pm_strerror(int code) {
+  switch (code) {
+    case PM_OK: return "ok";
+    case PM_WARN_IMBALANCED: return "mapping written but exceeds L_max";
+    case PM_EINVAL: return "invalid argument";
+    case PM_EGRAPH: return "graph failed validation";
+    case PM_EOVERFLOW: return "size or weight limit exceeded";
+    case PM_ENOMEM: return "out of device memory";
+    case PM_EHIP: return "HIP runtime error";
+    case PM_ENODEVICE: return "no HIP device";
+    default: return "unknown error";
+  }
+}
+
+void pm_release(void) { release_all_arenas(); }
+
+int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part, int64_t *j_out,
+                 uint32_t flags, void *stream) {
+  return guarded([&] {
+    check_device();
+    if (!j_out || (!part && g && g->n > 0)) throw Error(PM_EINVAL, "NULL output or mapping");
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    ArenaLease lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(*lease, s);
+    int64_t total = 0;
+    validate_graph(*lease, dg, (flags & PM_FLAG_VALIDATE) != 0, &total, s);
+    require_ids(cx, hh, part, dg.n);
+    int32_t *codes = const_cast<int32_t *>(part);
+    if (!hh.pow2) {
+      codes = lease->alloc_n<int32_t>(dg.n);
+      ids_to_codes(hh, part, codes, dg.n, s);
+    }
+    int32_t *list = lease->alloc_n<int32_t>(dg.n);
+    Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
+    comm_cost(dg, cl, hh, codes, cx.dev, s);
+    cx.pull();
+    *j_out = cx.host->j;
+    return PM_OK;
+  });
+}
+
+int pm_block_weights(const pm_graph *g, const pm_hierarchy *h, const int32_t *part,
+                     int64_t *w_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    if (!w_out || (!part && g && g->n > 0)) throw Error(PM_EINVAL, "NULL output or mapping");
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    ArenaLease lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(*lease, s);
+    require_ids(cx, hh, part, dg.n);
+    int32_t *codes = lease->alloc_n<int32_t>(dg.n);
+    ids_to_codes(hh, part, codes, dg.n, s);
+    int64_t *w = lease->alloc_n<int64_t>((size_t)1 << hh.bits);
+    block_weights(dg, hh, codes, w, s);
+    // codes -> ids order: gather on the host (k is small)
+    std::vector<int64_t> wc((size_t)1 << hh.bits), wi(hh.k);
+    PM_HIP(hipMemcpyAsync(wc.data(), w, sizeof(int64_t) * wc.size(), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    for (int64_t b = 0; b < hh.k; ++b) wi[b] = wc[id_to_code(hh, b)];
+    PM_HIP(hipMemcpyAsync(w_out, wi.data(), sizeof(int64_t) * hh.k, hipMemcpyHostToDevice, s));
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+  });
+}
+
+int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t *lock,
+                int32_t *target_out, int64_t *gain_out, uint8_t *moved_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    if (dg.n > 0 && (!part || !lock || !target_out || !gain_out || !moved_out))
+      throw Error(PM_EINVAL, "NULL array");
+    ArenaLease lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(*lease, s);
+    int64_t total = 0;
+    validate_graph(*lease, dg, false, &total, s);
+    require_ids(cx, hh, part, dg.n);
+    int32_t *codes = lease->alloc_n<int32_t>(dg.n);
+    ids_to_codes(hh, part, codes, dg.n, s);
+    int32_t *list = lease->alloc_n<int32_t>(dg.n);
+    Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
+    int64_t *w = lease->alloc_n<int64_t>((size_t)1 << hh.bits);
+    block_weights(dg, hh, codes, w, s);
+    lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s);
+    lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
+    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w, cx.dev, s);
+    codes_to_ids(hh, codes, part, dg.n, s);
+    codes_to_ids(hh, target_out, target_out, dg.n, s);
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+  });
+}
+
+int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64_t lmax,
+                 int64_t sigma, uint64_t seed, int32_t level, int32_t iter, int32_t *part,
+                 uint8_t *moved_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    if (dg.n > 0 && (!part || !moved_out)) throw Error(PM_EINVAL, "NULL array");
+    ArenaLease lease;
+    Arena &ar = *lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(ar, s);
+    int64_t total = 0;
+    validate_graph(ar, dg, false, &total, s);
+    require_ids(cx, hh, part, dg.n);
+    const int64_t n = dg.n;
+    const int32_t ncodes = 1 << hh.bits;
+    int32_t *codes = ar.alloc_n<int32_t>(n);
+    ids_to_codes(hh, part, codes, dg.n, s);
+    int32_t *list = ar.alloc_n<int32_t>(n);
+    Classes cl = build_classes(ar, dg, list, cx.dev, cx.host, s);
+    int64_t *w = ar.alloc_n<int64_t>(ncodes);
+    int32_t *target = ar.alloc_n<int32_t>(n);
+    RebalanceBuffers rb;
+    rb.key = ar.alloc_n<int32_t>(n);
+    rb.dest = ar.alloc_n<int32_t>(n);
+    rb.flag = ar.alloc_n<uint8_t>(n);
+    rb.list = ar.alloc_n<int32_t>(n);
+    rb.list2 = ar.alloc_n<int32_t>(n);
+    rb.skey = ar.alloc_n<uint32_t>(n);
+    rb.skey2 = ar.alloc_n<uint32_t>(n);
+    rb.pre = ar.alloc_n<int64_t>(n);
+    rb.seg = ar.alloc_n<int32_t>(ncodes);
+    rb.elig = ar.alloc_n<int32_t>(ncodes);
+    rb.acc = ar.alloc_n<int64_t>(ncodes);
+    rb.rstart = ar.alloc_n<int64_t>(ncodes);
+    rb.rblock = ar.alloc_n<int32_t>(ncodes);
+    block_weights(dg, hh, codes, w, s);
+    const uint64_t hseed =
+        mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
+    rebalance_select(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
+                     moved_out, rb, cx.dev, cx.host, s);
+    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, cx.dev, s);
+    codes_to_ids(hh, codes, part, dg.n, s);
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+  });
+}
+
+int pm_refine(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, int32_t level,
+              int32_t *part, pm_refine_stats *stats, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    if (dg.n > 0 && !part) throw Error(PM_EINVAL, "NULL mapping");
+    ArenaLease lease;
+    Arena &ar = *lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(ar, s);
+    int64_t total = 0;
+    validate_graph(ar, dg, false, &total, s);
+    require_ids(cx, hh, part, dg.n);
+    const int64_t lmax = lmax_of(total, hh.k, eps);
+    const int64_t sigma = sigma_of(lmax, total, hh.k);
+    int32_t *best = ar.alloc_n<int32_t>(dg.n);
+    ids_to_codes(hh, part, best, dg.n, s);
+    int32_t *list = ar.alloc_n<int32_t>(dg.n);
+    Classes cl = build_classes(ar, dg, list, cx.dev, cx.host, s);
+    RefineResult R = refine_level(cx, dg, cl, hh, lmax, sigma, total, seed, level, best);
+    codes_to_ids(hh, best, part, dg.n, s);
+    PM_HIP(hipStreamSynchronize(s));
+    if (stats) *stats = R.st;
+    return R.status;
+  });
+}
+
+int pm_hem(const pm_graph *g, int64_t lmax, uint64_t seed, int32_t level, int32_t *match_out,
+           int32_t *rounds_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    if (dg.n > 0 && !match_out) throw Error(PM_EINVAL, "NULL output");
+    ArenaLease lease;
+    Arena &ar = *lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(ar, s);
+    int64_t total = 0;
+    validate_graph(ar, dg, false, &total, s);
+    Level L;
+    L.g = dg;
+    L.list = ar.alloc_n<int32_t>(dg.n);
+    L.cl = build_classes(ar, dg, L.list, cx.dev, cx.host, s);
+    int32_t *pref = ar.alloc_n<int32_t>(dg.n);
+    const int32_t r = run_hem(cx, L, lmax, seed, level, match_out, pref);
+    int32_t *leader = ar.alloc_n<int32_t>(dg.n);
+    hem_finish(dg.n, match_out, leader, s);
+    PM_HIP(hipStreamSynchronize(s));
+    if (rounds_out) *rounds_out = r;
+    return PM_OK;
+  });
+}
+
+int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap, int64_t *cxadj,
+                int32_t *cadjncy, int32_t *cadjwgt, int32_t *cvwgt, int32_t *nc_out,
+                int64_t *nnz_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    if (dg.n > 0 && (!match || !cmap || !cxadj || !cvwgt || !nc_out || !nnz_out))
+      throw Error(PM_EINVAL, "NULL array");
+    ArenaLease lease;
+    Arena &ar = *lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(ar, s);
+    Level L;
+    L.g = dg;
+    L.list = ar.alloc_n<int32_t>(dg.n);
+    L.cl = build_classes(ar, dg, L.list, cx.dev, cx.host, s);
+    int32_t *m = ar.alloc_n<int32_t>(dg.n);
+    if (dg.n) PM_HIP(hipMemcpyAsync(m, match, sizeof(int32_t) * dg.n, hipMemcpyDeviceToDevice, s));
+    const int32_t nc = run_coarse_ids(cx, dg.n, m, cmap);
+    int64_t nnz = 0;
+    run_contract(cx, L, m, cmap, nc, cxadj, cadjncy, cadjwgt, cvwgt, &nnz);
+    *nc_out = nc;
+    *nnz_out = nnz;
+    return PM_OK;
+  });
+}
+
+int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h, int32_t *part_out,
+                         void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    if (dg.n > 0 && !part_out) throw Error(PM_EINVAL, "NULL output");
+    ArenaLease lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(*lease, s);
+    run_initial(cx, dg, hh, part_out);
+    codes_to_ids(hh, part_out, part_out, dg.n, s);
+    PM_HIP(hipStreamSynchronize(s));
+    return PM_OK;
+  });
+}
+
+int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, int32_t *part_out,
+           pm_map_stats *stats, uint32_t flags, void *stream) {
+  return guarded([&] {
+    check_device();
+    const auto t_start = std::chrono::steady_clock::now();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    if (dg.n > 0 && !part_out) throw Error(PM_EINVAL, "NULL output");
+    ArenaLease lease;
+    Arena &ar = *lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(ar, s);
+    int64_t total = 0;
+    validate_graph(ar, dg, (flags & PM_FLAG_VALIDATE) != 0, &total, s);
+    const int64_t lmax = lmax_of(total, hh.k, eps);
+    const int64_t sigma = sigma_of(lmax, total, hh.k);
+    pm_map_stats st;
+    std::memset(&st, 0, sizeof(st));
+    st.lmax = lmax;
+    KernelTimer timer;
+    struct TimerScope {
+      explicit TimerScope(KernelTimer *t) { tl_timer = t; }
+      ~TimerScope() { tl_timer = nullptr; }
+    } timer_scope((flags & PM_FLAG_KERNEL_TIMES) ? &timer : nullptr);
+
+    std::vector<hipEvent_t> evs;
+    auto mark_event = [&]() {
+      hipEvent_t e;
+      PM_HIP(hipEventCreate(&e));
+      PM_HIP(hipEventRecord(e, s));
+      evs.push_back(e);
+      return e;
+    };
+    struct Span { hipEvent_t a, b; double *acc; };
+    std::vector<Span> spans;
+
+    std::vector<Level> levels;
+    levels.reserve(PM_MAX_GRAPH_LEVELS);
+    Level L0;
+    L0.g = dg;
+    L0.list = ar.alloc_n<int32_t>(dg.n);
+    L0.cl = build_classes(ar, dg, L0.list, cx.dev, cx.host, s);
+    levels.push_back(L0);
+
+    // ---- coarsening ----
+    while ((int64_t)levels.back().g.n >= 8 * hh.k && (int)levels.size() < PM_MAX_GRAPH_LEVELS) {
+      Level &L = levels.back();
+      const int32_t n = L.g.n;
+      const size_t mark0 = ar.mark();
+      int32_t *cmap = ar.alloc_n<int32_t>(n);
+      int64_t *cxadj = ar.alloc_n<int64_t>((size_t)n + 1);
+      int32_t *cadj = ar.alloc_n<int32_t>(L.g.nnz);
+      int32_t *cw = ar.alloc_n<int32_t>(L.g.nnz);
+      int32_t *cvw = ar.alloc_n<int32_t>(n);
+      int32_t *clist = ar.alloc_n<int32_t>(n);
+      const size_t mark1 = ar.mark();
+      int32_t *match = ar.alloc_n<int32_t>(n);
+      int32_t *pref = ar.alloc_n<int32_t>(n);
+      hipEvent_t e0 = mark_event();
+      const int32_t rounds = run_hem(cx, L, lmax, seed, (int32_t)levels.size() - 1, match, pref);
+      hipEvent_t e1 = mark_event();
+      spans.push_back({e0, e1, &st.coarsen_ms});
+      const int32_t nc = run_coarse_ids(cx, n, match, cmap);
+      if (20 * (int64_t)nc > 19 * (int64_t)n) {
+        ar.rewind(mark0);
+        break;
+      }
+      int64_t cnnz = 0;
+      run_contract(cx, L, match, cmap, nc, cxadj, cadj, cw, cvw, &cnnz);
+      ar.rewind(mark1);
+      Level C;
+      C.g = DGraph{nc, cnnz, cxadj, cadj, cw, cvw};
+      C.list = clist;
+      C.cl = build_classes(ar, C.g, C.list, cx.dev, cx.host, s);
+      hipEvent_t e2 = mark_event();
+      spans.push_back({e1, e2, &st.contract_ms});
+      L.cmap = cmap;
+      L.hem_rounds = rounds;
+      levels.push_back(C);
+    }
+    const int t = (int)levels.size() - 1;
+    st.levels = t + 1;
+    for (int i = 0; i <= t; ++i) {
+      st.level_n[i] = levels[i].g.n;
+      st.level_nnz[i] = levels[i].g.nnz;
+      st.level_hem_rounds[i] = levels[i].hem_rounds;
+    }
+
+    // ---- initial partitioning ----
+    int32_t *part = ar.alloc_n<int32_t>(levels[t].g.n);
+    {
+      hipEvent_t e0 = mark_event();
+      run_initial(cx, levels[t].g, hh, part);
+      hipEvent_t e1 = mark_event();
+      spans.push_back({e0, e1, &st.initial_ms});
+    }
+    // ---- uncoarsening with refinement ----
+    int32_t status = PM_OK;
+    for (int lv = t;; --lv) {
+      const Level &L = levels[lv];
+      RefineResult R = refine_level(cx, L.g, L.cl, hh, lmax, sigma, total, seed, lv, part);
+      st.refine_ms += R.st.refine_ms;
+      st.refine_arcs += R.st.arcs_processed;
+      st.level_iterations[lv] = R.st.iterations;
+      st.j_final = R.st.j_final;
+      st.feasible = R.st.feasible;
+      status = R.status;
+      if (lv == 0) break;
+      const Level &F = levels[lv - 1];
+      int32_t *fine = ar.alloc_n<int32_t>(F.g.n);
+      hipEvent_t e0 = mark_event();
+      project(F.g.n, F.cmap, part, fine, s);
+      hipEvent_t e1 = mark_event();
+      spans.push_back({e0, e1, &st.uncoarsen_ms});
+      part = fine;
+    }
+    codes_to_ids(hh, part, part_out, dg.n, s);
+    PM_HIP(hipStreamSynchronize(s));
+    for (auto &sp : spans) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
+    }
+    for (auto e : evs) (void)hipEventDestroy(e);
+    if (flags & PM_FLAG_KERNEL_TIMES) timer.finish(st.kernel_launches, st.kernel_ms, st.kernel_bytes);
+    st.total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+    if (stats) *stats = st;
+    return status;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// kernels.h -- host-side launchers of the gfx950 kernels.
+#pragma once
+
+#include "pm_internal.h"
+
+namespace pm {
+
+// Small device-side status block for read-backs (one per call).
+struct Status {
+  int64_t dj;          // J change accumulated by apply_moves
+  int64_t maxw;        // heaviest block (max_block)
+  int64_t j;           // full J (comm_cost)
+  int32_t count;       // generic counter (matches, sources, ...)
+  int32_t count2;
+  int32_t n_eligible;  // blocks within the rebalancing cap
+  int32_t pad_;
+  int64_t resid_total; // strong rebalancing: total residual capacity
+};
+
+// ---- optional per-launch kernel timing --------------------------------------
+enum { KT_LP1 = 0, KT_LP2, KT_APPLY, KT_HEM, NKT };
+struct KernelTimer {
+  std::vector<hipEvent_t> start[NKT], stop[NKT];
+  double bytes[NKT] = {0, 0, 0, 0};
+  // event pair for one launch of kernel id (created here, destroyed in finish)
+  void pair(int id, hipEvent_t &a, hipEvent_t &b);
+  // sums the elapsed times; call after the stream has been synchronised
+  void finish(int64_t *launches, double *ms, double *bytes_out);
+  ~KernelTimer();
+};
+// timer of the call running on this host thread (nullptr: no timing)
+extern thread_local KernelTimer *tl_timer;
+
+// ---- per-level setup ------------------------------------------------------
+// Classifies every vertex by degree and builds the class lists.  `list` must
+// hold n entries.  Synchronises the stream (reads the class sizes).
+Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
+                      Status *st_host, hipStream_t s);
+int32_t classes_workgroups(const Classes &cl);
+
+// ---- mapping conversion ---------------------------------------------------
+void ids_to_codes(const Hier &h, const int32_t *ids, int32_t *codes, int32_t n, hipStream_t s);
+void codes_to_ids(const Hier &h, const int32_t *codes, int32_t *ids, int32_t n, hipStream_t s);
+// flags any id outside [0,k) into st->count
+void check_ids(const Hier &h, const int32_t *ids, int32_t n, Status *st, hipStream_t s);
+
+// ---- objective and balance ------------------------------------------------
+void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               Status *st, hipStream_t s);             // st->j = J
+void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
+                   hipStream_t s);                     // w[0..2^bits)
+void max_block(const Hier &h, const int64_t *w, Status *st, hipStream_t s);  // st->maxw
+
+// ---- label propagation (Algorithm 4) --------------------------------------
+void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s);
+void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
+// Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
+// st->dj and the block weight changes into w; sets lock = moved if lock != 0.
+void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
+                 const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
+                 Status *st, hipStream_t s);
+
+// ---- rebalancing (Algorithm 5) --------------------------------------------
+struct RebalanceBuffers {
+  int32_t *key;        // n: (block << 6 | bucket) for sources, -1 otherwise
+  int32_t *dest;       // n: chosen destination
+  uint8_t *flag;       // n: scratch flags
+  int32_t *list;       // n: compacted vertex ids
+  int32_t *list2;      // n
+  uint32_t *skey;      // n
+  uint32_t *skey2;     // n
+  int64_t *pre;        // n: exclusive weight prefix
+  int32_t *seg;        // 2^bits: segment starts per block
+  int32_t *elig;       // 2^bits: blocks within the cap, ascending
+  int64_t *acc;        // 2^bits: accepted weight per destination
+  int64_t *rstart;     // 2^bits: residual prefix
+  int32_t *rblock;     // 2^bits: blocks with residual > 0
+};
+// Full weak/strong rebalancing round; leaves moved/target ready for
+// apply_moves.  Synchronises the stream (list sizes).
+void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h,
+                      bool strong, int64_t lmax, int64_t sigma, int64_t total,
+                      uint64_t hseed, const int32_t *part, const int64_t *w,
+                      int32_t *target, uint8_t *moved,
+                      const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
+                      hipStream_t s);
+
+// ---- matching and contraction ---------------------------------------------
+void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
+                const int32_t *match, int32_t *pref, hipStream_t s);
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st, hipStream_t s);
+void hem_isolated_flags(const DGraph &g, const int32_t *match, uint8_t *flag, hipStream_t s);
+void hem_pair_isolated(const int32_t *iso, int32_t niso, const int32_t *vwgt, int64_t lmax,
+                       int32_t *match, hipStream_t s);
+void hem_finish(int32_t n, int32_t *match, int32_t *leader, hipStream_t s);
+void coarse_ids(int32_t n, const int32_t *match, const int32_t *rank, int32_t *cmap,
+                hipStream_t s);
+void coarse_vwgt(int32_t n, const int32_t *match, const int32_t *cmap, const int32_t *vwgt,
+                 int32_t *cvwgt, hipStream_t s);
+void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int bits,
+                   uint64_t *key, int32_t *val, Status *st, hipStream_t s);
+void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s);
+void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,
+                   const int32_t *pos, int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt,
+                   hipStream_t s);
+void project(int32_t n, const int32_t *cmap, const int32_t *coarse, int32_t *fine,
+             hipStream_t s);
+
+// ---- misc -----------------------------------------------------------------
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);
+void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+
+}  // namespace pm

@@ -1,0 +1,978 @@
+// refine.hip -- objective, balance, label propagation and rebalancing kernels
+// for gfx950.
+//
+// Vertices are processed by degree class (see Classes): a vertex of degree
+// <= G is owned by a group of G consecutive lanes of a wave64 holding one arc
+// per lane, so a single load instruction of the wave streams the adjacent rows
+// of 64/G vertices; vertices of degree > 64 get a whole workgroup that
+// aggregates the neighbour-block connectivity in an LDS histogram over block
+// codes (the per-vertex connectivity structure of Section 3.2, kept in LDS
+// instead of a global hash table).  All arithmetic is integer; sums are
+// order-independent, and every choice has a total-order tie-break, so results
+// do not depend on thread scheduling or on the order of entries in a row.
+#include <hip/hip_ext.h>
+
+#include "device_util.h"
+#include "kernels.h"
+#include "prim.h"
+
+namespace pm {
+
+static inline unsigned grid_for(int64_t n, int per = kThreads) {
+  int64_t b = (n + per - 1) / per;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+// ===========================================================================
+// misc fills
+// ===========================================================================
+template <class T>
+__global__ void k_fill(T *p, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+template <class T>
+static void fill(T *p, T v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  unsigned g = grid_for(n);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_fill<T>, dim3(g), dim3(kThreads), 0, s, p, v, n);
+  PM_LAUNCH_CHECK();
+}
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
+
+// ===========================================================================
+// degree classes
+// ===========================================================================
+__global__ void k_classify(DGraph g, uint8_t *cls, int32_t *counts) {
+  __shared__ int32_t c[NCLS];
+  if (threadIdx.x < NCLS) c[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < g.n) {
+    int64_t d = g.xadj[v + 1] - g.xadj[v];
+    int k = d == 0 ? CLS_ISO : d <= 8 ? CLS_G8 : d <= 16 ? CLS_G16 : d <= 32 ? CLS_G32
+          : d <= 64 ? CLS_G64 : CLS_BIG;
+    cls[v] = (uint8_t)k;
+    atomicAdd(&c[k], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < NCLS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+}
+
+Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
+                      Status *st_host, hipStream_t s) {
+  (void)st_dev;
+  (void)st_host;
+  Classes cl{};
+  cl.list = list;
+  size_t m = ar.mark();
+  uint8_t *cls = ar.alloc_n<uint8_t>((size_t)g.n + 1);
+  int32_t *counts = ar.alloc_n<int32_t>(2 * NCLS);
+  PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2 * NCLS, s));
+  if (g.n > 0) {
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, cls, counts);
+    PM_LAUNCH_CHECK();
+  }
+  int32_t *host = static_cast<int32_t *>(ar.host_stage(sizeof(int32_t) * 2 * NCLS));
+  PM_HIP(hipMemcpyAsync(host, counts, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  int32_t cnt[NCLS];
+  for (int c = 0; c < NCLS; ++c) cnt[c] = host[c];
+  cl.off[0] = 0;
+  cl.wg[0] = 0;
+  for (int c = 0; c < NCLS; ++c) {
+    cl.off[c + 1] = cl.off[c] + cnt[c];
+    int per = class_per_wg(c);
+    cl.wg[c + 1] = cl.wg[c] + (cnt[c] + per - 1) / per;
+  }
+  for (int c = 0; c < NCLS; ++c)
+    if (cnt[c]) select_class(ar, cls, (uint8_t)c, list + cl.off[c], counts + NCLS + c, g.n, s);
+  ar.rewind(m);
+  return cl;
+}
+
+int32_t classes_workgroups(const Classes &cl) { return cl.wg[NCLS]; }
+
+// ===========================================================================
+// id <-> code conversion
+// ===========================================================================
+__global__ void k_ids_to_codes(Hier h, const int32_t *ids, int32_t *codes, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) codes[i] = (int32_t)id_to_code(h, ids[i]);
+}
+__global__ void k_codes_to_ids(Hier h, const int32_t *codes, int32_t *ids, int32_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ids[i] = code_to_id(h, (uint32_t)codes[i]);
+}
+__global__ void k_check_ids(int64_t k, const int32_t *ids, int32_t n, Status *st) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (ids[i] < 0 || (int64_t)ids[i] >= k)) atomicAdd(&st->count, 1);
+}
+
+void ids_to_codes(const Hier &h, const int32_t *ids, int32_t *codes, int32_t n, hipStream_t s) {
+  if (n <= 0) return;
+  if (h.pow2) {
+    if (ids != codes)
+      PM_HIP(hipMemcpyAsync(codes, ids, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  hipLaunchKernelGGL(k_ids_to_codes, dim3(grid_for(n)), dim3(kThreads), 0, s, h, ids, codes, n);
+  PM_LAUNCH_CHECK();
+}
+void codes_to_ids(const Hier &h, const int32_t *codes, int32_t *ids, int32_t n, hipStream_t s) {
+  if (n <= 0) return;
+  if (h.pow2) {
+    if (ids != codes)
+      PM_HIP(hipMemcpyAsync(ids, codes, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    return;
+  }
+  hipLaunchKernelGGL(k_codes_to_ids, dim3(grid_for(n)), dim3(kThreads), 0, s, h, codes, ids, n);
+  PM_LAUNCH_CHECK();
+}
+void check_ids(const Hier &h, const int32_t *ids, int32_t n, Status *st, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(kThreads), 0, s, h.k, ids, n, st);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// J (Section 2): sum over arcs of w * D(Pi(u), Pi(v))
+// ===========================================================================
+struct CostArgs {
+  DGraph g;
+  Classes cl;
+  Hier h;
+  const int32_t *part;
+  Status *st;
+};
+
+template <int G>
+__device__ __forceinline__ int64_t cost_group(const CostArgs &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return 0;
+  const int lane = threadIdx.x % G;
+  const int64_t e = A.g.xadj[v] + lane;
+  if (e >= A.g.xadj[v + 1]) return 0;
+  return (int64_t)A.g.w[e] * dist(A.h, (uint32_t)A.part[v], (uint32_t)A.part[A.g.adj[e]]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_comm_cost(CostArgs A) {
+  __shared__ BlockScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  int64_t x = 0;
+  switch (cls) {
+    case CLS_G8: x = cost_group<8>(A, cls, local); break;
+    case CLS_G16: x = cost_group<16>(A, cls, local); break;
+    case CLS_G32: x = cost_group<32>(A, cls, local); break;
+    case CLS_G64: x = cost_group<64>(A, cls, local); break;
+    case CLS_BIG: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const uint32_t p = (uint32_t)A.part[v];
+      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+        x += (int64_t)A.g.w[e] * dist(A.h, p, (uint32_t)A.part[A.g.adj[e]]);
+      break;
+    }
+    default: break;
+  }
+  x = block_sum64(x, sc);
+  if (threadIdx.x == 0 && x != 0) atomicAdd((unsigned long long *)&A.st->j, (unsigned long long)x);
+}
+
+void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               Status *st, hipStream_t s) {
+  PM_HIP(hipMemsetAsync(&st->j, 0, sizeof(int64_t), s));
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  CostArgs A{g, cl, h, part, st};
+  hipLaunchKernelGGL(k_comm_cost, dim3(nwg), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// block weights and the heaviest block
+// ===========================================================================
+__global__ __launch_bounds__(kThreads) void k_block_weights(const int32_t *part,
+                                                            const int32_t *vwgt, int32_t n,
+                                                            int32_t ncodes, int64_t *w) {
+  extern __shared__ uint32_t hist[];
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) hist[c] = 0;
+  __syncthreads();
+  for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * kThreads)
+    atomicAdd(&hist[part[v]], (uint32_t)vwgt[v]);
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncodes; c += kThreads)
+    if (hist[c]) atomicAdd((unsigned long long *)&w[c], (unsigned long long)hist[c]);
+}
+
+void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
+                   hipStream_t s) {
+  const int32_t ncodes = 1 << h.bits;
+  PM_HIP(hipMemsetAsync(w, 0, sizeof(int64_t) * ncodes, s));
+  if (g.n <= 0) return;
+  unsigned grid = grid_for(g.n, kThreads * 16);
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(k_block_weights, dim3(grid), dim3(kThreads), sizeof(uint32_t) * ncodes, s,
+                     part, g.c, g.n, ncodes, w);
+  PM_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(kThreads) void k_max_block(const int64_t *w, int32_t ncodes,
+                                                        Status *st) {
+  __shared__ BlockScratch sc;
+  int64_t m = INT64_MIN;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) m = w[c] > m ? w[c] : m;
+  uint32_t dummy = 0;
+  block_argmax(m, dummy, sc);
+  if (threadIdx.x == 0) st->maxw = m;
+}
+
+void max_block(const Hier &h, const int64_t *w, Status *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_block, dim3(1), dim3(kThreads), 0, s, w, (int32_t)(1 << h.bits), st);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Label propagation, phase 1 (Algorithm 4, first filter)
+//
+// For vertex v in block p with neighbour-block connectivity conn(v,x):
+//   cost(b) = sum_x conn(v,x) D(b,x),  G_b(v) = cost(p) - cost(b)   (eq. 1)
+// The best candidate b != p among the neighbour blocks maximises G, ties to
+// the smaller block.  v enters X iff that gain is >= 0.
+// ===========================================================================
+struct LP1Args {
+  DGraph g;
+  Classes cl;
+  Hier h;
+  const int32_t *part;
+  const uint8_t *lock;
+  int32_t *target;
+  int64_t *gain;
+};
+
+template <int G>
+__device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return;
+  const int lane = threadIdx.x % G;
+  const uint32_t p = (uint32_t)A.part[v];
+  if (A.lock[v]) {
+    if (lane == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int64_t beg = A.g.xadj[v];
+  const int deg = (int)(A.g.xadj[v + 1] - beg);
+  const bool valid = lane < deg;
+  uint32_t bu = p;
+  int32_t wu = 0;
+  if (valid) {
+    bu = (uint32_t)A.part[A.g.adj[beg + lane]];
+    wu = A.g.w[beg + lane];
+  }
+  const bool cand = valid && bu != p;
+  if (!gor<G>(cand ? 1 : 0)) {
+    if (lane == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int64_t costp = gsum64<G>((int64_t)wu * dist(A.h, p, bu));
+  int64_t cost = 0;
+  for (int j = 0; j < deg; ++j) {
+    const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+    const int32_t wj = gshfl<G>(wu, j);
+    cost += (int64_t)wj * dist(A.h, bu, bj);
+  }
+  int64_t g = cand ? costp - cost : INT64_MIN;
+  uint32_t b = cand ? bu : 0xFFFFFFFFu;
+  gargmax<G>(g, b);
+  if (lane == 0) {
+    if (g >= 0) {
+      A.target[v] = (int32_t)b;
+      A.gain[v] = g;
+    } else {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+  }
+}
+
+// cost(c) from the exclusive prefix X over the connectivity histogram:
+// conn(c) = X[c+1] - X[c], S_i(c) = sum of conn over c's level-i group.
+__device__ __forceinline__ int64_t level_cost(const Hier &h, const uint32_t *X, uint32_t c,
+                                              int32_t ncodes) {
+  int64_t prev = (int64_t)(X[c + 1] - X[c]);
+  int64_t cost = 0;
+  for (int i = 1; i <= h.levels; ++i) {
+    const int sh = h.shift[i];
+    const uint32_t lo = (c >> sh) << sh;
+    uint32_t hi = lo + (1u << sh);
+    if (hi > (uint32_t)ncodes) hi = (uint32_t)ncodes;
+    const int64_t S = (int64_t)(X[hi] - X[lo]);
+    cost += (int64_t)h.d[i - 1] * (S - prev);
+    prev = S;
+  }
+  return cost;
+}
+
+// Builds X[0..ncodes] = exclusive prefix of conn(v, .) in LDS.
+__device__ __forceinline__ void big_histogram(const DGraph &g, const int32_t *part, int32_t v,
+                                              uint32_t *X, int32_t ncodes, BlockScratch &sc) {
+  for (int c = threadIdx.x; c <= ncodes; c += kThreads) X[c] = 0;
+  __syncthreads();
+  for (int64_t e = g.xadj[v] + threadIdx.x; e < g.xadj[v + 1]; e += kThreads)
+    atomicAdd(&X[part[g.adj[e]] + 1], (uint32_t)g.w[e]);
+  __syncthreads();
+  block_scan_lds(X, ncodes + 1, sc);
+}
+
+__device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X,
+                                        BlockScratch &sc) {
+  const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+  const uint32_t p = (uint32_t)A.part[v];
+  if (A.lock[v]) {
+    if (threadIdx.x == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int32_t ncodes = 1 << A.h.bits;
+  big_histogram(A.g, A.part, v, X, ncodes, sc);
+  const uint32_t total = X[ncodes];
+  const uint32_t connp = X[p + 1] - X[p];
+  if (total == connp) {
+    if (threadIdx.x == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int64_t costp = level_cost(A.h, X, p, ncodes);
+  int64_t g = INT64_MIN;
+  uint32_t b = 0xFFFFFFFFu;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
+    if ((uint32_t)c == p || X[c + 1] == X[c]) continue;
+    const int64_t gc = costp - level_cost(A.h, X, (uint32_t)c, ncodes);
+    if (gc > g || (gc == g && (uint32_t)c < b)) {
+      g = gc;
+      b = (uint32_t)c;
+    }
+  }
+  block_argmax(g, b, sc);
+  if (threadIdx.x == 0) {
+    if (g >= 0) {
+      A.target[v] = (int32_t)b;
+      A.gain[v] = g;
+    } else {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
+  extern __shared__ uint32_t X[];
+  __shared__ BlockScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+        A.target[v] = A.part[v];
+        A.gain[v] = kNotInX;
+      }
+      break;
+    }
+    case CLS_G8: lp1_group<8>(A, cls, local); break;
+    case CLS_G16: lp1_group<16>(A, cls, local); break;
+    case CLS_G32: lp1_group<32>(A, cls, local); break;
+    case CLS_G64: lp1_group<64>(A, cls, local); break;
+    default: lp1_big(A, local, X, sc); break;
+  }
+}
+
+static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << h.bits) + 1); }
+
+void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  LP1Args A{g, cl, h, part, lock, target, gain};
+  if (tl_timer) {
+    hipEvent_t a, b;
+    tl_timer->pair(KT_LP1, a, b);
+    tl_timer->bytes[KT_LP1] += 12.0 * (double)g.nnz + 25.0 * (double)g.n;
+    hipExtLaunchKernelGGL(k_lp_phase1, dim3(nwg), dim3(kThreads), big_lds(h), s, a, b, 0, A);
+  } else {
+    hipLaunchKernelGGL(k_lp_phase1, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+  }
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Label propagation, phase 2 (Algorithm 4, second filter)
+//
+// For v in X the gain of its move is re-evaluated with every neighbour u in X
+// that precedes v (g(u) > g(v), or equal gain and u < v) counted at u's
+// target and every other neighbour at its current block; v moves iff >= 0.
+// ===========================================================================
+struct LP2Args {
+  DGraph g;
+  Classes cl;
+  Hier h;
+  const int32_t *part;
+  const int32_t *target;
+  const int64_t *gain;
+  uint8_t *moved;
+};
+
+__device__ __forceinline__ int64_t lp2_arc(const LP2Args &A, int32_t v, int64_t gv, uint32_t p,
+                                           uint32_t t, int64_t e) {
+  const int32_t u = A.g.adj[e];
+  const int64_t gu = A.gain[u];
+  uint32_t pu = (uint32_t)A.part[u];
+  if (gu != kNotInX && (gu > gv || (gu == gv && u < v))) pu = (uint32_t)A.target[u];
+  return (int64_t)A.g.w[e] * (dist(A.h, p, pu) - dist(A.h, t, pu));
+}
+
+template <int G>
+__device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return;
+  const int lane = threadIdx.x % G;
+  const int64_t gv = A.gain[v];
+  if (gv == kNotInX) {
+    if (lane == 0) A.moved[v] = 0;
+    return;
+  }
+  const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+  const int64_t e = A.g.xadj[v] + lane;
+  int64_t x = e < A.g.xadj[v + 1] ? lp2_arc(A, v, gv, p, t, e) : 0;
+  x = gsum64<G>(x);
+  if (lane == 0) A.moved[v] = x >= 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
+  __shared__ BlockScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
+        A.moved[A.cl.list[A.cl.off[CLS_ISO] + idx]] = 0;
+      break;
+    }
+    case CLS_G8: lp2_group<8>(A, cls, local); break;
+    case CLS_G16: lp2_group<16>(A, cls, local); break;
+    case CLS_G32: lp2_group<32>(A, cls, local); break;
+    case CLS_G64: lp2_group<64>(A, cls, local); break;
+    default: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const int64_t gv = A.gain[v];
+      if (gv == kNotInX) {
+        if (threadIdx.x == 0) A.moved[v] = 0;
+        break;
+      }
+      const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+      int64_t x = 0;
+      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+        x += lp2_arc(A, v, gv, p, t, e);
+      x = block_sum64(x, sc);
+      if (threadIdx.x == 0) A.moved[v] = x >= 0 ? 1 : 0;
+      break;
+    }
+  }
+}
+
+void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
+               const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  LP2Args A{g, cl, h, part, target, gain, moved};
+  if (tl_timer) {
+    hipEvent_t a, b;
+    tl_timer->pair(KT_LP2, a, b);
+    hipExtLaunchKernelGGL(k_lp_phase2, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+  } else {
+    hipLaunchKernelGGL(k_lp_phase2, dim3(nwg), dim3(kThreads), 0, s, A);
+  }
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Applying a set of moves.
+//
+// apply_moves first accounts for the moves -- exact change of J and of the
+// block weights -- reading the old mapping only, then commits
+// part[v] <- target[v] in a second launch.  In the accounting, an arc with
+// exactly one moved endpoint is seen once, from the moved side, and stands
+// for both of its directions (weight 2); an arc with both endpoints moved is
+// seen from each side (weight 1 each).
+// ===========================================================================
+struct ApplyArgs {
+  DGraph g;
+  Classes cl;
+  Hier h;
+  const int32_t *part;
+  const int32_t *target;
+  const uint8_t *moved;
+  uint8_t *lock;
+  int64_t *w;
+  Status *st;
+};
+
+__device__ __forceinline__ int64_t apply_arc(const ApplyArgs &A, uint32_t p, uint32_t t,
+                                             int64_t e) {
+  const int32_t u = A.g.adj[e];
+  const uint32_t old_u = (uint32_t)A.part[u];
+  if (A.moved[u]) {
+    const uint32_t new_u = (uint32_t)A.target[u];
+    return (int64_t)A.g.w[e] * (dist(A.h, t, new_u) - dist(A.h, p, old_u));
+  }
+  return 2 * (int64_t)A.g.w[e] * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+}
+
+__device__ __forceinline__ void apply_weights(const ApplyArgs &A, int32_t v, uint32_t p,
+                                              uint32_t t) {
+  const unsigned long long c = (unsigned long long)(int64_t)A.g.c[v];
+  atomicAdd((unsigned long long *)&A.w[t], c);
+  atomicAdd((unsigned long long *)&A.w[p], (unsigned long long)(-(int64_t)c));
+}
+
+template <int G>
+__device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return 0;
+  const int lane = threadIdx.x % G;
+  const uint8_t m = A.moved[v];
+  if (A.lock && lane == 0) A.lock[v] = m;
+  if (!m) return 0;
+  const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+  if (lane == 0) apply_weights(A, v, p, t);
+  const int64_t e = A.g.xadj[v] + lane;
+  return e < A.g.xadj[v + 1] ? apply_arc(A, p, t, e) : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
+  __shared__ BlockScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  int64_t x = 0;
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+        const uint8_t m = A.moved[v];
+        if (A.lock) A.lock[v] = m;
+        if (m) apply_weights(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v]);
+      }
+      break;
+    }
+    case CLS_G8: x = apply_group<8>(A, cls, local); break;
+    case CLS_G16: x = apply_group<16>(A, cls, local); break;
+    case CLS_G32: x = apply_group<32>(A, cls, local); break;
+    case CLS_G64: x = apply_group<64>(A, cls, local); break;
+    default: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const uint8_t m = A.moved[v];
+      if (A.lock && threadIdx.x == 0) A.lock[v] = m;
+      if (m) {
+        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+        if (threadIdx.x == 0) apply_weights(A, v, p, t);
+        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+          x += apply_arc(A, p, t, e);
+      }
+      break;
+    }
+  }
+  x = block_sum64(x, sc);
+  if (threadIdx.x == 0 && x != 0)
+    atomicAdd((unsigned long long *)&A.st->dj, (unsigned long long)x);
+}
+
+__global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const uint8_t *moved) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && moved[v]) part[v] = target[v];
+}
+
+void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
+                 const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
+                 Status *st, hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  if (nwg == 0) return;
+  ApplyArgs A{g, cl, h, part, target, moved, lock, w, st};
+  if (tl_timer) {
+    hipEvent_t a, b;
+    tl_timer->pair(KT_APPLY, a, b);
+    hipExtLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+  } else {
+    hipLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), 0, s, A);
+  }
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
+                     moved);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Rebalancing (Algorithm 5 and the text around it)
+//
+// Sources: vertices of blocks heavier than L_max that are not heavy
+// (2k c(v) > 3 (k c(block) - c(V))).  Destination: the neighbour block with
+// the largest connection among blocks with weight <= cap (cap = sigma for
+// weak, L_max for strong; ties to the smaller block), else a pseudo-random
+// block within the cap.  Loss g = conn(v,t) - conn(v,own) (edge-cut loss),
+// bucket 0 ("+"), 1 ("0") or 2 + floor(log2(-g)).  Per source block the
+// sources ordered by (bucket, id) move while the weight before them is
+// below the block's excess.  Strong rebalancing then accepts movers per
+// destination while the destination stays within L_max, and spreads the
+// rejected ones over the residual capacities.
+// ===========================================================================
+struct RebArgs {
+  DGraph g;
+  Classes cl;
+  Hier h;
+  const int32_t *part;
+  const int64_t *w;
+  int64_t lmax;
+  int64_t cap;
+  int64_t total;
+  uint64_t hseed;
+  const int32_t *elig;
+  const Status *st;
+  int32_t *key;
+  int32_t *dest;
+  uint8_t *flag;
+};
+
+__device__ __forceinline__ int32_t bucket_of(int64_t g) {
+  if (g > 0) return 0;
+  if (g == 0) return 1;
+  return 2 + (63 - __builtin_clzll((unsigned long long)(-g)));
+}
+
+__device__ __forceinline__ bool is_source(const RebArgs &A, int32_t v, uint32_t p) {
+  const int64_t wp = A.w[p];
+  if (wp <= A.lmax) return false;
+  return !(2 * A.h.k * (int64_t)A.g.c[v] > 3 * (A.h.k * wp - A.total));
+}
+
+// Final decision for a source v with best neighbour block (b, conn_b) or none
+// (b == 0xFFFFFFFF), conn to own block connp.
+__device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
+                                           int64_t conn_b, int64_t connp) {
+  if (b == 0xFFFFFFFFu) {
+    const int32_t ne = A.st->n_eligible;
+    if (ne <= 0) {
+      A.key[v] = -1;
+      A.flag[v] = 0;
+      return;
+    }
+    b = (uint32_t)A.elig[mix_hash(A.hseed, (uint64_t)v) % (uint64_t)ne];
+    conn_b = 0;
+  }
+  A.key[v] = (int32_t)((p << 6) | (uint32_t)bucket_of(conn_b - connp));
+  A.dest[v] = (int32_t)b;
+  A.flag[v] = 1;
+}
+
+__device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) {
+  A.key[v] = -1;
+  A.flag[v] = 0;
+}
+
+template <int G>
+__device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) {
+  int32_t v;
+  if (!group_vertex<G>(A.cl, cls, local, v)) return;
+  const int lane = threadIdx.x % G;
+  const uint32_t p = (uint32_t)A.part[v];
+  if (!is_source(A, v, p)) {
+    if (lane == 0) reb_not_source(A, v);
+    return;
+  }
+  const int64_t beg = A.g.xadj[v];
+  const int deg = (int)(A.g.xadj[v + 1] - beg);
+  const bool valid = lane < deg;
+  uint32_t bu = p;
+  int32_t wu = 0;
+  if (valid) {
+    bu = (uint32_t)A.part[A.g.adj[beg + lane]];
+    wu = A.g.w[beg + lane];
+  }
+  const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
+  const bool cand = valid && bu != p && A.w[bu] <= A.cap;
+  int64_t conn = 0;
+  for (int j = 0; j < deg; ++j) {
+    const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+    const int32_t wj = gshfl<G>(wu, j);
+    conn += bj == bu ? wj : 0;
+  }
+  int64_t val = cand ? conn : INT64_MIN;
+  uint32_t b = cand ? bu : 0xFFFFFFFFu;
+  gargmax<G>(val, b);
+  if (lane == 0) reb_decide(A, v, p, b, val, connp);
+}
+
+__device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X,
+                                        BlockScratch &sc) {
+  const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+  const uint32_t p = (uint32_t)A.part[v];
+  if (!is_source(A, v, p)) {
+    if (threadIdx.x == 0) reb_not_source(A, v);
+    return;
+  }
+  const int32_t ncodes = 1 << A.h.bits;
+  big_histogram(A.g, A.part, v, X, ncodes, sc);
+  int64_t val = INT64_MIN;
+  uint32_t b = 0xFFFFFFFFu;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
+    const uint32_t conn = X[c + 1] - X[c];
+    if ((uint32_t)c == p || conn == 0 || A.w[c] > A.cap) continue;
+    if ((int64_t)conn > val) {
+      val = conn;
+      b = (uint32_t)c;
+    }
+  }
+  block_argmax(val, b, sc);
+  if (threadIdx.x == 0) reb_decide(A, v, p, b, val, (int64_t)(X[p + 1] - X[p]));
+}
+
+__global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
+  extern __shared__ uint32_t X[];
+  __shared__ BlockScratch sc;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+        const uint32_t p = (uint32_t)A.part[v];
+        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
+        else reb_not_source(A, v);
+      }
+      break;
+    }
+    case CLS_G8: reb_group<8>(A, cls, local); break;
+    case CLS_G16: reb_group<16>(A, cls, local); break;
+    case CLS_G32: reb_group<32>(A, cls, local); break;
+    case CLS_G64: reb_group<64>(A, cls, local); break;
+    default: reb_big(A, local, X, sc); break;
+  }
+}
+
+// Blocks within the cap, ascending (one workgroup over all codes).
+__global__ __launch_bounds__(kThreads) void k_reb_eligible(Hier h, const int64_t *w, int64_t cap,
+                                                           int32_t *elig, Status *st) {
+  __shared__ BlockScratch sc;
+  const int32_t ncodes = 1 << h.bits;
+  const int per = (ncodes + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < ncodes ? lo + per : ncodes;
+  uint32_t cnt = 0;
+  for (int c = lo; c < hi; ++c) cnt += (code_valid(h, (uint32_t)c) && w[c] <= cap) ? 1u : 0u;
+  uint32_t pos = block_excl_scan(cnt, sc);
+  for (int c = lo; c < hi; ++c)
+    if (code_valid(h, (uint32_t)c) && w[c] <= cap) elig[pos++] = c;
+  if (threadIdx.x == kThreads - 1) st->n_eligible = (int32_t)pos;
+}
+
+__global__ void k_gather_keys(int32_t m, const int32_t *list, const int32_t *key,
+                              uint32_t *skey) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) skey[i] = (uint32_t)key[list[i]];
+}
+__global__ void k_gather_dest_keys(int32_t m, const int32_t *list, const int32_t *key,
+                                   const int32_t *dest, uint32_t *skey) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) {
+    const int32_t v = list[i];
+    skey[i] = ((uint32_t)dest[v] << 6) | ((uint32_t)key[v] & 63u);
+  }
+}
+// first position of every block in a list sorted by (block << 6 | bucket)
+__global__ void k_seg_starts(int32_t m, const uint32_t *skey, int32_t *seg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && (i == 0 || (skey[i] >> 6) != (skey[i - 1] >> 6))) seg[skey[i] >> 6] = (int32_t)i;
+}
+// moves: sources whose exclusive prefix within their block is below the excess
+__global__ void k_select_prefix(int32_t m, const uint32_t *skey, const int32_t *list,
+                                const int64_t *pre, const int32_t *seg, const int64_t *w,
+                                int64_t lmax, const int32_t *dest, int32_t *target,
+                                uint8_t *moved) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t a = skey[i] >> 6;
+  if (pre[i] - pre[seg[a]] < w[a] - lmax) {
+    const int32_t v = list[i];
+    moved[v] = 1;
+    target[v] = dest[v];
+  }
+}
+// strong: accept per destination while it stays within L_max
+__global__ void k_accept(int32_t m, const uint32_t *skey, const int32_t *list,
+                         const int64_t *pre, const int32_t *seg, const int64_t *w,
+                         const int32_t *vwgt, int64_t lmax, int64_t *acc, uint8_t *moved,
+                         uint8_t *reject) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t t = skey[i] >> 6;
+  const int32_t v = list[i];
+  if (w[t] + (pre[i] - pre[seg[t]]) + vwgt[v] <= lmax) {
+    atomicAdd((unsigned long long *)&acc[t], (unsigned long long)(int64_t)vwgt[v]);
+  } else {
+    moved[v] = 0;
+    reject[v] = 1;
+  }
+}
+// residual capacities r_b = L_max - c(b) - accepted_b > 0, ascending blocks
+__global__ __launch_bounds__(kThreads) void k_residual(Hier h, const int64_t *w,
+                                                       const int64_t *acc, int64_t lmax,
+                                                       int64_t *rstart, int32_t *rblock,
+                                                       Status *st) {
+  __shared__ BlockScratch sc;
+  __shared__ int64_t wave_tot[kThreads / 64];
+  const int32_t ncodes = 1 << h.bits;
+  const int per = (ncodes + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < ncodes ? lo + per : ncodes;
+  uint32_t cnt = 0;
+  int64_t sum = 0;
+  for (int c = lo; c < hi; ++c) {
+    const int64_t r = code_valid(h, (uint32_t)c) ? lmax - w[c] - acc[c] : 0;
+    if (r > 0) {
+      ++cnt;
+      sum += r;
+    }
+  }
+  uint32_t pos = block_excl_scan(cnt, sc);
+  // exclusive scan of the int64 sums
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t incl = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();
+  if (lane == 63) wave_tot[wave] = incl;
+  __syncthreads();
+  int64_t off = 0;
+  for (int i = 0; i < wave; ++i) off += wave_tot[i];
+  int64_t run = off + incl - sum;
+  for (int c = lo; c < hi; ++c) {
+    const int64_t r = code_valid(h, (uint32_t)c) ? lmax - w[c] - acc[c] : 0;
+    if (r > 0) {
+      rstart[pos] = run;
+      rblock[pos] = c;
+      ++pos;
+      run += r;
+    }
+  }
+  if (threadIdx.x == kThreads - 1) {
+    st->count2 = (int32_t)pos;
+    st->resid_total = run;
+  }
+}
+// rejected movers (id order, exclusive weight prefix R) -> residual slots
+__global__ void k_assign_rejects(int32_t m, const int32_t *list, const int64_t *pre,
+                                 const int64_t *rstart, const int32_t *rblock,
+                                 const Status *st, int32_t *target, uint8_t *moved) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int64_t R = pre[i];
+  if (R >= st->resid_total) return;
+  int32_t lo = 0, hi = st->count2 - 1;  // largest j with rstart[j] <= R
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (rstart[mid] <= R) lo = mid;
+    else hi = mid - 1;
+  }
+  const int32_t v = list[i];
+  target[v] = rblock[lo];
+  moved[v] = 1;
+}
+
+void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h,
+                      bool strong, int64_t lmax, int64_t sigma, int64_t total,
+                      uint64_t hseed, const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
+                      const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
+                      hipStream_t s) {
+  const int nwg = classes_workgroups(cl);
+  const int64_t n = g.n;
+  fill_u8(moved, 0, n, s);
+  if (nwg == 0) return;
+  const int64_t cap = strong ? lmax : sigma;
+  hipLaunchKernelGGL(k_reb_eligible, dim3(1), dim3(kThreads), 0, s, h, w, cap, rb.elig, st_dev);
+  PM_LAUNCH_CHECK();
+  RebArgs A{g, cl, h, part, w, lmax, cap, total, hseed, rb.elig, st_dev, rb.key, rb.dest, rb.flag};
+  hipLaunchKernelGGL(k_reb_select, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+  PM_LAUNCH_CHECK();
+  // sources in id order
+  select_indices(ar, rb.flag, rb.list, &st_dev->count, n, s);
+  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  const int32_t ns = st_host->count;
+  if (ns == 0) return;
+  const int kbits = h.bits + 6;
+  hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.list, rb.key,
+                     rb.skey);
+  PM_LAUNCH_CHECK();
+  sort_pairs(ar, rb.skey, rb.skey2, rb.list, rb.list2, ns, kbits, s);
+  scan_excl_gather(ar, rb.list2, g.c, rb.pre, ns, s);
+  hipLaunchKernelGGL(k_seg_starts, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.skey2, rb.seg);
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_select_prefix, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.skey2,
+                     rb.list2, rb.pre, rb.seg, w, lmax, rb.dest, target, moved);
+  PM_LAUNCH_CHECK();
+  if (!strong) return;
+
+  // ---- strong: acceptance per destination ----
+  select_indices(ar, moved, rb.list, &st_dev->count, n, s);
+  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  const int32_t nsel = st_host->count;
+  if (nsel == 0) return;
+  hipLaunchKernelGGL(k_gather_dest_keys, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.list,
+                     rb.key, rb.dest, rb.skey);
+  PM_LAUNCH_CHECK();
+  sort_pairs(ar, rb.skey, rb.skey2, rb.list, rb.list2, nsel, kbits, s);
+  scan_excl_gather(ar, rb.list2, g.c, rb.pre, nsel, s);
+  hipLaunchKernelGGL(k_seg_starts, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.skey2,
+                     rb.seg);
+  PM_LAUNCH_CHECK();
+  fill_i64(rb.acc, 0, (int64_t)1 << h.bits, s);
+  fill_u8(rb.flag, 0, n, s);
+  hipLaunchKernelGGL(k_accept, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.skey2,
+                     rb.list2, rb.pre, rb.seg, w, g.c, lmax, rb.acc, moved, rb.flag);
+  PM_LAUNCH_CHECK();
+  // ---- rejected movers, id order ----
+  select_indices(ar, rb.flag, rb.list, &st_dev->count, n, s);
+  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  PM_HIP(hipStreamSynchronize(s));
+  const int32_t nrej = st_host->count;
+  if (nrej == 0) return;
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kThreads), 0, s, h, w, rb.acc, lmax, rb.rstart,
+                     rb.rblock, st_dev);
+  PM_LAUNCH_CHECK();
+  scan_excl_gather(ar, rb.list, g.c, rb.pre, nrej, s);
+  hipLaunchKernelGGL(k_assign_rejects, dim3(grid_for(nrej)), dim3(kThreads), 0, s, nrej, rb.list,
+                     rb.pre, rb.rstart, rb.rblock, st_dev, target, moved);
+  PM_LAUNCH_CHECK();
+}
+
+}  // namespace pm

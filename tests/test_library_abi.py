@@ -1,0 +1,66 @@
+"""Host-side checks of the C ABI: the library loads and exports every entry
+point that include/pm.h declares (no compute calls: no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "pm.h")
+LIB = os.path.join(ROOT, "paper_2510_12196_amd", "libpm.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path_entry_points():
+    names = declared_functions()
+    for required in ["pm_comm_cost", "pm_refine", "pm_map", "pm_lp_round", "pm_rebalance",
+                     "pm_hem", "pm_contract", "pm_initial_partition", "pm_block_weights",
+                     "pm_strerror", "pm_version", "pm_release"]:
+        assert required in names
+
+
+@pytest.fixture(scope="module")
+def libpm():
+    if not os.path.exists(LIB):
+        import paper_2510_12196_amd.build as b
+        b.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_library_exports_every_declared_symbol(libpm):
+    missing = [n for n in declared_functions() if not hasattr(libpm, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_version_need_no_device(libpm):
+    libpm.pm_strerror.restype = ctypes.c_char_p
+    libpm.pm_version.restype = ctypes.c_char_p
+    assert libpm.pm_strerror(0) == b"ok"
+    assert b"invalid" in libpm.pm_strerror(-1)
+    assert libpm.pm_strerror(12345) == b"unknown error"
+    assert b"gfx950" in libpm.pm_version()
+
+
+def test_struct_layouts_match_header():
+    import paper_2510_12196_amd as pm
+    # pm_graph: int32 n (padded), int64 nnz, four pointers
+    assert ctypes.sizeof(pm.PmGraph) == 8 + 8 + 4 * 8
+    assert ctypes.sizeof(pm.PmHierarchy) == 4 + 8 * 4 + 8 * 4
+    assert ctypes.sizeof(pm.PmRefineStats) == 4 * 8 + 6 * 4 + 8 + 8
+    assert pm.PmMapStats.kernel_bytes.offset == ctypes.sizeof(pm.PmMapStats) - 4 * 8
+    assert pm.PmMapStats.refine_arcs.offset + 8 == pm.PmMapStats.kernel_launches.offset
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2510_12196_amd as pm
+    monkeypatch.setattr(pm, "LIB_PATH", str(tmp_path / "absent.so"))
+    monkeypatch.setattr(pm, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        pm.lib()
