@@ -103,49 +103,53 @@ struct CandScratch {
 
 __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
   __shared__ CandScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
-  switch (cls) {
-    case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
-        A.pref[A.cl.list[A.cl.off[CLS_ISO] + idx]] = -1;
-      break;
-    }
-    case CLS_G8: hem_group<8>(A, cls, local); break;
-    case CLS_G16: hem_group<16>(A, cls, local); break;
-    case CLS_G32: hem_group<32>(A, cls, local); break;
-    case CLS_G64: hem_group<64>(A, cls, local); break;
-    default: {
-      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      if (A.match[v] >= 0) {
-        if (threadIdx.x == 0) A.pref[v] = -1;
+  const int total = A.cl.wg[NCLS];
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: {
+        const int idx = local * kThreads + threadIdx.x;
+        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
+          A.pref[A.cl.list[A.cl.off[CLS_ISO] + idx]] = -1;
         break;
       }
-      const int32_t cv = A.g.c[v];
-      Cand best{-1, 0, 1, 0};
-      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads) {
-        const Cand c = hem_arc(A, v, cv, e);
-        if (cand_better(c, best, v)) best = c;
+      case CLS_G8: hem_group<8>(A, cls, local); break;
+      case CLS_G16: hem_group<16>(A, cls, local); break;
+      case CLS_G32: hem_group<32>(A, cls, local); break;
+      case CLS_G64: hem_group<64>(A, cls, local); break;
+      default: {
+        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+        if (A.match[v] >= 0) {
+          if (threadIdx.x == 0) A.pref[v] = -1;
+          break;
+        }
+        const int32_t cv = A.g.c[v];
+        Cand best{-1, 0, 1, 0};
+        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads) {
+          const Cand c = hem_arc(A, v, cv, e);
+          if (cand_better(c, best, v)) best = c;
+        }
+        cand_reduce<64>(best, v);
+        const int wave = threadIdx.x >> 6;
+        __syncthreads();  // the previous tile's reads of sc are done
+        if ((threadIdx.x & 63) == 0) sc.c[wave] = best;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          Cand bb = sc.c[0];
+          for (int i = 1; i < kThreads / 64; ++i)
+            if (cand_better(sc.c[i], bb, v)) bb = sc.c[i];
+          A.pref[v] = bb.u;
+        }
+        break;
       }
-      cand_reduce<64>(best, v);
-      const int wave = threadIdx.x >> 6;
-      if ((threadIdx.x & 63) == 0) sc.c[wave] = best;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        Cand b = sc.c[0];
-        for (int i = 1; i < kThreads / 64; ++i)
-          if (cand_better(sc.c[i], b, v)) b = sc.c[i];
-        A.pref[v] = b.u;
-      }
-      break;
     }
   }
 }
 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
+  const unsigned nwg = classed_grid(cl);
   if (nwg == 0) return;
   HemArgs A{g, cl, lmax, hseed, match, pref};
   if (tl_timer) {
@@ -159,24 +163,32 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
 }
 
 // v and pref[v] are matched iff they prefer each other.
-__global__ void k_hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool hit = false;
-  if (v < n && match[v] < 0) {
+__global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
+                                                         int32_t *match, int64_t *stripes) {
+  __shared__ BlockScratch sc;
+  int64_t hits = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    if (match[v] >= 0) continue;
     const int32_t u = pref[v];
     if (u >= 0 && pref[u] == (int32_t)v) {
       match[v] = u;
-      hit = true;
+      ++hits;
     }
   }
-  const unsigned long long b = __ballot(hit);
-  if ((threadIdx.x & 63) == 0 && b) atomicAdd(&st->count, (int32_t)__popcll(b));
+  hits = block_sum64(hits, sc);
+  if (threadIdx.x == 0) stripe_add(stripes, hits);
 }
 
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_hem_commit, dim3(grid_for(n)), dim3(kThreads), 0, s, n, pref, match, st);
-  PM_LAUNCH_CHECK();
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes, Status *st,
+                hipStream_t s) {
+  if (n > 0) {
+    unsigned g = grid_for(n);
+    if (g > kMaxGrid) g = kMaxGrid;
+    hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, stripes);
+    PM_LAUNCH_CHECK();
+  }
+  fold_stripes(stripes, nullptr, &st->count, s);
 }
 
 // unmatched vertices without neighbours (they share the empty neighbourhood)
@@ -274,7 +286,7 @@ struct KeyArgs {
   int bits;
   uint64_t *key;
   int32_t *val;
-  Status *st;
+  int64_t *stripes;
 };
 
 __device__ __forceinline__ int32_t key_arc(const KeyArgs &A, uint64_t cv, int64_t e) {
@@ -299,36 +311,40 @@ __device__ __forceinline__ int32_t key_group(const KeyArgs &A, int cls, int loca
 }
 
 __global__ __launch_bounds__(kThreads) void k_contract_keys(KeyArgs A) {
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
-  int32_t self = 0;
-  switch (cls) {
-    case CLS_ISO: break;
-    case CLS_G8: self = key_group<8>(A, cls, local); break;
-    case CLS_G16: self = key_group<16>(A, cls, local); break;
-    case CLS_G32: self = key_group<32>(A, cls, local); break;
-    case CLS_G64: self = key_group<64>(A, cls, local); break;
-    default: {
-      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      const uint64_t cv = (uint64_t)A.cmap[v];
-      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-        self += key_arc(A, cv, e);
-      break;
+  __shared__ BlockScratch sc;
+  const int total = A.cl.wg[NCLS];
+  int64_t self = 0;
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: break;
+      case CLS_G8: self += key_group<8>(A, cls, local); break;
+      case CLS_G16: self += key_group<16>(A, cls, local); break;
+      case CLS_G32: self += key_group<32>(A, cls, local); break;
+      case CLS_G64: self += key_group<64>(A, cls, local); break;
+      default: {
+        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+        const uint64_t cv = (uint64_t)A.cmap[v];
+        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+          self += key_arc(A, cv, e);
+        break;
+      }
     }
   }
-  // per-lane counts may exceed one in the big class: reduce through a wave sum
-  int32_t x = self;
-  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, 64);
-  if ((threadIdx.x & 63) == 0 && x) atomicAdd(&A.st->count, x);
+  self = block_sum64(self, sc);
+  if (threadIdx.x == 0) stripe_add(A.stripes, self);
 }
 
 void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int bits,
-                   uint64_t *key, int32_t *val, Status *st, hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
-  if (nwg == 0) return;
-  KeyArgs A{g, cl, cmap, bits, key, val, st};
-  hipLaunchKernelGGL(k_contract_keys, dim3(nwg), dim3(kThreads), 0, s, A);
-  PM_LAUNCH_CHECK();
+                   uint64_t *key, int32_t *val, int64_t *stripes, Status *st, hipStream_t s) {
+  const unsigned nwg = classed_grid(cl);
+  if (nwg > 0) {
+    KeyArgs A{g, cl, cmap, bits, key, val, stripes};
+    hipLaunchKernelGGL(k_contract_keys, dim3(nwg), dim3(kThreads), 0, s, A);
+    PM_LAUNCH_CHECK();
+  }
+  fold_stripes(stripes, nullptr, &st->count, s);
 }
 
 __global__ void k_contract_heads(int64_t m, const uint64_t *key, int32_t *head) {

@@ -119,7 +119,23 @@ __device__ __forceinline__ void block_scan_lds(uint32_t *a, int m, BlockScratch 
   __syncthreads();
 }
 
+// ---- striped accumulators ---------------------------------------------------
+// A global sum updated by thousands of workgroups is spread over kStripes
+// counters one cache line apart (atomics on a single address serialise);
+// fold_stripes() adds them up afterwards and clears them.
+constexpr int kStripes = 256;
+constexpr int kStripeStride = 16;  // int64 words: 128 bytes
+constexpr int kStripeWords = kStripes * kStripeStride;
+__device__ __forceinline__ void stripe_add(int64_t *stripes, int64_t x) {
+  if (x != 0)
+    atomicAdd((unsigned long long *)&stripes[(blockIdx.x & (kStripes - 1)) * kStripeStride],
+              (unsigned long long)x);
+}
+
 // ---- classed launches --------------------------------------------------------
+// Classed kernels run a capped grid; every workgroup walks the class tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...
+constexpr int kMaxGrid = 2048;
 __device__ __forceinline__ int find_class(const Classes &cl, int b) {
   int c = 0;
   while (c < NCLS - 1 && b >= cl.wg[c + 1]) ++c;

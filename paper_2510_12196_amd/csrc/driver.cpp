@@ -73,10 +73,14 @@ struct Ctx {
   hipStream_t s;
   Status *dev;
   Status *host;
+  Stripes sp;
   explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
     dev = ar.alloc_n<Status>(1);
     host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
+    sp.a = ar.alloc_n<int64_t>(2 * (size_t)stripe_words());
+    sp.b = sp.a + stripe_words();
     PM_HIP(hipMemsetAsync(dev, 0, sizeof(Status), s));
+    PM_HIP(hipMemsetAsync(sp.a, 0, sizeof(int64_t) * 2 * (size_t)stripe_words(), s));
   }
   void pull() {
     PM_HIP(hipMemcpyAsync(host, dev, sizeof(Status), hipMemcpyDeviceToHost, s));
@@ -134,8 +138,8 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   if (n > 0) PM_HIP(hipMemcpyAsync(cur, best, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
   fill_u8(lock, 0, n, s);
   block_weights(g, h, cur, w, s);
-  comm_cost(g, cl, h, cur, cx.dev, s);
-  max_block(h, w, cx.dev, s);
+  comm_cost(g, cl, h, cur, cx.sp.a, cx.dev, s);
+  max_block(h, w, nullptr, cx.dev, s);
   cx.pull();
   int64_t j_cur = cx.host->j, imb_cur = cx.host->maxw;
   if (n == 0) imb_cur = 0;
@@ -151,19 +155,18 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   while (i < 12 && bodies < 4096) {
     ++i;
     ++bodies;
-    PM_HIP(hipMemsetAsync(&cx.dev->dj, 0, sizeof(int64_t), s));
     if (imb_cur <= lmax) {
       lp_phase1(g, cl, h, cur, lock, target, gain, s);
       lp_phase2(g, cl, h, cur, target, gain, moved, s);
-      apply_moves(g, cl, h, cur, target, moved, lock, w, cx.dev, s);
+      apply_moves(g, cl, h, cur, target, moved, lock, w, cx.sp.a, s);
       iw = 0;
       ++R.st.lp_iterations;
     } else {
       const bool strong = iw >= 2;
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
       rebalance_select(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
-                       cx.dev, cx.host, s);
-      apply_moves(g, cl, h, cur, target, moved, nullptr, w, cx.dev, s);
+                       cx.dev, cx.host, cx.sp, s);
+      apply_moves(g, cl, h, cur, target, moved, nullptr, w, cx.sp.a, s);
       if (strong) {
         iw = 0;
         ++R.st.strong_iterations;
@@ -172,7 +175,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         ++R.st.weak_iterations;
       }
     }
-    max_block(h, w, cx.dev, s);
+    max_block(h, w, cx.sp.a, cx.dev, s);
     cx.pull();
     j_cur += cx.host->dj;
     imb_cur = cx.host->maxw;
@@ -242,9 +245,8 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   int64_t matched = 0;
   while (rounds < 64) {
     ++rounds;
-    PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), s));
     hem_prefer(g, L.cl, lmax, hseed, match, pref, s);
-    hem_commit(g.n, pref, match, cx.dev, s);
+    hem_commit(g.n, pref, match, cx.sp.b, cx.dev, s);
     cx.pull();
     const int32_t added = cx.host->count;
     matched += added;
@@ -279,8 +281,7 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
   uint64_t *key2 = ar.alloc_n<uint64_t>(nnz);
   int32_t *val = ar.alloc_n<int32_t>(nnz);
   int32_t *val2 = ar.alloc_n<int32_t>(nnz);
-  PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), s));
-  contract_keys(g, L.cl, cmap, bits, key, val, cx.dev, s);
+  contract_keys(g, L.cl, cmap, bits, key, val, cx.sp.b, cx.dev, s);
   sort_pairs(ar, key, key2, val, val2, nnz, 2 * bits, s);
   cx.pull();
   const int64_t mvalid = nnz - cx.host->count;
@@ -367,8 +368,7 @@ void check_device() {
 
 // Rejects mappings with ids outside [0,k): block ids index device arrays.
 void require_ids(Ctx &cx, const Hier &h, const int32_t *part, int32_t n) {
-  PM_HIP(hipMemsetAsync(&cx.dev->count, 0, sizeof(int32_t), cx.s));
-  check_ids(h, part, n, cx.dev, cx.s);
+  check_ids(h, part, n, cx.sp.b, cx.dev, cx.s);
   cx.pull();
   if (cx.host->count) throw Error(PM_EINVAL, "mapping holds ids outside [0,k)");
 }
@@ -415,7 +415,7 @@ int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part, 
     }
     int32_t *list = lease->alloc_n<int32_t>(dg.n);
     Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
-    comm_cost(dg, cl, hh, codes, cx.dev, s);
+    comm_cost(dg, cl, hh, codes, cx.sp.a, cx.dev, s);
     cx.pull();
     *j_out = cx.host->j;
     return PM_OK;
@@ -470,7 +470,7 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t
     block_weights(dg, hh, codes, w, s);
     lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s);
     lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
-    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w, cx.dev, s);
+    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w, cx.sp.a, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     codes_to_ids(hh, target_out, target_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
@@ -519,8 +519,8 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
     rebalance_select(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
-                     moved_out, rb, cx.dev, cx.host, s);
-    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, cx.dev, s);
+                     moved_out, rb, cx.dev, cx.host, cx.sp, s);
+    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, cx.sp.a, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;

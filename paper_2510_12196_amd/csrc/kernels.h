@@ -17,6 +17,17 @@ struct Status {
   int64_t resid_total; // strong rebalancing: total residual capacity
 };
 
+// Striped accumulator buffers of one call (kStripes x 16 int64 each, zeroed
+// at creation and by every fold).
+struct Stripes {
+  int64_t *a;   // sums of J / J changes
+  int64_t *b;   // counts
+};
+// Adds up the stripes into *out64 (if non-null) or *out32, clears them.
+void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s);
+int stripe_words();
+unsigned classed_grid(const Classes &cl);
+
 // ---- optional per-launch kernel timing --------------------------------------
 enum { KT_LP1 = 0, KT_LP2, KT_APPLY, KT_HEM, NKT };
 struct KernelTimer {
@@ -42,14 +53,16 @@ int32_t classes_workgroups(const Classes &cl);
 void ids_to_codes(const Hier &h, const int32_t *ids, int32_t *codes, int32_t n, hipStream_t s);
 void codes_to_ids(const Hier &h, const int32_t *codes, int32_t *ids, int32_t n, hipStream_t s);
 // flags any id outside [0,k) into st->count
-void check_ids(const Hier &h, const int32_t *ids, int32_t n, Status *st, hipStream_t s);
+void check_ids(const Hier &h, const int32_t *ids, int32_t n, int64_t *stripes, Status *st,
+               hipStream_t s);
 
 // ---- objective and balance ------------------------------------------------
 void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               Status *st, hipStream_t s);             // st->j = J
+               int64_t *stripes, Status *st, hipStream_t s);   // st->j = J
 void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
                    hipStream_t s);                     // w[0..2^bits)
-void max_block(const Hier &h, const int64_t *w, Status *st, hipStream_t s);  // st->maxw
+// st->maxw = heaviest block; if dj_stripes, also folds them into st->dj
+void max_block(const Hier &h, const int64_t *w, int64_t *dj_stripes, Status *st, hipStream_t s);
 
 // ---- label propagation (Algorithm 4) --------------------------------------
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
@@ -57,10 +70,11 @@ void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
-// st->dj and the block weight changes into w; sets lock = moved if lock != 0.
+// dj_stripes and the block weight changes into w; sets lock = moved if lock
+// != 0.
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 Status *st, hipStream_t s);
+                 int64_t *dj_stripes, hipStream_t s);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
 struct RebalanceBuffers {
@@ -85,12 +99,13 @@ void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier 
                       uint64_t hseed, const int32_t *part, const int64_t *w,
                       int32_t *target, uint8_t *moved,
                       const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
-                      hipStream_t s);
+                      const Stripes &sp, hipStream_t s);
 
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s);
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, Status *st, hipStream_t s);
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes, Status *st,
+                hipStream_t s);   // st->count = new matches
 void hem_isolated_flags(const DGraph &g, const int32_t *match, uint8_t *flag, hipStream_t s);
 void hem_pair_isolated(const int32_t *iso, int32_t niso, const int32_t *vwgt, int64_t lmax,
                        int32_t *match, hipStream_t s);
@@ -100,7 +115,8 @@ void coarse_ids(int32_t n, const int32_t *match, const int32_t *rank, int32_t *c
 void coarse_vwgt(int32_t n, const int32_t *match, const int32_t *cmap, const int32_t *vwgt,
                  int32_t *cvwgt, hipStream_t s);
 void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int bits,
-                   uint64_t *key, int32_t *val, Status *st, hipStream_t s);
+                   uint64_t *key, int32_t *val, int64_t *stripes, Status *st,
+                   hipStream_t s);   // st->count = arcs inside coarse vertices
 void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s);
 void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,
                    const int32_t *pos, int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt,

@@ -108,9 +108,14 @@ __global__ void k_codes_to_ids(Hier h, const int32_t *codes, int32_t *ids, int32
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) ids[i] = code_to_id(h, (uint32_t)codes[i]);
 }
-__global__ void k_check_ids(int64_t k, const int32_t *ids, int32_t n, Status *st) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n && (ids[i] < 0 || (int64_t)ids[i] >= k)) atomicAdd(&st->count, 1);
+__global__ void k_check_ids(int64_t k, const int32_t *ids, int32_t n, int64_t *stripes) {
+  __shared__ BlockScratch sc;
+  int64_t bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad += (ids[i] < 0 || (int64_t)ids[i] >= k) ? 1 : 0;
+  bad = block_sum64(bad, sc);
+  if (threadIdx.x == 0) stripe_add(stripes, bad);
 }
 
 void ids_to_codes(const Hier &h, const int32_t *ids, int32_t *codes, int32_t n, hipStream_t s) {
@@ -133,10 +138,41 @@ void codes_to_ids(const Hier &h, const int32_t *codes, int32_t *ids, int32_t n, 
   hipLaunchKernelGGL(k_codes_to_ids, dim3(grid_for(n)), dim3(kThreads), 0, s, h, codes, ids, n);
   PM_LAUNCH_CHECK();
 }
-void check_ids(const Hier &h, const int32_t *ids, int32_t n, Status *st, hipStream_t s) {
-  if (n <= 0) return;
-  hipLaunchKernelGGL(k_check_ids, dim3(grid_for(n)), dim3(kThreads), 0, s, h.k, ids, n, st);
+void check_ids(const Hier &h, const int32_t *ids, int32_t n, int64_t *stripes, Status *st,
+               hipStream_t s) {
+  unsigned g = grid_for(n);
+  if (g > kMaxGrid) g = kMaxGrid;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_check_ids, dim3(g), dim3(kThreads), 0, s, h.k, ids, n, stripes);
+    PM_LAUNCH_CHECK();
+  }
+  fold_stripes(stripes, nullptr, &st->count, s);
+}
+
+// ===========================================================================
+// striped accumulators
+// ===========================================================================
+__global__ __launch_bounds__(kThreads) void k_fold(int64_t *stripes, int64_t *out64,
+                                                   int32_t *out32) {
+  __shared__ BlockScratch sc;
+  int64_t x = stripes[threadIdx.x * kStripeStride];
+  stripes[threadIdx.x * kStripeStride] = 0;
+  x = block_sum64(x, sc);
+  if (threadIdx.x == 0) {
+    if (out64) *out64 = x;
+    else *out32 = (int32_t)x;
+  }
+}
+static_assert(kStripes == kThreads, "one stripe per thread in k_fold");
+
+void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s) {
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kThreads), 0, s, stripes, out64, out32);
   PM_LAUNCH_CHECK();
+}
+int stripe_words() { return kStripeWords; }
+unsigned classed_grid(const Classes &cl) {
+  const int t = cl.wg[NCLS];
+  return (unsigned)(t < kMaxGrid ? t : kMaxGrid);
 }
 
 // ===========================================================================
@@ -147,7 +183,7 @@ struct CostArgs {
   Classes cl;
   Hier h;
   const int32_t *part;
-  Status *st;
+  int64_t *stripes;
 };
 
 template <int G>
@@ -162,35 +198,39 @@ __device__ __forceinline__ int64_t cost_group(const CostArgs &A, int cls, int lo
 
 __global__ __launch_bounds__(kThreads) void k_comm_cost(CostArgs A) {
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
+  const int total = A.cl.wg[NCLS];
   int64_t x = 0;
-  switch (cls) {
-    case CLS_G8: x = cost_group<8>(A, cls, local); break;
-    case CLS_G16: x = cost_group<16>(A, cls, local); break;
-    case CLS_G32: x = cost_group<32>(A, cls, local); break;
-    case CLS_G64: x = cost_group<64>(A, cls, local); break;
-    case CLS_BIG: {
-      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      const uint32_t p = (uint32_t)A.part[v];
-      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-        x += (int64_t)A.g.w[e] * dist(A.h, p, (uint32_t)A.part[A.g.adj[e]]);
-      break;
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_G8: x += cost_group<8>(A, cls, local); break;
+      case CLS_G16: x += cost_group<16>(A, cls, local); break;
+      case CLS_G32: x += cost_group<32>(A, cls, local); break;
+      case CLS_G64: x += cost_group<64>(A, cls, local); break;
+      case CLS_BIG: {
+        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+        const uint32_t p = (uint32_t)A.part[v];
+        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+          x += (int64_t)A.g.w[e] * dist(A.h, p, (uint32_t)A.part[A.g.adj[e]]);
+        break;
+      }
+      default: break;
     }
-    default: break;
   }
   x = block_sum64(x, sc);
-  if (threadIdx.x == 0 && x != 0) atomicAdd((unsigned long long *)&A.st->j, (unsigned long long)x);
+  if (threadIdx.x == 0) stripe_add(A.stripes, x);
 }
 
 void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               Status *st, hipStream_t s) {
-  PM_HIP(hipMemsetAsync(&st->j, 0, sizeof(int64_t), s));
-  const int nwg = classes_workgroups(cl);
-  if (nwg == 0) return;
-  CostArgs A{g, cl, h, part, st};
-  hipLaunchKernelGGL(k_comm_cost, dim3(nwg), dim3(kThreads), 0, s, A);
-  PM_LAUNCH_CHECK();
+               int64_t *stripes, Status *st, hipStream_t s) {
+  const unsigned grid = classed_grid(cl);
+  if (grid > 0) {
+    CostArgs A{g, cl, h, part, stripes};
+    hipLaunchKernelGGL(k_comm_cost, dim3(grid), dim3(kThreads), 0, s, A);
+    PM_LAUNCH_CHECK();
+  }
+  fold_stripes(stripes, &st->j, nullptr, s);
 }
 
 // ===========================================================================
@@ -223,17 +263,24 @@ void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t 
 }
 
 __global__ __launch_bounds__(kThreads) void k_max_block(const int64_t *w, int32_t ncodes,
-                                                        Status *st) {
+                                                        int64_t *dj_stripes, Status *st) {
   __shared__ BlockScratch sc;
   int64_t m = INT64_MIN;
   for (int c = threadIdx.x; c < ncodes; c += kThreads) m = w[c] > m ? w[c] : m;
   uint32_t dummy = 0;
   block_argmax(m, dummy, sc);
   if (threadIdx.x == 0) st->maxw = m;
+  if (dj_stripes) {
+    int64_t x = dj_stripes[threadIdx.x * kStripeStride];
+    dj_stripes[threadIdx.x * kStripeStride] = 0;
+    x = block_sum64(x, sc);
+    if (threadIdx.x == 0) st->dj = x;
+  }
 }
 
-void max_block(const Hier &h, const int64_t *w, Status *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_max_block, dim3(1), dim3(kThreads), 0, s, w, (int32_t)(1 << h.bits), st);
+void max_block(const Hier &h, const int64_t *w, int64_t *dj_stripes, Status *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_block, dim3(1), dim3(kThreads), 0, s, w, (int32_t)(1 << h.bits),
+                     dj_stripes, st);
   PM_LAUNCH_CHECK();
 }
 
@@ -327,6 +374,7 @@ __device__ __forceinline__ int64_t level_cost(const Hier &h, const uint32_t *X, 
 // Builds X[0..ncodes] = exclusive prefix of conn(v, .) in LDS.
 __device__ __forceinline__ void big_histogram(const DGraph &g, const int32_t *part, int32_t v,
                                               uint32_t *X, int32_t ncodes, BlockScratch &sc) {
+  __syncthreads();  // every wave is done reading the previous vertex's histogram
   for (int c = threadIdx.x; c <= ncodes; c += kThreads) X[c] = 0;
   __syncthreads();
   for (int64_t e = g.xadj[v] + threadIdx.x; e < g.xadj[v + 1]; e += kThreads)
@@ -383,23 +431,26 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X
 __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
-  switch (cls) {
-    case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
-        A.target[v] = A.part[v];
-        A.gain[v] = kNotInX;
+  const int total = A.cl.wg[NCLS];
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: {
+        const int idx = local * kThreads + threadIdx.x;
+        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+          A.target[v] = A.part[v];
+          A.gain[v] = kNotInX;
+        }
+        break;
       }
-      break;
+      case CLS_G8: lp1_group<8>(A, cls, local); break;
+      case CLS_G16: lp1_group<16>(A, cls, local); break;
+      case CLS_G32: lp1_group<32>(A, cls, local); break;
+      case CLS_G64: lp1_group<64>(A, cls, local); break;
+      default: lp1_big(A, local, X, sc); break;
     }
-    case CLS_G8: lp1_group<8>(A, cls, local); break;
-    case CLS_G16: lp1_group<16>(A, cls, local); break;
-    case CLS_G32: lp1_group<32>(A, cls, local); break;
-    case CLS_G64: lp1_group<64>(A, cls, local); break;
-    default: lp1_big(A, local, X, sc); break;
   }
 }
 
@@ -407,7 +458,7 @@ static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << 
 
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
+  const unsigned nwg = classed_grid(cl);
   if (nwg == 0) return;
   LP1Args A{g, cl, h, part, lock, target, gain};
   if (tl_timer) {
@@ -466,40 +517,43 @@ __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) 
 
 __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
-  switch (cls) {
-    case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
-        A.moved[A.cl.list[A.cl.off[CLS_ISO] + idx]] = 0;
-      break;
-    }
-    case CLS_G8: lp2_group<8>(A, cls, local); break;
-    case CLS_G16: lp2_group<16>(A, cls, local); break;
-    case CLS_G32: lp2_group<32>(A, cls, local); break;
-    case CLS_G64: lp2_group<64>(A, cls, local); break;
-    default: {
-      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      const int64_t gv = A.gain[v];
-      if (gv == kNotInX) {
-        if (threadIdx.x == 0) A.moved[v] = 0;
+  const int total = A.cl.wg[NCLS];
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: {
+        const int idx = local * kThreads + threadIdx.x;
+        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
+          A.moved[A.cl.list[A.cl.off[CLS_ISO] + idx]] = 0;
         break;
       }
-      const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-      int64_t x = 0;
-      for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-        x += lp2_arc(A, v, gv, p, t, e);
-      x = block_sum64(x, sc);
-      if (threadIdx.x == 0) A.moved[v] = x >= 0 ? 1 : 0;
-      break;
+      case CLS_G8: lp2_group<8>(A, cls, local); break;
+      case CLS_G16: lp2_group<16>(A, cls, local); break;
+      case CLS_G32: lp2_group<32>(A, cls, local); break;
+      case CLS_G64: lp2_group<64>(A, cls, local); break;
+      default: {
+        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+        const int64_t gv = A.gain[v];
+        if (gv == kNotInX) {
+          if (threadIdx.x == 0) A.moved[v] = 0;
+          break;
+        }
+        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+        int64_t x = 0;
+        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+          x += lp2_arc(A, v, gv, p, t, e);
+        x = block_sum64(x, sc);
+        if (threadIdx.x == 0) A.moved[v] = x >= 0 ? 1 : 0;
+        break;
+      }
     }
   }
 }
 
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
+  const unsigned nwg = classed_grid(cl);
   if (nwg == 0) return;
   LP2Args A{g, cl, h, part, target, gain, moved};
   if (tl_timer) {
@@ -531,7 +585,7 @@ struct ApplyArgs {
   const uint8_t *moved;
   uint8_t *lock;
   int64_t *w;
-  Status *st;
+  int64_t *dj;
 };
 
 __device__ __forceinline__ int64_t apply_arc(const ApplyArgs &A, uint32_t p, uint32_t t,
@@ -545,15 +599,17 @@ __device__ __forceinline__ int64_t apply_arc(const ApplyArgs &A, uint32_t p, uin
   return 2 * (int64_t)A.g.w[e] * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
 }
 
+// block weight deltas go to the workgroup's LDS copy first
 __device__ __forceinline__ void apply_weights(const ApplyArgs &A, int32_t v, uint32_t p,
-                                              uint32_t t) {
-  const unsigned long long c = (unsigned long long)(int64_t)A.g.c[v];
-  atomicAdd((unsigned long long *)&A.w[t], c);
-  atomicAdd((unsigned long long *)&A.w[p], (unsigned long long)(-(int64_t)c));
+                                              uint32_t t, int32_t *dw) {
+  const int32_t c = A.g.c[v];
+  atomicAdd(&dw[t], c);
+  atomicAdd(&dw[p], -c);
 }
 
 template <int G>
-__device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local) {
+__device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local,
+                                               int32_t *dw) {
   int32_t v;
   if (!group_vertex<G>(A.cl, cls, local, v)) return 0;
   const int lane = threadIdx.x % G;
@@ -561,47 +617,55 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
   if (A.lock && lane == 0) A.lock[v] = m;
   if (!m) return 0;
   const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-  if (lane == 0) apply_weights(A, v, p, t);
+  if (lane == 0) apply_weights(A, v, p, t, dw);
   const int64_t e = A.g.xadj[v] + lane;
   return e < A.g.xadj[v + 1] ? apply_arc(A, p, t, e) : 0;
 }
 
 __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
+  extern __shared__ int32_t dw[];
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
+  const int32_t ncodes = 1 << A.h.bits;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) dw[c] = 0;
+  __syncthreads();
+  const int total = A.cl.wg[NCLS];
   int64_t x = 0;
-  switch (cls) {
-    case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: {
+        const int idx = local * kThreads + threadIdx.x;
+        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+          const uint8_t m = A.moved[v];
+          if (A.lock) A.lock[v] = m;
+          if (m) apply_weights(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v], dw);
+        }
+        break;
+      }
+      case CLS_G8: x += apply_group<8>(A, cls, local, dw); break;
+      case CLS_G16: x += apply_group<16>(A, cls, local, dw); break;
+      case CLS_G32: x += apply_group<32>(A, cls, local, dw); break;
+      case CLS_G64: x += apply_group<64>(A, cls, local, dw); break;
+      default: {
+        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint8_t m = A.moved[v];
-        if (A.lock) A.lock[v] = m;
-        if (m) apply_weights(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v]);
+        if (A.lock && threadIdx.x == 0) A.lock[v] = m;
+        if (m) {
+          const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+          if (threadIdx.x == 0) apply_weights(A, v, p, t, dw);
+          for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
+            x += apply_arc(A, p, t, e);
+        }
+        break;
       }
-      break;
-    }
-    case CLS_G8: x = apply_group<8>(A, cls, local); break;
-    case CLS_G16: x = apply_group<16>(A, cls, local); break;
-    case CLS_G32: x = apply_group<32>(A, cls, local); break;
-    case CLS_G64: x = apply_group<64>(A, cls, local); break;
-    default: {
-      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      const uint8_t m = A.moved[v];
-      if (A.lock && threadIdx.x == 0) A.lock[v] = m;
-      if (m) {
-        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-        if (threadIdx.x == 0) apply_weights(A, v, p, t);
-        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-          x += apply_arc(A, p, t, e);
-      }
-      break;
     }
   }
-  x = block_sum64(x, sc);
-  if (threadIdx.x == 0 && x != 0)
-    atomicAdd((unsigned long long *)&A.st->dj, (unsigned long long)x);
+  x = block_sum64(x, sc);  // also orders the LDS weight deltas before the flush
+  if (threadIdx.x == 0) stripe_add(A.dj, x);
+  for (int c = threadIdx.x; c < ncodes; c += kThreads)
+    if (dw[c]) atomicAdd((unsigned long long *)&A.w[c], (unsigned long long)(int64_t)dw[c]);
 }
 
 __global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const uint8_t *moved) {
@@ -611,16 +675,17 @@ __global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const 
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 Status *st, hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
+                 int64_t *dj_stripes, hipStream_t s) {
+  const unsigned nwg = classed_grid(cl);
   if (nwg == 0) return;
-  ApplyArgs A{g, cl, h, part, target, moved, lock, w, st};
+  ApplyArgs A{g, cl, h, part, target, moved, lock, w, dj_stripes};
+  const size_t lds = sizeof(int32_t) * ((size_t)1 << h.bits);
   if (tl_timer) {
     hipEvent_t a, b;
     tl_timer->pair(KT_APPLY, a, b);
-    hipExtLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+    hipExtLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
   } else {
-    hipLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), 0, s, A);
+    hipLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), lds, s, A);
   }
   PM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
@@ -755,24 +820,27 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
-  switch (cls) {
-    case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
-        const uint32_t p = (uint32_t)A.part[v];
-        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
-        else reb_not_source(A, v);
+  const int total = A.cl.wg[NCLS];
+  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+    const int cls = find_class(A.cl, blk);
+    const int local = blk - A.cl.wg[cls];
+    switch (cls) {
+      case CLS_ISO: {
+        const int idx = local * kThreads + threadIdx.x;
+        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+          const uint32_t p = (uint32_t)A.part[v];
+          if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
+          else reb_not_source(A, v);
+        }
+        break;
       }
-      break;
+      case CLS_G8: reb_group<8>(A, cls, local); break;
+      case CLS_G16: reb_group<16>(A, cls, local); break;
+      case CLS_G32: reb_group<32>(A, cls, local); break;
+      case CLS_G64: reb_group<64>(A, cls, local); break;
+      default: reb_big(A, local, X, sc); break;
     }
-    case CLS_G8: reb_group<8>(A, cls, local); break;
-    case CLS_G16: reb_group<16>(A, cls, local); break;
-    case CLS_G32: reb_group<32>(A, cls, local); break;
-    case CLS_G64: reb_group<64>(A, cls, local); break;
-    default: reb_big(A, local, X, sc); break;
   }
 }
 
@@ -911,8 +979,9 @@ void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier 
                       bool strong, int64_t lmax, int64_t sigma, int64_t total,
                       uint64_t hseed, const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
                       const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
-                      hipStream_t s) {
-  const int nwg = classes_workgroups(cl);
+                      const Stripes &sp, hipStream_t s) {
+  (void)sp;
+  const unsigned nwg = classed_grid(cl);
   const int64_t n = g.n;
   fill_u8(moved, 0, n, s);
   if (nwg == 0) return;

@@ -30,17 +30,15 @@ __global__ void k_check_weights(DGraph g, Checks *c) {
     if (x <= 0) ++be;
     else es += (unsigned long long)x;
   }
-  for (int m = 32; m > 0; m >>= 1) {
-    vs += (unsigned long long)__shfl_xor((long long)vs, m, 64);
-    es += (unsigned long long)__shfl_xor((long long)es, m, 64);
-    bv += __shfl_xor(bv, m, 64);
-    be += __shfl_xor(be, m, 64);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    if (vs) atomicAdd(&c->vsum, vs);
-    if (es) atomicAdd(&c->esum, es);
-    if (bv) atomicAdd(&c->bad_vwgt, bv);
-    if (be) atomicAdd(&c->bad_ewgt, be);
+  __shared__ BlockScratch sc;
+  const int64_t tv = block_sum64((int64_t)vs, sc);
+  const int64_t te = block_sum64((int64_t)es, sc);
+  const int64_t tb = block_sum64((int64_t)bv + ((int64_t)be << 32), sc);
+  if (threadIdx.x == 0) {
+    if (tv) atomicAdd(&c->vsum, (unsigned long long)tv);
+    if (te) atomicAdd(&c->esum, (unsigned long long)te);
+    if (tb & 0xffffffffll) atomicAdd(&c->bad_vwgt, (int32_t)(tb & 0xffffffffll));
+    if (tb >> 32) atomicAdd(&c->bad_ewgt, (int32_t)(tb >> 32));
   }
 }
 
@@ -80,7 +78,7 @@ void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, 
   const int64_t big = g.n > g.nnz ? g.n : g.nnz;
   unsigned grid = (unsigned)((big + kThreads - 1) / kThreads);
   if (grid < 1) grid = 1;
-  if (grid > 2048) grid = 2048;
+  if (grid > 512) grid = 512;
   if (g.n > 0 || g.nnz > 0) {
     hipLaunchKernelGGL(k_check_weights, dim3(grid), dim3(kThreads), 0, s, g, c);
     PM_LAUNCH_CHECK();
