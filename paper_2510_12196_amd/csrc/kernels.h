@@ -26,7 +26,8 @@ struct Stripes {
 // Adds up the stripes into *out64 (if non-null) or *out32, clears them.
 void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s);
 int stripe_words();
-unsigned classed_grid(const Classes &cl);
+unsigned classed_grid(const Classes &cl);   // one tile per workgroup
+unsigned capped_grid(const Classes &cl);    // at most kMaxGrid workgroups
 
 // ---- optional per-launch kernel timing --------------------------------------
 enum { KT_LP1 = 0, KT_LP2, KT_APPLY, KT_HEM, NKT };

@@ -170,7 +170,11 @@ void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t 
   PM_LAUNCH_CHECK();
 }
 int stripe_words() { return kStripeWords; }
-unsigned classed_grid(const Classes &cl) {
+// One class tile per workgroup: the hardware dispatcher balances the
+// tiles across the chip better than a fixed grid-stride assignment (the
+// kernels still loop, so a capped grid stays correct).
+unsigned classed_grid(const Classes &cl) { return (unsigned)cl.wg[NCLS]; }
+unsigned capped_grid(const Classes &cl) {
   const int t = cl.wg[NCLS];
   return (unsigned)(t < kMaxGrid ? t : kMaxGrid);
 }
@@ -676,7 +680,8 @@ __global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
                  int64_t *dj_stripes, hipStream_t s) {
-  const unsigned nwg = classed_grid(cl);
+  // capped: every workgroup flushes its LDS block-weight deltas once
+  const unsigned nwg = capped_grid(cl);
   if (nwg == 0) return;
   ApplyArgs A{g, cl, h, part, target, moved, lock, w, dj_stripes};
   const size_t lds = sizeof(int32_t) * ((size_t)1 << h.bits);
