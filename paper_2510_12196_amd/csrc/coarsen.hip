@@ -103,8 +103,8 @@ struct CandScratch {
 
 __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
   __shared__ CandScratch sc;
-  const int total = A.cl.wg[NCLS];
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+  {  // one class tile per workgroup
+    const int blk = blockIdx.x;
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
@@ -312,9 +312,9 @@ __device__ __forceinline__ int32_t key_group(const KeyArgs &A, int cls, int loca
 
 __global__ __launch_bounds__(kThreads) void k_contract_keys(KeyArgs A) {
   __shared__ BlockScratch sc;
-  const int total = A.cl.wg[NCLS];
   int64_t self = 0;
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+  {  // one class tile per workgroup
+    const int blk = blockIdx.x;
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {

@@ -115,20 +115,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   uint8_t *moved = ar.alloc_n<uint8_t>(n);
   uint8_t *lock = ar.alloc_n<uint8_t>(n);
   int64_t *w = ar.alloc_n<int64_t>(ncodes);
-  RebalanceBuffers rb;
-  rb.key = ar.alloc_n<int32_t>(n);
-  rb.dest = ar.alloc_n<int32_t>(n);
-  rb.flag = ar.alloc_n<uint8_t>(n);
-  rb.list = ar.alloc_n<int32_t>(n);
-  rb.list2 = ar.alloc_n<int32_t>(n);
-  rb.skey = ar.alloc_n<uint32_t>(n);
-  rb.skey2 = ar.alloc_n<uint32_t>(n);
-  rb.pre = ar.alloc_n<int64_t>(n);
-  rb.seg = ar.alloc_n<int32_t>(ncodes);
-  rb.elig = ar.alloc_n<int32_t>(ncodes);
-  rb.acc = ar.alloc_n<int64_t>(ncodes);
-  rb.rstart = ar.alloc_n<int64_t>(ncodes);
-  rb.rblock = ar.alloc_n<int32_t>(ncodes);
+  RebalanceBuffers rb = alloc_rebalance(ar, n, h, s);
 
   hipEvent_t ev0, ev1;
   PM_HIP(hipEventCreate(&ev0));
@@ -164,8 +151,8 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     } else {
       const bool strong = iw >= 2;
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
-      rebalance_select(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
-                       cx.dev, cx.host, cx.sp, s);
+      rebalance_round(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
+                      cx.dev, s);
       apply_moves(g, cl, h, cur, target, moved, nullptr, w, cx.sp.a, s);
       if (strong) {
         iw = 0;
@@ -501,25 +488,12 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
     Classes cl = build_classes(ar, dg, list, cx.dev, cx.host, s);
     int64_t *w = ar.alloc_n<int64_t>(ncodes);
     int32_t *target = ar.alloc_n<int32_t>(n);
-    RebalanceBuffers rb;
-    rb.key = ar.alloc_n<int32_t>(n);
-    rb.dest = ar.alloc_n<int32_t>(n);
-    rb.flag = ar.alloc_n<uint8_t>(n);
-    rb.list = ar.alloc_n<int32_t>(n);
-    rb.list2 = ar.alloc_n<int32_t>(n);
-    rb.skey = ar.alloc_n<uint32_t>(n);
-    rb.skey2 = ar.alloc_n<uint32_t>(n);
-    rb.pre = ar.alloc_n<int64_t>(n);
-    rb.seg = ar.alloc_n<int32_t>(ncodes);
-    rb.elig = ar.alloc_n<int32_t>(ncodes);
-    rb.acc = ar.alloc_n<int64_t>(ncodes);
-    rb.rstart = ar.alloc_n<int64_t>(ncodes);
-    rb.rblock = ar.alloc_n<int32_t>(ncodes);
+    RebalanceBuffers rb = alloc_rebalance(ar, n, hh, s);
     block_weights(dg, hh, codes, w, s);
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
-    rebalance_select(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
-                     moved_out, rb, cx.dev, cx.host, cx.sp, s);
+    rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
+                    moved_out, rb, cx.dev, s);
     apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, cx.sp.a, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));

@@ -81,26 +81,28 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
 struct RebalanceBuffers {
   int32_t *key;        // n: (block << 6 | bucket) for sources, -1 otherwise
   int32_t *dest;       // n: chosen destination
-  uint8_t *flag;       // n: scratch flags
-  int32_t *list;       // n: compacted vertex ids
-  int32_t *list2;      // n
-  uint32_t *skey;      // n
-  uint32_t *skey2;     // n
-  int64_t *pre;        // n: exclusive weight prefix
-  int32_t *seg;        // 2^bits: segment starts per block
+  uint8_t *reject;     // n: strong rounds, movers refused by their destination
+  int64_t *pre;        // n: exclusive weight prefix of the refused movers
   int32_t *elig;       // 2^bits: blocks within the cap, ascending
-  int64_t *acc;        // 2^bits: accepted weight per destination
+  int64_t *bw;         // 8 x 2^bits x 64 bucket weights (kept zero between rounds)
+  int64_t *acc;        // 8 x 2^bits accepted weights (kept zero between rounds)
+  int32_t *crit;       // 2^bits
+  int64_t *need;       // 2^bits
+  int32_t *tcrit;      // 2^bits
+  int64_t *tneed;      // 2^bits
+  int32_t *tsum;       // 2^bits x ntiles
   int64_t *rstart;     // 2^bits: residual prefix
   int32_t *rblock;     // 2^bits: blocks with residual > 0
+  int32_t tile;        // ids per tile
+  int32_t ntiles;
 };
-// Full weak/strong rebalancing round; leaves moved/target ready for
-// apply_moves.  Synchronises the stream (list sizes).
-void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h,
-                      bool strong, int64_t lmax, int64_t sigma, int64_t total,
-                      uint64_t hseed, const int32_t *part, const int64_t *w,
-                      int32_t *target, uint8_t *moved,
-                      const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
-                      const Stripes &sp, hipStream_t s);
+RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_t s);
+// One weak/strong rebalancing round: writes moved/target for every vertex,
+// ready for apply_moves.  No host synchronisation.
+void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
+                     int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
+                     const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
+                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s);
 
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,

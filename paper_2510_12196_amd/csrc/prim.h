@@ -15,6 +15,10 @@ void scan_excl_widen(Arena &ar, const int32_t *in, int64_t *out, int64_t n, hipS
 void scan_excl_gather(Arena &ar, const int32_t *idx, const int32_t *vwgt, int64_t *out,
                       int64_t n, hipStream_t s);
 
+// out[i] = sum_{j<i, flags[j] != 0} vwgt[j] (int64)
+void scan_excl_masked(Arena &ar, const uint8_t *flags, const int32_t *vwgt, int64_t *out,
+                      int64_t n, hipStream_t s);
+
 // Stable compaction of the indices i in [0,n) with flags[i] != 0 (ascending).
 // *count_dev receives the number selected.
 void select_indices(Arena &ar, const uint8_t *flags, int32_t *out, int32_t *count_dev,

@@ -27,6 +27,14 @@ struct GatherWeight {
   __host__ __device__ int64_t operator()(int32_t v) const { return (int64_t)vwgt[v]; }
 };
 
+struct MaskedWeight {
+  const uint8_t *flags;
+  const int32_t *vwgt;
+  __host__ __device__ int64_t operator()(int32_t i) const {
+    return flags[i] ? (int64_t)vwgt[i] : 0;
+  }
+};
+
 struct IsClass {
   uint8_t c;
   __host__ __device__ bool operator()(uint8_t x) const { return x == c; }
@@ -67,6 +75,17 @@ void scan_excl_gather(Arena &ar, const int32_t *idx, const int32_t *vwgt, int64_
                       int64_t n, hipStream_t s) {
   if (n <= 0) return;
   auto it = rocprim::make_transform_iterator(idx, GatherWeight{vwgt});
+  run_two_phase(ar, [&](void *t, size_t &b) {
+    return rocprim::exclusive_scan(t, b, it, out, int64_t(0), (size_t)n,
+                                   rocprim::plus<int64_t>(), s);
+  });
+}
+
+void scan_excl_masked(Arena &ar, const uint8_t *flags, const int32_t *vwgt, int64_t *out,
+                      int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  auto it = rocprim::make_transform_iterator(rocprim::counting_iterator<int32_t>(0),
+                                             MaskedWeight{flags, vwgt});
   run_two_phase(ar, [&](void *t, size_t &b) {
     return rocprim::exclusive_scan(t, b, it, out, int64_t(0), (size_t)n,
                                    rocprim::plus<int64_t>(), s);

@@ -202,9 +202,9 @@ __device__ __forceinline__ int64_t cost_group(const CostArgs &A, int cls, int lo
 
 __global__ __launch_bounds__(kThreads) void k_comm_cost(CostArgs A) {
   __shared__ BlockScratch sc;
-  const int total = A.cl.wg[NCLS];
   int64_t x = 0;
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+  {  // one class tile per workgroup
+    const int blk = blockIdx.x;
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
@@ -435,8 +435,8 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X
 __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  const int total = A.cl.wg[NCLS];
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+  {  // one class tile per workgroup
+    const int blk = blockIdx.x;
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
@@ -521,8 +521,8 @@ __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) 
 
 __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
   __shared__ BlockScratch sc;
-  const int total = A.cl.wg[NCLS];
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
+  {  // one class tile per workgroup
+    const int blk = blockIdx.x;
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
@@ -711,7 +711,16 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
 // below the block's excess.  Strong rebalancing then accepts movers per
 // destination while the destination stays within L_max, and spreads the
 // rejected ones over the residual capacities.
+//
+// The ordered prefixes are computed without sorting ("keyed prefix"): with
+// per-(key, bucket) weight sums the critical bucket of every key is found;
+// only members of that bucket need an id-ordered prefix, which is split
+// into per-tile sums (tiles of consecutive ids), a critical tile per key,
+// and an in-tile scan.  Every size stays on the device.
 // ===========================================================================
+constexpr int kBuckets = 64;
+constexpr int kBucketStripes = 8;
+
 struct RebArgs {
   DGraph g;
   Classes cl;
@@ -726,7 +735,7 @@ struct RebArgs {
   const Status *st;
   int32_t *key;
   int32_t *dest;
-  uint8_t *flag;
+  int64_t *bw;   // bucket weight stripes [stripe][code][bucket]
 };
 
 __device__ __forceinline__ int32_t bucket_of(int64_t g) {
@@ -741,6 +750,12 @@ __device__ __forceinline__ bool is_source(const RebArgs &A, int32_t v, uint32_t 
   return !(2 * A.h.k * (int64_t)A.g.c[v] > 3 * (A.h.k * wp - A.total));
 }
 
+__device__ __forceinline__ void bw_add(int64_t *bw, int32_t ncodes, uint32_t code, int32_t bucket,
+                                       int64_t c) {
+  const size_t i = ((size_t)(blockIdx.x & (kBucketStripes - 1)) * ncodes + code) * kBuckets + bucket;
+  atomicAdd((unsigned long long *)&bw[i], (unsigned long long)c);
+}
+
 // Final decision for a source v with best neighbour block (b, conn_b) or none
 // (b == 0xFFFFFFFF), conn to own block connp.
 __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
@@ -749,21 +764,18 @@ __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t
     const int32_t ne = A.st->n_eligible;
     if (ne <= 0) {
       A.key[v] = -1;
-      A.flag[v] = 0;
       return;
     }
     b = (uint32_t)A.elig[mix_hash(A.hseed, (uint64_t)v) % (uint64_t)ne];
     conn_b = 0;
   }
-  A.key[v] = (int32_t)((p << 6) | (uint32_t)bucket_of(conn_b - connp));
+  const int32_t bucket = bucket_of(conn_b - connp);
+  A.key[v] = (int32_t)((p << 6) | (uint32_t)bucket);
   A.dest[v] = (int32_t)b;
-  A.flag[v] = 1;
+  bw_add(A.bw, 1 << A.h.bits, p, bucket, A.g.c[v]);
 }
 
-__device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) {
-  A.key[v] = -1;
-  A.flag[v] = 0;
-}
+__device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) { A.key[v] = -1; }
 
 template <int G>
 __device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) {
@@ -825,27 +837,24 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  const int total = A.cl.wg[NCLS];
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
-    const int cls = find_class(A.cl, blk);
-    const int local = blk - A.cl.wg[cls];
-    switch (cls) {
-      case CLS_ISO: {
-        const int idx = local * kThreads + threadIdx.x;
-        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
-          const uint32_t p = (uint32_t)A.part[v];
-          if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
-          else reb_not_source(A, v);
-        }
-        break;
+  const int cls = find_class(A.cl, blockIdx.x);
+  const int local = blockIdx.x - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int idx = local * kThreads + threadIdx.x;
+      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
+        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+        const uint32_t p = (uint32_t)A.part[v];
+        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
+        else reb_not_source(A, v);
       }
-      case CLS_G8: reb_group<8>(A, cls, local); break;
-      case CLS_G16: reb_group<16>(A, cls, local); break;
-      case CLS_G32: reb_group<32>(A, cls, local); break;
-      case CLS_G64: reb_group<64>(A, cls, local); break;
-      default: reb_big(A, local, X, sc); break;
+      break;
     }
+    case CLS_G8: reb_group<8>(A, cls, local); break;
+    case CLS_G16: reb_group<16>(A, cls, local); break;
+    case CLS_G32: reb_group<32>(A, cls, local); break;
+    case CLS_G64: reb_group<64>(A, cls, local); break;
+    default: reb_big(A, local, X, sc); break;
   }
 }
 
@@ -865,76 +874,259 @@ __global__ __launch_bounds__(kThreads) void k_reb_eligible(Hier h, const int64_t
   if (threadIdx.x == kThreads - 1) st->n_eligible = (int32_t)pos;
 }
 
-__global__ void k_gather_keys(int32_t m, const int32_t *list, const int32_t *key,
-                              uint32_t *skey) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) skey[i] = (uint32_t)key[list[i]];
-}
-__global__ void k_gather_dest_keys(int32_t m, const int32_t *list, const int32_t *key,
-                                   const int32_t *dest, uint32_t *skey) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) {
-    const int32_t v = list[i];
-    skey[i] = ((uint32_t)dest[v] << 6) | ((uint32_t)key[v] & 63u);
-  }
-}
-// first position of every block in a list sorted by (block << 6 | bucket)
-__global__ void k_seg_starts(int32_t m, const uint32_t *skey, int32_t *seg) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m && (i == 0 || (skey[i] >> 6) != (skey[i - 1] >> 6))) seg[skey[i] >> 6] = (int32_t)i;
-}
-// moves: sources whose exclusive prefix within their block is below the excess
-__global__ void k_select_prefix(int32_t m, const uint32_t *skey, const int32_t *list,
-                                const int64_t *pre, const int32_t *seg, const int64_t *w,
-                                int64_t lmax, const int32_t *dest, int32_t *target,
-                                uint8_t *moved) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint32_t a = skey[i] >> 6;
-  if (pre[i] - pre[seg[a]] < w[a] - lmax) {
-    const int32_t v = list[i];
-    moved[v] = 1;
-    target[v] = dest[v];
-  }
-}
-// strong: accept per destination while it stays within L_max
-__global__ void k_accept(int32_t m, const uint32_t *skey, const int32_t *list,
-                         const int64_t *pre, const int32_t *seg, const int64_t *w,
-                         const int32_t *vwgt, int64_t lmax, int64_t *acc, uint8_t *moved,
-                         uint8_t *reject) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const uint32_t t = skey[i] >> 6;
-  const int32_t v = list[i];
-  if (w[t] + (pre[i] - pre[seg[t]]) + vwgt[v] <= lmax) {
-    atomicAdd((unsigned long long *)&acc[t], (unsigned long long)(int64_t)vwgt[v]);
+// ---------------------------------------------------------------------------
+// Keyed prefix: an element v (key K, bucket b, weight c) passes iff
+//   prefix(v) + delta * c < budget'(K),
+// prefix(v) = weight of the elements of key K before v in (bucket, id) order.
+// Selection of sources (key = source block): delta = 0, budget' = c(A) - L_max.
+// Acceptance per destination (key = destination): delta = 1,
+// budget' = L_max - c(t) + 1, i.e. prefix + c <= L_max - c(t).
+// ---------------------------------------------------------------------------
+enum { KP_SELECT = 0, KP_ACCEPT = 1 };
+
+struct KPArgs {
+  int32_t n;
+  int32_t ncodes;
+  int32_t tile;
+  int32_t ntiles;
+  int32_t pass;       // KP_SELECT or KP_ACCEPT
+  int32_t strong;     // selection of a strong round: feed the acceptance sums
+  int64_t lmax;
+  const int64_t *w;   // block weights
+  const int32_t *vwgt;
+  const int32_t *key; // source block << 6 | bucket, or -1
+  const int32_t *dest;
+  int64_t *bw;        // bucket weight stripes
+  int64_t *acc;       // accepted weight stripes [stripe][code]
+  int32_t *crit;      // critical bucket per key (-1: key without elements)
+  int64_t *need;      // budget left inside the critical bucket
+  int32_t *tsum;      // [code][tile] weight of critical members per tile
+  int32_t *tcrit;     // critical tile per key
+  int64_t *tneed;     // budget left inside the critical tile
+  uint8_t *moved;
+  int32_t *target;
+  uint8_t *reject;
+};
+
+// element of the current pass?  (key K, bucket b)
+__device__ __forceinline__ bool kp_element(const KPArgs &A, int32_t v, uint32_t &K, int32_t &b) {
+  const int32_t k = A.key[v];
+  if (A.pass == KP_SELECT) {
+    if (k < 0) return false;
+    K = (uint32_t)k >> 6;
   } else {
-    moved[v] = 0;
-    reject[v] = 1;
+    if (!A.moved[v]) return false;
+    K = (uint32_t)A.dest[v];
+  }
+  b = k & 63;
+  return true;
+}
+
+// one wave per key: fold the bucket stripes, find the critical bucket
+__global__ __launch_bounds__(kThreads) void k_kp_crit(KPArgs A) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t K = blockIdx.x * (kThreads / 64) + wave;
+  if (K >= A.ncodes) return;
+  int64_t budget;
+  if (A.pass == KP_SELECT) {
+    if (A.w[K] <= A.lmax) {
+      if (lane == 0) A.crit[K] = -1;
+      return;
+    }
+    budget = A.w[K] - A.lmax;
+  } else {
+    budget = A.lmax - A.w[K] + 1;
+  }
+  int64_t x = 0;
+  for (int s = 0; s < kBucketStripes; ++s) {
+    int64_t *p = &A.bw[((size_t)s * A.ncodes + K) * kBuckets + lane];
+    x += *p;
+    *p = 0;
+  }
+  // inclusive scan over the 64 buckets
+  int64_t incl = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+    if (lane >= o) incl += y;
+  }
+  const unsigned long long reach = __ballot(incl >= budget);
+  if (lane == 0) {
+    if (!reach) {
+      A.crit[K] = kBuckets;  // every element passes
+      A.need[K] = 0;
+    }
+  }
+  if (reach) {
+    const int first = __ffsll((long long)reach) - 1;
+    if (lane == first) {
+      A.crit[K] = first;
+      A.need[K] = budget - (incl - x);
+    }
   }
 }
-// residual capacities r_b = L_max - c(b) - accepted_b > 0, ascending blocks
-__global__ __launch_bounds__(kThreads) void k_residual(Hier h, const int64_t *w,
-                                                       const int64_t *acc, int64_t lmax,
-                                                       int64_t *rstart, int32_t *rblock,
-                                                       Status *st) {
+
+// one workgroup per tile of consecutive ids: weight of critical members per key
+__global__ __launch_bounds__(kThreads) void k_kp_tilesum(KPArgs A) {
+  extern __shared__ int32_t accl[];
+  const int32_t t = blockIdx.x;
+  for (int c = threadIdx.x; c < A.ncodes; c += kThreads) accl[c] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)t * A.tile;
+  const int64_t hi = lo + A.tile < A.n ? lo + A.tile : A.n;
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+    uint32_t K;
+    int32_t b;
+    if (kp_element(A, (int32_t)v, K, b) && A.crit[K] == b) atomicAdd(&accl[K], A.vwgt[v]);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < A.ncodes; c += kThreads)
+    A.tsum[(size_t)c * A.ntiles + t] = accl[c];
+}
+
+// one wave per key: the critical tile and the budget left inside it
+__global__ __launch_bounds__(kThreads) void k_kp_tilecrit(KPArgs A) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t K = blockIdx.x * (kThreads / 64) + wave;
+  if (K >= A.ncodes) return;
+  const int32_t cb = A.crit[K];
+  if (cb < 0 || cb >= kBuckets) return;
+  const int64_t need = A.need[K];
+  int64_t base = 0;
+  const int32_t *row = A.tsum + (size_t)K * A.ntiles;
+  for (int32_t t0 = 0; t0 < A.ntiles; t0 += 64) {
+    const int32_t t = t0 + lane;
+    const int64_t x = t < A.ntiles ? row[t] : 0;
+    int64_t incl = x;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+      if (lane >= o) incl += y;
+    }
+    const unsigned long long reach = __ballot(t < A.ntiles && base + incl >= need);
+    if (reach) {
+      const int first = __ffsll((long long)reach) - 1;
+      if (lane == first) {
+        A.tcrit[K] = t;
+        A.tneed[K] = need - (base + incl - x);
+      }
+      return;
+    }
+    base += gshfl64<64>(incl, 63);
+  }
+  if (lane == 0) A.tcrit[K] = A.ntiles;  // every critical member passes
+}
+
+__device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t K, int32_t b,
+                                           bool pass) {
+  if (A.pass == KP_SELECT) {
+    if (pass) {
+      const int32_t d = A.dest[v];
+      A.moved[v] = 1;
+      A.target[v] = d;
+      if (A.strong) bw_add(A.bw, A.ncodes, (uint32_t)d, b, A.vwgt[v]);
+    } else {
+      A.moved[v] = 0;
+    }
+  } else {
+    if (pass) {
+      atomicAdd((unsigned long long *)&A.acc[(size_t)(blockIdx.x & (kBucketStripes - 1)) * A.ncodes + K],
+                (unsigned long long)(int64_t)A.vwgt[v]);
+      A.reject[v] = 0;
+    } else {
+      A.moved[v] = 0;
+      A.reject[v] = 1;
+    }
+  }
+}
+
+// one workgroup per tile: final pass/fail of every element in the tile
+__global__ __launch_bounds__(kThreads) void k_kp_decide(KPArgs A) {
+  extern __shared__ int64_t run[];
+  const int32_t t = blockIdx.x;
+  const int delta = A.pass == KP_SELECT ? 0 : 1;
+  for (int c = threadIdx.x; c < A.ncodes; c += kThreads) run[c] = 0;
+  const int64_t lo = (int64_t)t * A.tile;
+  const int64_t hi = lo + A.tile < A.n ? lo + A.tile : A.n;
+  // everything but the members of a key whose critical tile is this one
+  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+    uint32_t K;
+    int32_t b;
+    if (!kp_element(A, (int32_t)v, K, b)) {
+      if (A.pass == KP_SELECT) A.moved[v] = 0;
+      else A.reject[v] = 0;
+      continue;
+    }
+    const int32_t cb = A.crit[K];
+    if (b != cb) {
+      kp_outcome(A, (int32_t)v, K, b, b < cb);
+      continue;
+    }
+    const int32_t tc = A.tcrit[K];
+    if (tc != t) kp_outcome(A, (int32_t)v, K, b, tc > t);
+  }
+  __syncthreads();
+  // members in this critical tile: id-ordered prefix per key, by wave 0
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x;
+  for (int64_t base = lo; base < hi; base += 64) {
+    const int64_t v = base + lane;
+    uint32_t K = 0;
+    int32_t b = 0;
+    bool mine = false;
+    int64_t c = 0;
+    if (v < hi && kp_element(A, (int32_t)v, K, b) && A.crit[K] == b && A.tcrit[K] == t) {
+      mine = true;
+      c = A.vwgt[v];
+    }
+    unsigned long long left = __ballot(mine);
+    while (left) {
+      const int leader = __ffsll((long long)left) - 1;
+      const uint32_t LK = (uint32_t)__shfl((int32_t)K, leader, 64);
+      const bool in = mine && K == LK;
+      const unsigned long long grp = __ballot(in);
+      int64_t x = in ? c : 0;
+      int64_t incl = x;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+        if (lane >= o) incl += y;
+      }
+      const int64_t before = run[LK];
+      if (in) kp_outcome(A, (int32_t)v, K, b, before + (incl - x) + delta * c < A.tneed[K]);
+      const int64_t tot = gshfl64<64>(incl, 63);
+      if (lane == 0) run[LK] = before + tot;
+      left &= ~grp;
+    }
+  }
+}
+
+// residual capacities r_b = L_max - c(b) - accepted_b > 0, ascending blocks;
+// folds (and clears) the accepted-weight stripes.  One workgroup; thread i
+// owns the codes [i*per, (i+1)*per), per <= 32.
+__global__ __launch_bounds__(kThreads) void k_residual(Hier h, const int64_t *w, int64_t *acc,
+                                                       int64_t lmax, int64_t *rstart,
+                                                       int32_t *rblock, Status *st) {
   __shared__ BlockScratch sc;
   __shared__ int64_t wave_tot[kThreads / 64];
   const int32_t ncodes = 1 << h.bits;
   const int per = (ncodes + kThreads - 1) / kThreads;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < ncodes ? lo + per : ncodes;
+  int64_t r[(1 << kMaxCodeBits) / kThreads];
   uint32_t cnt = 0;
   int64_t sum = 0;
   for (int c = lo; c < hi; ++c) {
-    const int64_t r = code_valid(h, (uint32_t)c) ? lmax - w[c] - acc[c] : 0;
-    if (r > 0) {
+    int64_t a = 0;
+    for (int s = 0; s < kBucketStripes; ++s) {
+      a += acc[(size_t)s * ncodes + c];
+      acc[(size_t)s * ncodes + c] = 0;
+    }
+    const int64_t x = code_valid(h, (uint32_t)c) ? lmax - w[c] - a : 0;
+    r[c - lo] = x;
+    if (x > 0) {
       ++cnt;
-      sum += r;
+      sum += x;
     }
   }
   uint32_t pos = block_excl_scan(cnt, sc);
-  // exclusive scan of the int64 sums
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int64_t incl = sum;
   for (int o = 1; o < 64; o <<= 1) {
@@ -946,28 +1138,28 @@ __global__ __launch_bounds__(kThreads) void k_residual(Hier h, const int64_t *w,
   __syncthreads();
   int64_t off = 0;
   for (int i = 0; i < wave; ++i) off += wave_tot[i];
-  int64_t run = off + incl - sum;
+  int64_t runv = off + incl - sum;
   for (int c = lo; c < hi; ++c) {
-    const int64_t r = code_valid(h, (uint32_t)c) ? lmax - w[c] - acc[c] : 0;
-    if (r > 0) {
-      rstart[pos] = run;
+    if (r[c - lo] > 0) {
+      rstart[pos] = runv;
       rblock[pos] = c;
       ++pos;
-      run += r;
+      runv += r[c - lo];
     }
   }
   if (threadIdx.x == kThreads - 1) {
     st->count2 = (int32_t)pos;
-    st->resid_total = run;
+    st->resid_total = runv;
   }
 }
+
 // rejected movers (id order, exclusive weight prefix R) -> residual slots
-__global__ void k_assign_rejects(int32_t m, const int32_t *list, const int64_t *pre,
+__global__ void k_assign_rejects(int32_t n, const uint8_t *reject, const int64_t *pre,
                                  const int64_t *rstart, const int32_t *rblock,
                                  const Status *st, int32_t *target, uint8_t *moved) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  const int64_t R = pre[i];
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || !reject[v]) return;
+  const int64_t R = pre[v];
   if (R >= st->resid_total) return;
   int32_t lo = 0, hi = st->count2 - 1;  // largest j with rstart[j] <= R
   while (lo < hi) {
@@ -975,77 +1167,98 @@ __global__ void k_assign_rejects(int32_t m, const int32_t *list, const int64_t *
     if (rstart[mid] <= R) lo = mid;
     else hi = mid - 1;
   }
-  const int32_t v = list[i];
   target[v] = rblock[lo];
   moved[v] = 1;
 }
 
-void rebalance_select(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h,
-                      bool strong, int64_t lmax, int64_t sigma, int64_t total,
-                      uint64_t hseed, const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
-                      const RebalanceBuffers &rb, Status *st_dev, Status *st_host,
-                      const Stripes &sp, hipStream_t s) {
-  (void)sp;
+RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_t s) {
+  RebalanceBuffers rb{};
+  const int32_t ncodes = 1 << h.bits;
+  int64_t tile = 4096;
+  while (((n + tile - 1) / tile) * (int64_t)ncodes > (int64_t(1) << 24)) tile *= 2;
+  rb.tile = (int32_t)tile;
+  rb.ntiles = (int32_t)((n + tile - 1) / tile);
+  rb.key = ar.alloc_n<int32_t>(n);
+  rb.dest = ar.alloc_n<int32_t>(n);
+  rb.reject = ar.alloc_n<uint8_t>(n);
+  rb.pre = ar.alloc_n<int64_t>(n);
+  rb.elig = ar.alloc_n<int32_t>(ncodes);
+  rb.bw = ar.alloc_n<int64_t>((size_t)kBucketStripes * ncodes * kBuckets);
+  rb.acc = ar.alloc_n<int64_t>((size_t)kBucketStripes * ncodes);
+  rb.crit = ar.alloc_n<int32_t>(ncodes);
+  rb.need = ar.alloc_n<int64_t>(ncodes);
+  rb.tcrit = ar.alloc_n<int32_t>(ncodes);
+  rb.tneed = ar.alloc_n<int64_t>(ncodes);
+  rb.tsum = ar.alloc_n<int32_t>((size_t)ncodes * (rb.ntiles > 0 ? rb.ntiles : 1));
+  rb.rstart = ar.alloc_n<int64_t>(ncodes);
+  rb.rblock = ar.alloc_n<int32_t>(ncodes);
+  fill_i64(rb.bw, 0, (int64_t)kBucketStripes * ncodes * kBuckets, s);
+  fill_i64(rb.acc, 0, (int64_t)kBucketStripes * ncodes, s);
+  return rb;
+}
+
+static void keyed_prefix(KPArgs A, hipStream_t s) {
+  const unsigned waves_grid = (unsigned)((A.ncodes + (kThreads / 64) - 1) / (kThreads / 64));
+  hipLaunchKernelGGL(k_kp_crit, dim3(waves_grid), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+  if (A.ntiles <= 0) return;
+  hipLaunchKernelGGL(k_kp_tilesum, dim3(A.ntiles), dim3(kThreads), sizeof(int32_t) * A.ncodes, s, A);
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_kp_tilecrit, dim3(waves_grid), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_kp_decide, dim3(A.ntiles), dim3(kThreads), sizeof(int64_t) * A.ncodes, s, A);
+  PM_LAUNCH_CHECK();
+}
+
+void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
+                     int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
+                     const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
+                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s) {
   const unsigned nwg = classed_grid(cl);
   const int64_t n = g.n;
-  fill_u8(moved, 0, n, s);
-  if (nwg == 0) return;
+  if (n <= 0) return;
+  const int32_t ncodes = 1 << h.bits;
   const int64_t cap = strong ? lmax : sigma;
   hipLaunchKernelGGL(k_reb_eligible, dim3(1), dim3(kThreads), 0, s, h, w, cap, rb.elig, st_dev);
   PM_LAUNCH_CHECK();
-  RebArgs A{g, cl, h, part, w, lmax, cap, total, hseed, rb.elig, st_dev, rb.key, rb.dest, rb.flag};
-  hipLaunchKernelGGL(k_reb_select, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
-  PM_LAUNCH_CHECK();
-  // sources in id order
-  select_indices(ar, rb.flag, rb.list, &st_dev->count, n, s);
-  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
-  const int32_t ns = st_host->count;
-  if (ns == 0) return;
-  const int kbits = h.bits + 6;
-  hipLaunchKernelGGL(k_gather_keys, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.list, rb.key,
-                     rb.skey);
-  PM_LAUNCH_CHECK();
-  sort_pairs(ar, rb.skey, rb.skey2, rb.list, rb.list2, ns, kbits, s);
-  scan_excl_gather(ar, rb.list2, g.c, rb.pre, ns, s);
-  hipLaunchKernelGGL(k_seg_starts, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.skey2, rb.seg);
-  PM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_select_prefix, dim3(grid_for(ns)), dim3(kThreads), 0, s, ns, rb.skey2,
-                     rb.list2, rb.pre, rb.seg, w, lmax, rb.dest, target, moved);
-  PM_LAUNCH_CHECK();
+  if (nwg > 0) {
+    RebArgs A{g, cl, h, part, w, lmax, cap, total, hseed, rb.elig, st_dev, rb.key, rb.dest, rb.bw};
+    hipLaunchKernelGGL(k_reb_select, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+    PM_LAUNCH_CHECK();
+  }
+  KPArgs K{};
+  K.n = (int32_t)n;
+  K.ncodes = ncodes;
+  K.tile = rb.tile;
+  K.ntiles = rb.ntiles;
+  K.pass = KP_SELECT;
+  K.strong = strong ? 1 : 0;
+  K.lmax = lmax;
+  K.w = w;
+  K.vwgt = g.c;
+  K.key = rb.key;
+  K.dest = rb.dest;
+  K.bw = rb.bw;
+  K.acc = rb.acc;
+  K.crit = rb.crit;
+  K.need = rb.need;
+  K.tsum = rb.tsum;
+  K.tcrit = rb.tcrit;
+  K.tneed = rb.tneed;
+  K.moved = moved;
+  K.target = target;
+  K.reject = rb.reject;
+  keyed_prefix(K, s);
   if (!strong) return;
-
-  // ---- strong: acceptance per destination ----
-  select_indices(ar, moved, rb.list, &st_dev->count, n, s);
-  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
-  const int32_t nsel = st_host->count;
-  if (nsel == 0) return;
-  hipLaunchKernelGGL(k_gather_dest_keys, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.list,
-                     rb.key, rb.dest, rb.skey);
-  PM_LAUNCH_CHECK();
-  sort_pairs(ar, rb.skey, rb.skey2, rb.list, rb.list2, nsel, kbits, s);
-  scan_excl_gather(ar, rb.list2, g.c, rb.pre, nsel, s);
-  hipLaunchKernelGGL(k_seg_starts, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.skey2,
-                     rb.seg);
-  PM_LAUNCH_CHECK();
-  fill_i64(rb.acc, 0, (int64_t)1 << h.bits, s);
-  fill_u8(rb.flag, 0, n, s);
-  hipLaunchKernelGGL(k_accept, dim3(grid_for(nsel)), dim3(kThreads), 0, s, nsel, rb.skey2,
-                     rb.list2, rb.pre, rb.seg, w, g.c, lmax, rb.acc, moved, rb.flag);
-  PM_LAUNCH_CHECK();
-  // ---- rejected movers, id order ----
-  select_indices(ar, rb.flag, rb.list, &st_dev->count, n, s);
-  PM_HIP(hipMemcpyAsync(&st_host->count, &st_dev->count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
-  const int32_t nrej = st_host->count;
-  if (nrej == 0) return;
+  K.pass = KP_ACCEPT;
+  K.strong = 0;
+  keyed_prefix(K, s);
   hipLaunchKernelGGL(k_residual, dim3(1), dim3(kThreads), 0, s, h, w, rb.acc, lmax, rb.rstart,
                      rb.rblock, st_dev);
   PM_LAUNCH_CHECK();
-  scan_excl_gather(ar, rb.list, g.c, rb.pre, nrej, s);
-  hipLaunchKernelGGL(k_assign_rejects, dim3(grid_for(nrej)), dim3(kThreads), 0, s, nrej, rb.list,
-                     rb.pre, rb.rstart, rb.rblock, st_dev, target, moved);
+  scan_excl_masked(ar, rb.reject, g.c, rb.pre, n, s);
+  hipLaunchKernelGGL(k_assign_rejects, dim3(grid_for(n)), dim3(kThreads), 0, s, (int32_t)n,
+                     rb.reject, rb.pre, rb.rstart, rb.rblock, st_dev, target, moved);
   PM_LAUNCH_CHECK();
 }
 
