@@ -23,6 +23,77 @@ sys.path.insert(0, ROOT)
 
 METRIC = "refinement GTEPS + end-to-end map time; batched/served vs plain at equal J"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 512 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lp_phase1_rgg20_traffic.txt")
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2510_12196_amd", "csrc", f)
+                   for f in ("refine.hip", "device_util.h", "pm_internal.h")]
+
+
+def source_digest():
+    """Digest of the sources that define the label-propagation phase-1 kernel."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(workload):
+    """Measured HBM bytes per launch of k_lp_phase1 from the committed counter
+    summary, if it was taken on this workload and on the current sources."""
+    try:
+        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("workload") != workload or kv.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def summarize_pmc(d):
+    """Reduce rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch)
+    for k_lp_phase1 and the calibration copy kernel to bytes per launch."""
+    import csv
+    import glob
+    sums = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            name = r.get("Kernel_Name", "")
+            ctr = r.get("Counter_Name", "")
+            val = float(r.get("Counter_Value", "0") or 0)
+            disp = r.get("Dispatch_Id", "")
+            kind = "lp1" if "k_lp_phase1" in name else ("copy" if "copyBuffer" in name else None)
+            if kind is None:
+                continue
+            key = (kind, ctr)
+            sums.setdefault(key, {})
+            sums[key][disp] = sums[key].get(disp, 0.0) + val
+    out = {}
+    for (kind, ctr), per in sums.items():
+        if kind == "copy":  # the 512 MiB calibration copy is the largest copy dispatch
+            out[(kind, ctr)] = (max(per.values()), 1)
+        else:
+            out[(kind, ctr)] = (sum(per.values()), len(per))
+    for k, v in sorted(out.items()):
+        print(k, v)
+    copy_mib = COPY_BYTES / 1024.0
+    res = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        if ("copy", ctr) in out and ("lp1", ctr) in out:
+            ctot, cn = out[("copy", ctr)]
+            ltot, ln = out[("lp1", ctr)]
+            scale = copy_mib / (ctot / cn) if ctot else float("nan")
+            res[ctr] = (ltot / ln) * scale * 1024.0
+            print(f"{ctr}: copy reads {ctot / cn:.0f} KiB for {copy_mib:.0f} KiB -> scale "
+                  f"{scale:.4f}; k_lp_phase1 {ltot / ln:.1f} KiB/launch -> {res[ctr]:.0f} B")
+    if len(res) == 2:
+        print(f"hbm_bytes_per_launch: {res['FETCH_SIZE'] + res['WRITE_SIZE']:.0f}")
+    print(f"source_digest: {source_digest()}")
 
 
 def log(*a):
@@ -36,7 +107,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rgg20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device-to-device copy of 512 MiB (known traffic) for "
+                         "scaling hardware byte counters")
+    ap.add_argument("--summarize-pmc", metavar="DIR",
+                    help="summarise rocprofv3 --pmc counter CSVs under DIR and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the mapping of one task graph runs on a single "
               "device; run it with --gpus 1", file=sys.stderr)
@@ -59,6 +138,15 @@ def main():
 
     def step(i, kernel_times):
         return pm.pm_map(dg, w.a, w.d, w.eps, 1 + i % 5, kernel_times=kernel_times)
+
+    if args.copy_calibration:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {COPY_BYTES} bytes read, {COPY_BYTES} bytes written")
+        del src, dst
 
     for i in range(args.warmup):
         rc, part, st = step(i, True)
@@ -123,7 +211,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": read_traffic(w.name),
             "bytes_per_launch": round(kbytes / kl[0], 1) if kl[0] else None,
             "avg_launch_us": round(kms[0] * 1e3 / kl[0], 3) if kl[0] else None,
         },
