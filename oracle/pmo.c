@@ -618,16 +618,61 @@ static int hem_better(int64_t w1, int64_t c1, uint64_t h1, int32_t lo1,
   return hi1 < hi2;
 }
 
-/* Heavy-edge matching in synchronous rounds.  In a round every unmatched
- * vertex v prefers the unmatched neighbour u with c(u)+c(v) <= L_max whose
- * edge rates highest (see hem_better); v and u are matched iff they prefer
- * each other.  Rounds repeat until one adds no match (at most 64).  If 75 %
- * or fewer of the vertices are then matched, the isolated vertices (which
- * all share the empty neighbourhood and are therefore twins) are paired in
- * id order -- the 1st with the 2nd, the 3rd with the 4th, ... -- whenever
- * the pair's weight is at most L_max.
+typedef struct {
+  uint64_t key;
+  int32_t v;
+} keyed_vertex;
+
+static int cmp_keyed(const void *x, const void *y) {
+  const keyed_vertex *a = (const keyed_vertex *)x, *b = (const keyed_vertex *)y;
+  if (a->key != b->key) return (a->key > b->key) - (a->key < b->key);
+  return (a->v > b->v) - (a->v < b->v);
+}
+
+/* Pairs the members of every group of equal keys, in id order: the 1st with
+ * the 2nd, the 3rd with the 4th, ..., a pair only when its weight fits
+ * L_max (otherwise both stay unmatched).  Returns the vertices matched. */
+static int64_t pair_groups(keyed_vertex *items, int64_t cnt, const int32_t *vwgt,
+                           int64_t lmax, int32_t *match) {
+  qsort(items, (size_t)cnt, sizeof(keyed_vertex), cmp_keyed);
+  int64_t added = 0;
+  for (int64_t i = 0; i < cnt;) {
+    int64_t j = i;
+    while (j < cnt && items[j].key == items[i].key) ++j;
+    for (int64_t p = i; p + 1 < j; p += 2) {
+      int32_t a = items[p].v, b = items[p + 1].v;
+      if ((int64_t)vwgt[a] + vwgt[b] <= lmax) {
+        match[a] = b;
+        match[b] = a;
+        added += 2;
+      }
+    }
+    i = j;
+  }
+  return added;
+}
+
+#define TAG_TWIN 0x5457494EULL
+
+/* Heavy-edge matching in synchronous rounds, followed by two-hop matching.
+ *
+ * Heavy-edge rounds: every unmatched vertex v prefers the unmatched
+ * neighbour u with c(u)+c(v) <= L_max whose edge rates highest (see
+ * hem_better); v and u are matched iff they prefer each other.  Rounds repeat
+ * until one adds no match (at most 64).
+ *
+ * Two-hop matching (the leaf, twin and relative categories), each step only
+ * while 75 % or fewer of the vertices are matched:
+ *  - leaves: unmatched vertices of degree one, grouped by their neighbour;
+ *  - twins: unmatched vertices with the same neighbourhood, recognised by an
+ *    order-independent neighbourhood hash (sum of the splitmix64 hashes of
+ *    the neighbour ids) together with the degree; all isolated vertices
+ *    share the empty neighbourhood;
+ *  - relatives: unmatched vertices with a neighbour, grouped by their
+ *    matchmaker -- the neighbour of smallest (degree, id).
+ * In every group the members are paired in id order (see pair_groups).
  * match_out[v] = partner, or v itself if unmatched.  Returns the number of
- * matching rounds executed. */
+ * heavy-edge rounds executed. */
 int32_t pmo_hem(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                 const int32_t *adjwgt, const int32_t *vwgt, int64_t lmax,
                 uint64_t seed, int32_t level, int32_t *match_out) {
@@ -672,24 +717,59 @@ int32_t pmo_hem(int32_t n, const int64_t *xadj, const int32_t *adjncy,
     matched += added;
     if (added == 0) break;
   }
+  free(pref);
+
+  keyed_vertex *items = (keyed_vertex *)xmalloc(sizeof(keyed_vertex) * (size_t)n);
+  /* leaves, grouped by their only neighbour */
   if (4 * matched <= 3 * (int64_t)n) {
-    int32_t pending = -1;
-    for (int32_t v = 0; v < n; ++v) {
-      if (match[v] >= 0 || xadj[v + 1] != xadj[v]) continue;
-      if (pending < 0) {
-        pending = v;
-      } else {
-        if ((int64_t)vwgt[pending] + vwgt[v] <= lmax) {
-          match[pending] = v;
-          match[v] = pending;
-        }
-        pending = -1;
+    int64_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v)
+      if (match[v] < 0 && xadj[v + 1] - xadj[v] == 1) {
+        items[cnt].key = (uint64_t)(uint32_t)adjncy[xadj[v]];
+        items[cnt].v = v;
+        ++cnt;
       }
-    }
+    matched += pair_groups(items, cnt, vwgt, lmax, match);
   }
+  /* twins, grouped by neighbourhood hash and degree */
+  if (4 * matched <= 3 * (int64_t)n) {
+    uint64_t tseed = pmo_hash(seed ^ TAG_TWIN, (uint64_t)level);
+    int64_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      if (match[v] >= 0) continue;
+      uint64_t h = 0;
+      for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e)
+        h += pmo_hash(tseed, (uint64_t)(uint32_t)adjncy[e]);
+      items[cnt].key = pmo_hash(h, (uint64_t)(xadj[v + 1] - xadj[v]));
+      items[cnt].v = v;
+      ++cnt;
+    }
+    matched += pair_groups(items, cnt, vwgt, lmax, match);
+  }
+  /* relatives, grouped by their matchmaker */
+  if (4 * matched <= 3 * (int64_t)n) {
+    int64_t cnt = 0;
+    for (int32_t v = 0; v < n; ++v) {
+      if (match[v] >= 0 || xadj[v + 1] == xadj[v]) continue;
+      int32_t mm = -1;
+      int64_t mdeg = 0;
+      for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e) {
+        int32_t u = adjncy[e];
+        int64_t du = xadj[u + 1] - xadj[u];
+        if (mm < 0 || du < mdeg || (du == mdeg && u < mm)) {
+          mm = u;
+          mdeg = du;
+        }
+      }
+      items[cnt].key = (uint64_t)(uint32_t)mm;
+      items[cnt].v = v;
+      ++cnt;
+    }
+    matched += pair_groups(items, cnt, vwgt, lmax, match);
+  }
+  free(items);
   for (int32_t v = 0; v < n; ++v)
     if (match[v] < 0) match[v] = v;
-  free(pref);
   return rounds;
 }
 

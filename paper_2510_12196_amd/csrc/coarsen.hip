@@ -191,37 +191,6 @@ void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes
   fold_stripes(stripes, nullptr, &st->count, s);
 }
 
-// unmatched vertices without neighbours (they share the empty neighbourhood)
-__global__ void k_iso_flags(DGraph g, const int32_t *match, uint8_t *flag) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < g.n) flag[v] = (match[v] < 0 && g.xadj[v + 1] == g.xadj[v]) ? 1 : 0;
-}
-void hem_isolated_flags(const DGraph &g, const int32_t *match, uint8_t *flag, hipStream_t s) {
-  if (g.n <= 0) return;
-  hipLaunchKernelGGL(k_iso_flags, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, match, flag);
-  PM_LAUNCH_CHECK();
-}
-
-// pairs (iso[2j], iso[2j+1]) when their weight fits
-__global__ void k_pair_iso(const int32_t *iso, int32_t npairs, const int32_t *vwgt,
-                           int64_t lmax, int32_t *match) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= npairs) return;
-  const int32_t a = iso[2 * j], b = iso[2 * j + 1];
-  if ((int64_t)vwgt[a] + vwgt[b] <= lmax) {
-    match[a] = b;
-    match[b] = a;
-  }
-}
-void hem_pair_isolated(const int32_t *iso, int32_t niso, const int32_t *vwgt, int64_t lmax,
-                       int32_t *match, hipStream_t s) {
-  const int32_t np = niso / 2;
-  if (np <= 0) return;
-  hipLaunchKernelGGL(k_pair_iso, dim3(grid_for(np)), dim3(kThreads), 0, s, iso, np, vwgt, lmax,
-                     match);
-  PM_LAUNCH_CHECK();
-}
-
 // unmatched -> self; leader flag (the smaller member of a pair, or a single)
 __global__ void k_hem_finish(int32_t n, int32_t *match, int32_t *leader) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

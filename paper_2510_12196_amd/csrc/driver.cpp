@@ -239,16 +239,12 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
     matched += added;
     if (added == 0) break;
   }
-  if (4 * matched <= 3 * (int64_t)g.n) {
-    const size_t m = cx.ar.mark();
-    uint8_t *flag = cx.ar.alloc_n<uint8_t>(g.n);
-    int32_t *iso = cx.ar.alloc_n<int32_t>(g.n);
-    hem_isolated_flags(g, match, flag, s);
-    select_indices(cx.ar, flag, iso, &cx.dev->count, g.n, s);
-    cx.pull();
-    hem_pair_isolated(iso, cx.host->count, g.c, lmax, match, s);
-    cx.ar.rewind(m);
-  }
+  // two-hop matching while 75 % or fewer of the vertices are matched
+  const int64_t lim = 3 * (int64_t)g.n;
+  const uint64_t tseed = mix_hash(seed ^ kTagTwin, (uint64_t)(int64_t)level);
+  for (int mode : {TWOHOP_LEAF, TWOHOP_TWIN, TWOHOP_RELATIVE})
+    if (4 * matched <= lim)
+      matched += two_hop_step(cx.ar, g, L.cl, mode, tseed, lmax, match, cx.sp.b, cx.dev, cx.host, s);
   return rounds;
 }
 

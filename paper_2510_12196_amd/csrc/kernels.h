@@ -15,6 +15,7 @@ struct Status {
   int32_t n_eligible;  // blocks within the rebalancing cap
   int32_t pad_;
   int64_t resid_total; // strong rebalancing: total residual capacity
+  int64_t aux;         // generic 64-bit result
 };
 
 // Striped accumulator buffers of one call (kStripes x 16 int64 each, zeroed
@@ -109,9 +110,13 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
                 const int32_t *match, int32_t *pref, hipStream_t s);
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes, Status *st,
                 hipStream_t s);   // st->count = new matches
-void hem_isolated_flags(const DGraph &g, const int32_t *match, uint8_t *flag, hipStream_t s);
-void hem_pair_isolated(const int32_t *iso, int32_t niso, const int32_t *vwgt, int64_t lmax,
-                       int32_t *match, hipStream_t s);
+// Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched
+// vertices and pairs each group in id order.  Returns the vertices matched.
+// Synchronises the stream.
+enum { TWOHOP_LEAF = 0, TWOHOP_TWIN = 1, TWOHOP_RELATIVE = 2 };
+int64_t two_hop_step(Arena &ar, const DGraph &g, const Classes &cl, int mode, uint64_t tseed,
+                     int64_t lmax, int32_t *match, int64_t *stripes, Status *st_dev,
+                     Status *st_host, hipStream_t s);
 void hem_finish(int32_t n, int32_t *match, int32_t *leader, hipStream_t s);
 void coarse_ids(int32_t n, const int32_t *match, const int32_t *rank, int32_t *cmap,
                 hipStream_t s);

@@ -107,6 +107,7 @@ __host__ __device__ inline uint64_t mix_hash(uint64_t seed, uint64_t word) {
 }
 constexpr uint64_t kTagMatch = 0x48454D31ull;
 constexpr uint64_t kTagRebalance = 0x5245424Cull;
+constexpr uint64_t kTagTwin = 0x5457494Eull;
 
 // Graph view (device pointers).
 struct DGraph {

@@ -15,6 +15,8 @@ void scan_excl_widen(Arena &ar, const int32_t *in, int64_t *out, int64_t n, hipS
 void scan_excl_gather(Arena &ar, const int32_t *idx, const int32_t *vwgt, int64_t *out,
                       int64_t n, hipStream_t s);
 
+// out[i] = max_{j<=i} in[j]
+void scan_incl_max(Arena &ar, const int32_t *in, int32_t *out, int64_t n, hipStream_t s);
 // out[i] = sum_{j<i, flags[j] != 0} vwgt[j] (int64)
 void scan_excl_masked(Arena &ar, const uint8_t *flags, const int32_t *vwgt, int64_t *out,
                       int64_t n, hipStream_t s);

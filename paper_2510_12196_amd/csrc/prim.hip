@@ -81,6 +81,13 @@ void scan_excl_gather(Arena &ar, const int32_t *idx, const int32_t *vwgt, int64_
   });
 }
 
+void scan_incl_max(Arena &ar, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  run_two_phase(ar, [&](void *t, size_t &b) {
+    return rocprim::inclusive_scan(t, b, in, out, (size_t)n, rocprim::maximum<int32_t>(), s);
+  });
+}
+
 void scan_excl_masked(Arena &ar, const uint8_t *flags, const int32_t *vwgt, int64_t *out,
                       int64_t n, hipStream_t s) {
   if (n <= 0) return;

@@ -406,6 +406,52 @@ def test_row_order_invariance(pmo, name):
 # matching and contraction (Section 3.2)
 # ----------------------------------------------------------------------------
 
+def test_two_hop_matching_properties(pmo):
+    fx = golden("two_hop_matching.json")
+    g = graph_from_fixture(fx)
+    for seed in range(1, 9):
+        _, m = pmo.hem(g, fx["lmax"], seed)
+        assert np.array_equal(m[m], np.arange(g.n))
+        nb = [set(g.adjncy[g.xadj[x]:g.xadj[x + 1]].tolist()) for x in range(g.n)]
+        for x in range(g.n):
+            y = int(m[x])
+            if y == x or y in nb[x]:
+                continue
+            assert (nb[x] & nb[y]) or (not nb[x] and not nb[y])
+        # 9 is the only isolated vertex: no twin partner
+        assert m[9] == 9
+        # leaves 3 and 4 (neighbour 0) pair up whenever both are still unmatched leaves
+        if m[3] != 0 and m[4] != 0:
+            assert m[3] == 4
+
+
+def test_two_hop_leaf_twin_relative_closed_cases(pmo):
+    """Hand cases where heavy-edge matching cannot act and each two-hop
+    category decides alone."""
+    # leaves: star with 4 leaves, centre heavier than L_max allows to pair
+    g = gen.from_edges(5, [0, 0, 0, 0], [1, 2, 3, 4], [1, 1, 1, 1], [9, 1, 1, 1, 1])
+    _, m = pmo.hem(g, 5, 1)
+    assert m.tolist() == [0, 2, 1, 4, 3]
+    # twins: K_{2,3} -- 2,3,4 all see {0,1}; the heavy vertices 0,1 (weight 9)
+    # fit no pair under L_max 9; relatives then group 0 and 1 (matchmaker 2)
+    # but their pair is too heavy
+    g = gen.from_edges(5, [0, 0, 0, 1, 1, 1], [2, 3, 4, 2, 3, 4], [1] * 6, [9, 9, 1, 1, 1])
+    _, m = pmo.hem(g, 9, 1)
+    assert m.tolist() == [0, 1, 3, 2, 4]
+    # relatives: path 0-1-2 with centre too heavy: 0 and 2 share neighbour 1
+    # but are leaves (degree 1) -> paired already as leaves of 1
+    g = gen.from_edges(4, [0, 1, 1], [1, 2, 3], [1, 1, 1], [1, 9, 1, 1])
+    _, m = pmo.hem(g, 5, 1)
+    assert m.tolist() == [2, 1, 0, 3]
+    # relatives proper: light 0 (neighbours 1,4) and 3 (neighbours 1,5) are
+    # not twins; their smallest-degree neighbour is 1 (degree 2 < 3), so they
+    # form one relative group; heavy 1,2,4,5 (weight 9) fit no pair
+    g = gen.from_edges(6, [0, 0, 3, 3, 4, 4, 5], [1, 4, 1, 5, 5, 2, 2], [1] * 7,
+                       [1, 9, 9, 1, 9, 9])
+    _, m = pmo.hem(g, 5, 1)
+    assert m.tolist() == [3, 1, 2, 0, 4, 5]
+
+
 def test_hem_hand_example(pmo):
     fx = golden("hem_rating.json")
     g = graph_from_fixture(fx)
@@ -425,14 +471,18 @@ def test_hem_matching_properties(pmo, name):
     paired = match != v
     assert (g.vwgt[v[paired]] + g.vwgt[match[paired]] <= lm).all()
     deg = np.diff(g.xadj)
-    # pairs are edges, except isolated twins
+    # pairs are edges, or two-hop pairs (a common neighbour), or isolated twins
     src = np.repeat(v, deg)
     is_edge = set(zip(src.tolist(), g.adjncy.tolist()))
+    nbrs = [set(g.adjncy[g.xadj[x]:g.xadj[x + 1]].tolist()) for x in range(g.n)]
     for x in v[paired]:
-        if deg[x] > 0:
-            assert (int(x), int(match[x])) in is_edge
+        y = int(match[x])
+        if (int(x), y) in is_edge:
+            continue
+        if deg[x] == 0:
+            assert deg[y] == 0
         else:
-            assert deg[match[x]] == 0
+            assert nbrs[int(x)] & nbrs[y], (x, y)
     # maximality: no eligible edge joins two unmatched vertices
     un = ~paired
     both = un[src] & un[g.adjncy] & (g.vwgt[src] + g.vwgt[g.adjncy] <= lm)
