@@ -26,6 +26,7 @@ __all__ = [
     "random_mapping",
     "shuffle_rows",
     "path_graph",
+    "rmat_n",
 ]
 
 
@@ -177,6 +178,44 @@ def rmat(scale: int, draws: int, seed: int,
     vwgt = rng.integers(1, cmax + 1, size=n, dtype=np.int32)
     g = from_edges(n, u, v, wsum.astype(np.int32), vwgt)
     g.name = name or f"rmat{scale}"
+    return g
+
+
+def rmat_n(n: int, draws: int, seed: int, probs=(0.57, 0.19, 0.19, 0.05), wmax: int = 10,
+           cmax: int = 4, name: str = "") -> Graph:
+    """R-MAT on n vertices (n need not be a power of two): quadrant descent over
+    ceil(log2 n) levels, draws with an endpoint >= n are dropped and replaced
+    by further draws until `draws` draws are in range; then as rmat()."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    scale = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    a, b, c, _ = probs
+    t1, t2, t3 = a, a + b, a + b + c
+    src_all, dst_all = [], []
+    have = 0
+    while have < draws:
+        m = int((draws - have) * (2 ** scale) / n * 1.2) + 64
+        src = np.zeros(m, dtype=np.int64)
+        dst = np.zeros(m, dtype=np.int64)
+        for level in range(scale):
+            bit = np.int64(1) << np.int64(scale - 1 - level)
+            x = rng.random(m)
+            src += (x >= t2) * bit
+            dst += (((x >= t1) & (x < t2)) | (x >= t3)) * bit
+        ok = (src < n) & (dst < n)
+        src_all.append(src[ok])
+        dst_all.append(dst[ok])
+        have += int(ok.sum())
+    src = np.concatenate(src_all)[:draws]
+    dst = np.concatenate(dst_all)[:draws]
+    w = rng.integers(1, wmax + 1, size=draws, dtype=np.int64)
+    keep = src != dst
+    src, dst, w = src[keep], dst[keep], w[keep]
+    key = np.minimum(src, dst) * n + np.maximum(src, dst)
+    uniq, inv = np.unique(key, return_inverse=True)
+    wsum = np.bincount(inv, weights=w).astype(np.int64)
+    vwgt = rng.integers(1, cmax + 1, size=n, dtype=np.int32)
+    g = from_edges(n, uniq // n, uniq % n, wsum.astype(np.int32), vwgt)
+    g.name = name or f"rmat_n{n}"
     return g
 
 

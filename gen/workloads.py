@@ -70,3 +70,73 @@ WORKLOADS = {
 
 def get(name: str) -> Workload:
     return WORKLOADS[name]
+
+
+# ---------------------------------------------------------------------------
+# many instances: the batched workload and the served request stream
+# ---------------------------------------------------------------------------
+BATCH_HIERARCHIES = [(2, 2, 4), (4, 4, 8), (4, 8, 8)]
+
+
+@dataclasses.dataclass
+class Instance:
+    name: str
+    graph: graphs.Graph
+    a: tuple
+    d: tuple
+    eps: float
+    seed: int
+
+
+def _member_rng(base: int, index: int):
+    return np.random.Generator(np.random.PCG64([base, index]))
+
+
+def instance(kind: str, n: int, a, seed: int, name: str) -> Instance:
+    if kind == "grid":
+        r = max(1, int(np.floor(np.sqrt(n))))
+        g = graphs.grid2d(r, max(1, n // r))
+    elif kind == "rgg":
+        g = graphs.rgg(n, seed)
+    else:
+        g = graphs.rmat_n(n, 8 * n, seed)
+    return Instance(name, g, tuple(a), D3, 0.03, 1)
+
+
+def batch_members(count: int = 512, base_seed: int = 0xC4, log2_lo: float = 10.0,
+                  log2_hi: float = 16.0):
+    """Instances of the batched workload: n = floor(2^U(lo,hi)), kind grid /
+    rgg / rmat with probability 1/3 each, hierarchy drawn from 2:2:4, 4:4:8,
+    4:8:8, distances 1:10:100, eps 3 %; everything derived from
+    (base_seed, index)."""
+    out = []
+    for i in range(count):
+        rng = _member_rng(base_seed, i)
+        n = int(np.floor(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        kind = ["grid", "rgg", "rmat"][int(rng.integers(0, 3))]
+        a = BATCH_HIERARCHIES[int(rng.integers(0, 3))]
+        gseed = int(rng.integers(0, 2 ** 31))
+        inst = instance(kind, n, a, gseed, f"{kind}{n}")
+        inst.seed = 1 + int(rng.integers(0, 5))
+        out.append(inst)
+    return out
+
+
+def serve_stream(count: int, qps: float, base_seed: int = 0xC5, log2_lo: float = 12.0,
+                 log2_hi: float = 20.0):
+    """Requests of the served workload: exponential inter-arrival times at
+    `qps`, n = floor(2^U(lo,hi)), rgg or rmat 1/2 each, hierarchy 4:8:8 or
+    4:16:8 1/2 each.  Returns (arrival_seconds, Instance) pairs."""
+    out = []
+    t = 0.0
+    for i in range(count):
+        rng = _member_rng(base_seed, i)
+        t += float(rng.exponential(1.0 / qps))
+        n = int(np.floor(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        kind = "rgg" if rng.integers(0, 2) == 0 else "rmat"
+        a = (4, 8, 8) if rng.integers(0, 2) == 0 else (4, 16, 8)
+        gseed = int(rng.integers(0, 2 ** 31))
+        inst = instance(kind, n, a, gseed, f"{kind}{n}")
+        inst.seed = 1 + int(rng.integers(0, 5))
+        out.append((t, inst))
+    return out

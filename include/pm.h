@@ -212,6 +212,61 @@ int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps,
            uint64_t seed, int32_t *part_out, pm_map_stats *stats,
            uint32_t flags, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Many instances.  A job is one independent mapping instance: a device graph,
+ * its own hierarchy, eps and seed, and a device output array.  Every job is
+ * computed by exactly the code path of pm_map, so its mapping and status are
+ * the ones pm_map returns for it, whatever else runs beside it.
+ * ------------------------------------------------------------------------- */
+typedef struct pm_map_job {
+  pm_graph graph;          /* device arrays, owned by the caller, complete   */
+  pm_hierarchy hierarchy;
+  double eps;
+  uint64_t seed;
+  int32_t *part_out;       /* device int32[n]                               */
+  int32_t status;          /* out: the instance's return code               */
+  int32_t levels;          /* out: graphs in its hierarchy                  */
+  int64_t j_final;         /* out: J of the returned mapping                */
+  double ms;               /* out: wall time of the instance                */
+} pm_map_job;
+
+/* Batched mapping (the batched workload of the survey's C4): the jobs are
+ * spread over `workers` host threads (0: 8), each with its own HIP stream and
+ * scratch, so that the small kernels and host round trips of many instances
+ * overlap on the device.  Jobs are started largest first.  `stream` is
+ * synchronised before any job starts.  Returns PM_OK if every job has a
+ * non-negative status, otherwise the first negative status. */
+int pm_map_batch(pm_map_job *jobs, int32_t count, int32_t workers,
+                 void *stream);
+
+/* Estimated device scratch of one pm_map call on this graph and hierarchy
+ * (bytes); the server admits jobs against its budget with it. */
+int64_t pm_job_footprint(const pm_graph *g, const pm_hierarchy *h);
+
+/* Serving with continuous batching: a server owns `workers` host threads with
+ * their own streams.  Submitted jobs wait in a FIFO queue and are admitted in
+ * order as soon as the summed footprint of the admitted, unfinished jobs
+ * plus theirs fits `hbm_budget_bytes` and a worker is free; jobs that
+ * arrive while others run overlap with them on the device.  The job's device
+ * arrays must be complete when it is submitted and stay valid until it is
+ * done. */
+typedef struct pm_server pm_server;
+pm_server *pm_server_create(int64_t hbm_budget_bytes, int32_t workers);
+/* Returns a ticket >= 0, or PM_EINVAL / PM_ENOMEM (footprint above the
+ * budget).  The job struct is copied. */
+int64_t pm_server_submit(pm_server *srv, const pm_map_job *job);
+/* 1 if the ticket is done, 0 if queued or running, PM_EINVAL if unknown. */
+int pm_server_poll(pm_server *srv, int64_t ticket);
+/* Blocks until the ticket is done; copies the finished job (status, levels,
+ * j_final, ms) into *out (may be NULL) and the latency from submission to
+ * completion into *latency_ms (may be NULL), then releases the ticket.
+ * Returns the job's status (PM_EINVAL for an unknown ticket).  Two threads
+ * must not wait on the same ticket. */
+int pm_server_wait(pm_server *srv, int64_t ticket, pm_map_job *out,
+                   double *latency_ms);
+/* Waits for every submitted job, then stops the workers. */
+void pm_server_destroy(pm_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -74,6 +74,13 @@ class PmMapStats(ctypes.Structure):
                 ("kernel_bytes", ctypes.c_double * 4)]
 
 
+class PmMapJob(ctypes.Structure):
+    _fields_ = [("graph", PmGraph), ("hierarchy", PmHierarchy), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("part_out", ctypes.c_void_p),
+                ("status", ctypes.c_int32), ("levels", ctypes.c_int32),
+                ("j_final", ctypes.c_int64), ("ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _I32, _I64, _U32, _U64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
 _SIGS = {
@@ -89,6 +96,13 @@ _SIGS = {
     "pm_contract": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pm_initial_partition": (ctypes.c_int, [_P, _P, _P, _P]),
     "pm_map": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P]),
+    "pm_map_batch": (ctypes.c_int, [_P, _I32, _I32, _P]),
+    "pm_job_footprint": (_I64, [_P, _P]),
+    "pm_server_create": (_P, [_I64, _I32]),
+    "pm_server_submit": (_I64, [_P, _P]),
+    "pm_server_poll": (ctypes.c_int, [_P, _I64]),
+    "pm_server_wait": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "pm_server_destroy": (None, [_P]),
 }
 _lib = None
 
@@ -313,7 +327,88 @@ def pm_map(g: DeviceGraph, a, d, eps: float, seed: int, part=None, validate: boo
     return rc, part, st
 
 
+def make_job(g: DeviceGraph, a, d, eps: float, seed: int, part=None):
+    """A PmMapJob for one instance; returns (job, part) -- keep g and part
+    alive until the job is done."""
+    torch = _torch()
+    if part is None:
+        part = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.vwgt.device)
+    job = PmMapJob()
+    job.graph = g.struct()
+    job.hierarchy = hierarchy(a, d)
+    job.eps = float(eps)
+    job.seed = seed & (2**64 - 1)
+    job.part_out = part.data_ptr()
+    return job, part
+
+
+def pm_job_footprint(g: DeviceGraph, a, d) -> int:
+    gs, hs = g.struct(), hierarchy(a, d)
+    return int(_check(lib().pm_job_footprint(ctypes.byref(gs), ctypes.byref(hs)),
+                      "pm_job_footprint"))
+
+
+def pm_map_batch(instances, workers: int = 8):
+    """instances: list of (DeviceGraph, a, d, eps, seed).  Maps them all with
+    the batched executor.  Returns a list of (status, part, PmMapJob)."""
+    made = [make_job(*inst) for inst in instances]
+    arr = (PmMapJob * max(len(made), 1))()
+    for i, (job, _) in enumerate(made):
+        arr[i] = job
+    rc = lib().pm_map_batch(arr, len(made), int(workers), _stream())
+    out = []
+    for i, (_, part) in enumerate(made):
+        j = arr[i]
+        out.append((int(j.status), part, j))
+    if rc < 0 and all(o[0] >= 0 for o in out):
+        raise PmError(rc, "pm_map_batch")
+    return out
+
+
+class PmServer:
+    """Continuous-batching server (C ABI pm_server_*).  Jobs are admitted in
+    FIFO order against an HBM footprint budget and overlap on the device."""
+
+    def __init__(self, budget_bytes: int, workers: int = 8):
+        self._h = lib().pm_server_create(int(budget_bytes), int(workers))
+        if not self._h:
+            raise PmError(PM_EINVAL, "pm_server_create")
+        self._keep = {}
+
+    def submit(self, g: DeviceGraph, a, d, eps: float, seed: int, part=None) -> int:
+        job, part = make_job(g, a, d, eps, seed, part)
+        t = lib().pm_server_submit(self._h, ctypes.byref(job))
+        if t < 0:
+            raise PmError(int(t), "pm_server_submit")
+        self._keep[t] = (g, part)
+        return int(t)
+
+    def poll(self, ticket: int) -> bool:
+        return _check(lib().pm_server_poll(self._h, ticket), "pm_server_poll") == 1
+
+    def wait(self, ticket: int):
+        """Returns (status, part, PmMapJob, latency_ms)."""
+        out = PmMapJob()
+        lat = ctypes.c_double(0.0)
+        rc = lib().pm_server_wait(self._h, ticket, ctypes.byref(out), ctypes.byref(lat))
+        _, part = self._keep.pop(ticket)
+        return int(rc), part, out, float(lat.value)
+
+    def close(self):
+        if self._h:
+            lib().pm_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 __all__ = ["DeviceGraph", "PmError", "PmGraph", "PmHierarchy", "PmMapStats", "PmRefineStats",
            "hierarchy", "lib", "pm_version", "pm_release", "pm_comm_cost", "pm_block_weights",
            "pm_lp_round", "pm_rebalance", "pm_refine", "pm_hem", "pm_contract",
-           "pm_initial_partition", "pm_map"]
+           "pm_initial_partition", "pm_map", "PmMapJob", "make_job", "pm_map_batch",
+           "pm_job_footprint", "PmServer"]

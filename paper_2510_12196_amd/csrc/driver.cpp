@@ -599,13 +599,24 @@ int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, 
            pm_map_stats *stats, uint32_t flags, void *stream) {
   return guarded([&] {
     check_device();
+    return map_impl(g, h, eps, seed, part_out, stats, flags, as_stream(stream));
+  });
+}
+
+}  // extern "C"
+
+namespace pm {
+// The whole multilevel mapping on stream `stream` (throws Error).
+int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream) {
+  {
     const auto t_start = std::chrono::steady_clock::now();
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     if (dg.n > 0 && !part_out) throw Error(PM_EINVAL, "NULL output");
     ArenaLease lease;
     Arena &ar = *lease;
-    hipStream_t s = as_stream(stream);
+    hipStream_t s = stream;
     Ctx cx(ar, s);
     int64_t total = 0;
     validate_graph(ar, dg, (flags & PM_FLAG_VALIDATE) != 0, &total, s);
@@ -724,7 +735,7 @@ int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, 
             .count();
     if (stats) *stats = st;
     return status;
-  });
+  }
 }
+}  // namespace pm
 
-}  // extern "C"

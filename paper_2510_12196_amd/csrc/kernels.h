@@ -132,6 +132,11 @@ void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int
 void project(int32_t n, const int32_t *cmap, const int32_t *coarse, int32_t *fine,
              hipStream_t s);
 
+// ---- whole mapping ------------------------------------------------------------
+// The multilevel mapping of one instance on `stream` (throws Error).
+int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream);
+
 // ---- misc -----------------------------------------------------------------
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s);

@@ -22,7 +22,9 @@ def test_header_declares_the_hot_path_entry_points():
     names = declared_functions()
     for required in ["pm_comm_cost", "pm_refine", "pm_map", "pm_lp_round", "pm_rebalance",
                      "pm_hem", "pm_contract", "pm_initial_partition", "pm_block_weights",
-                     "pm_strerror", "pm_version", "pm_release"]:
+                     "pm_strerror", "pm_version", "pm_release", "pm_map_batch",
+                     "pm_job_footprint", "pm_server_create", "pm_server_submit",
+                     "pm_server_poll", "pm_server_wait", "pm_server_destroy"]:
         assert required in names
 
 
@@ -56,6 +58,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(pm.PmRefineStats) == 4 * 8 + 6 * 4 + 8 + 8
     assert pm.PmMapStats.kernel_bytes.offset == ctypes.sizeof(pm.PmMapStats) - 4 * 8
     assert pm.PmMapStats.refine_arcs.offset + 8 == pm.PmMapStats.kernel_launches.offset
+    # pm_map_job: graph 48, hierarchy 68 (+4 padding), eps, seed, part, 2 x int32, j, ms
+    assert ctypes.sizeof(pm.PmMapJob) == 168 and pm.PmMapJob.eps.offset == 120
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
