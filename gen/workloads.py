@@ -122,6 +122,16 @@ def batch_members(count: int = 512, base_seed: int = 0xC4, log2_lo: float = 10.0
     return out
 
 
+def serve_arrivals(count: int, qps: float, base_seed: int = 0xC5):
+    """Arrival times (seconds) of serve_stream(count, qps, base_seed), without
+    building the graphs."""
+    t, out = 0.0, []
+    for i in range(count):
+        t += float(_member_rng(base_seed, i).exponential(1.0 / qps))
+        out.append(t)
+    return out
+
+
 def serve_stream(count: int, qps: float, base_seed: int = 0xC5, log2_lo: float = 12.0,
                  log2_hi: float = 20.0):
     """Requests of the served workload: exponential inter-arrival times at
