@@ -67,7 +67,7 @@ def summarize_pmc(d):
             ctr = r.get("Counter_Name", "")
             val = float(r.get("Counter_Value", "0") or 0)
             disp = r.get("Dispatch_Id", "")
-            kind = "lp1" if "k_lp_phase1" in name else ("copy" if "copyBuffer" in name else None)
+            kind = "lp1" if "k_lp_phase1" in name else ("copy" if "neg_kernel" in name else None)
             if kind is None:
                 continue
             key = (kind, ctr)
@@ -75,7 +75,7 @@ def summarize_pmc(d):
             sums[key][disp] = sums[key].get(disp, 0.0) + val
     out = {}
     for (kind, ctr), per in sums.items():
-        if kind == "copy":  # the 512 MiB calibration copy is the largest copy dispatch
+        if kind == "copy":  # the 512 MiB calibration pass is the largest such dispatch
             out[(kind, ctr)] = (max(per.values()), 1)
         else:
             out[(kind, ctr)] = (sum(per.values()), len(per))
@@ -108,8 +108,8 @@ def main():
     ap.add_argument("--workload", default="rgg20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one device-to-device copy of 512 MiB (known traffic) for "
-                         "scaling hardware byte counters")
+                    help="also run one elementwise pass over 512 MiB (known traffic: 512 MiB "
+                         "read, 512 MiB written) for scaling hardware byte counters")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="summarise rocprofv3 --pmc counter CSVs under DIR and exit")
     args = ap.parse_args()
@@ -147,7 +147,7 @@ def main():
         src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda").fill_(1)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # an elementwise kernel: reads and writes COPY_BYTES once
         torch.cuda.synchronize()
         log(f"copy calibration: {COPY_BYTES} bytes read, {COPY_BYTES} bytes written")
         del src, dst

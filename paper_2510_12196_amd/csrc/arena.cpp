@@ -1,4 +1,5 @@
 // arena.cpp -- per-call scratch memory for the process-mapping library.
+#include <cstring>
 #include <map>
 
 #include "pm_internal.h"
@@ -17,6 +18,30 @@ void Arena::release() {
   if (host_) (void)hipHostFree(host_);
   host_ = nullptr;
   host_size_ = 0;
+  if (mapped_) (void)hipHostFree(mapped_);
+  mapped_ = nullptr;
+  mapped_dev_ = nullptr;
+}
+
+void *Arena::host_mapped(void **dev_view) {
+  if (!mapped_) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, kMappedBytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(PM_ENOMEM, "hipHostMalloc of mapped status memory failed");
+    }
+    void *d = nullptr;
+    if (hipHostGetDevicePointer(&d, p, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipHostFree(p);
+      throw Error(PM_EHIP, "hipHostGetDevicePointer failed");
+    }
+    std::memset(p, 0, kMappedBytes);
+    mapped_ = p;
+    mapped_dev_ = d;
+  }
+  *dev_view = mapped_dev_;
+  return mapped_;
 }
 
 void *Arena::alloc(size_t bytes) {

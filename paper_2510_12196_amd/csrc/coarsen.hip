@@ -126,10 +126,18 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
         }
         const int32_t cv = A.g.c[v];
         Cand best{-1, 0, 1, 0};
-        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads) {
-          const Cand c = hem_arc(A, v, cv, e);
-          if (cand_better(c, best, v)) best = c;
-        }
+        big_arcs(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) {
+              const int32_t u = A.g.adj[e];
+              return make_int4(u, A.match[u], A.g.c[u], A.g.w[e]);
+            },
+            [&](int64_t, int4 a) {
+              if (a.y >= 0 || (int64_t)a.z + cv > A.lmax) return;
+              const uint32_t lo = (uint32_t)(a.x < v ? a.x : v), hi = (uint32_t)(a.x < v ? v : a.x);
+              const Cand c{a.x, a.w, a.z, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+              if (cand_better(c, best, v)) best = c;
+            });
         cand_reduce<64>(best, v);
         const int wave = threadIdx.x >> 6;
         __syncthreads();  // the previous tile's reads of sc are done
@@ -295,8 +303,16 @@ __global__ __launch_bounds__(kThreads) void k_contract_keys(KeyArgs A) {
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint64_t cv = (uint64_t)A.cmap[v];
-        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-          self += key_arc(A, cv, e);
+        const uint64_t sentinel = (A.bits >= 32) ? ~0ull : ((1ull << (2 * A.bits)) - 1ull);
+        big_arcs(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) { return make_int2(A.cmap[A.g.adj[e]], A.g.w[e]); },
+            [&](int64_t e, int2 a) {
+              const uint64_t cu = (uint64_t)a.x;
+              A.val[e] = a.y;
+              A.key[e] = cu == cv ? sentinel : ((cv << A.bits) | cu);
+              self += cu == cv ? 1 : 0;
+            });
         break;
       }
     }
@@ -327,7 +343,11 @@ void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s
   PM_LAUNCH_CHECK();
 }
 
-// one thread per run head: fuse the run (at most 4 arcs: two members per side)
+// One thread per run head: fuse the run (at most 4 arcs: two members per
+// side).  The runs of a coarse row are consecutive, so its length is
+// (position of its last run + 1) - (position of its first run); only the
+// threads of those two runs touch the row's counter (a hub row would
+// otherwise take one atomic per run on a single address).
 __global__ void k_contract_emit(int64_t m, const uint64_t *key, const int32_t *val,
                                 const int32_t *head, const int32_t *pos, int bits,
                                 int32_t *cadj, int32_t *cw, int32_t *rowcnt) {
@@ -335,11 +355,17 @@ __global__ void k_contract_emit(int64_t m, const uint64_t *key, const int32_t *v
   if (i >= m || !head[i]) return;
   const uint64_t k = key[i];
   int64_t sum = 0;
-  for (int64_t j = i; j < m && key[j] == k; ++j) sum += val[j];
+  int64_t j = i;
+  for (; j < m && key[j] == k; ++j) sum += val[j];
   const int32_t o = pos[i];
   cadj[o] = (int32_t)(k & ((1ull << bits) - 1ull));
   cw[o] = (int32_t)sum;
-  atomicAdd(&rowcnt[k >> bits], 1);
+  const uint64_t row = k >> bits;
+  const bool first = i == 0 || (key[i - 1] >> bits) != row;
+  const bool last = j == m || (key[j] >> bits) != row;
+  if (first && last) rowcnt[row] = 1;
+  else if (first) atomicAdd(&rowcnt[row], -o);
+  else if (last) atomicAdd(&rowcnt[row], o + 1);
 }
 
 void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,

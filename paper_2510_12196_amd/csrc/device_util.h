@@ -132,6 +132,45 @@ __device__ __forceinline__ void stripe_add(int64_t *stripes, int64_t x) {
               (unsigned long long)x);
 }
 
+// ---- arcs of one high-degree vertex over a whole workgroup -------------------
+// For the arcs e in [beg, end) owned by this thread (stride kThreads), calls
+// use(e, load(e)).  load() may only read memory; kArcBatch loads are issued
+// before their uses, so that that many arcs' gathers are in flight together.
+constexpr int kArcBatch = 8;
+template <class L, class U>
+__device__ __forceinline__ void big_arcs(int64_t beg, int64_t end, L load, U use) {
+  int64_t e = beg + threadIdx.x;
+  for (; e + (kArcBatch - 1) * kThreads < end; e += kArcBatch * kThreads) {
+    decltype(load(e)) a[kArcBatch];
+#pragma unroll
+    for (int i = 0; i < kArcBatch; ++i) a[i] = load(e + i * kThreads);
+#pragma unroll
+    for (int i = 0; i < kArcBatch; ++i) use(e + i * kThreads, a[i]);
+  }
+  for (; e < end; e += kThreads) use(e, load(e));
+}
+
+// ---- keyed adds aggregated over a wave ----------------------------------------
+__device__ __forceinline__ void atomic_add_any(int32_t *p, int64_t x) { atomicAdd(p, (int32_t)x); }
+__device__ __forceinline__ void atomic_add_any(int64_t *p, int64_t x) {
+  atomicAdd((unsigned long long *)p, (unsigned long long)x);
+}
+// For every lane with `has`, adds val to *addr(key); one atomic per distinct
+// key in the wave.  Every lane of the wave must call it (no lane may have
+// left the kernel).
+template <class AddrF>
+__device__ __forceinline__ void wave_keyed_add(bool has, uint32_t key, int64_t val, AddrF addr) {
+  unsigned long long left = __ballot(has);
+  while (left) {
+    const int leader = __ffsll((long long)left) - 1;
+    const uint32_t lk = (uint32_t)__shfl((int32_t)key, leader, 64);
+    const bool in = has && key == lk;
+    const int64_t sum = gsum64<64>(in ? val : 0);
+    if ((int)(threadIdx.x & 63) == leader && sum != 0) atomic_add_any(addr(lk), sum);
+    left &= ~__ballot(in);
+  }
+}
+
 // ---- classed launches --------------------------------------------------------
 // Classed kernels run a capped grid; every workgroup walks the class tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...

@@ -74,17 +74,51 @@ struct Ctx {
   Status *dev;
   Status *host;
   Stripes sp;
+  // mapped mirror: [0, sizeof(Status)) status words, then the sequence slot
+  Status *mirror = nullptr;
+  Status *mirror_dev = nullptr;
+  int64_t *seq_dev = nullptr;
+  const volatile int64_t *seq_host = nullptr;
   explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
     dev = ar.alloc_n<Status>(1);
     host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
+    void *mdev = nullptr;
+    char *m = static_cast<char *>(ar.host_mapped(&mdev));
+    mirror = reinterpret_cast<Status *>(m);
+    mirror_dev = static_cast<Status *>(mdev);
+    seq_host = reinterpret_cast<const volatile int64_t *>(m + 256);
+    seq_dev = reinterpret_cast<int64_t *>(static_cast<char *>(mdev) + 256);
     sp.a = ar.alloc_n<int64_t>(2 * (size_t)stripe_words());
     sp.b = sp.a + stripe_words();
     PM_HIP(hipMemsetAsync(dev, 0, sizeof(Status), s));
     PM_HIP(hipMemsetAsync(sp.a, 0, sizeof(int64_t) * 2 * (size_t)stripe_words(), s));
   }
+  // Status read-back: a one-thread kernel publishes the status into mapped
+  // host memory and the host polls its sequence number, which returns sooner
+  // than a copy plus a stream synchronisation.  A stream that fails or goes
+  // idle without publishing raises PM_EHIP.
   void pull() {
-    PM_HIP(hipMemcpyAsync(host, dev, sizeof(Status), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
+    const int64_t seq = ar.next_publish();
+    publish_status(dev, mirror_dev, seq_dev, seq, s);
+    for (uint64_t it = 1;; ++it) {
+      if (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == seq) break;
+      __builtin_ia32_pause();
+      if ((it & 1023) == 0) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          throw Error(PM_EHIP, hipGetErrorString(e));
+        }
+        // idle stream: the release store is visible by now
+        bool seen = false;
+        for (int r = 0; r < 4096 && !seen; ++r)
+          seen = __atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == seq;
+        if (!seen) throw Error(PM_EHIP, "status publish not observed");
+        break;
+      }
+    }
+    std::memcpy(host, mirror, sizeof(Status));
   }
 };
 
@@ -115,6 +149,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   uint8_t *moved = ar.alloc_n<uint8_t>(n);
   uint8_t *lock = ar.alloc_n<uint8_t>(n);
   int64_t *w = ar.alloc_n<int64_t>(ncodes);
+  int64_t *wst = alloc_weight_stripes(ar, h, s);
   RebalanceBuffers rb = alloc_rebalance(ar, n, h, s);
 
   hipEvent_t ev0, ev1;
@@ -145,7 +180,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     if (imb_cur <= lmax) {
       lp_phase1(g, cl, h, cur, lock, target, gain, s);
       lp_phase2(g, cl, h, cur, target, gain, moved, s);
-      apply_moves(g, cl, h, cur, target, moved, lock, w, cx.sp.a, s);
+      apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, s);
       iw = 0;
       ++R.st.lp_iterations;
     } else {
@@ -153,7 +188,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
       rebalance_round(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
                       cx.dev, s);
-      apply_moves(g, cl, h, cur, target, moved, nullptr, w, cx.sp.a, s);
+      apply_moves(g, cl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, s);
       if (strong) {
         iw = 0;
         ++R.st.strong_iterations;
@@ -453,7 +488,8 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t
     block_weights(dg, hh, codes, w, s);
     lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s);
     lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
-    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w, cx.sp.a, s);
+    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w,
+                alloc_weight_stripes(*lease, hh, s), cx.sp.a, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     codes_to_ids(hh, target_out, target_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
@@ -490,7 +526,8 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
                     moved_out, rb, cx.dev, s);
-    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, cx.sp.a, s);
+    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s),
+                cx.sp.a, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;

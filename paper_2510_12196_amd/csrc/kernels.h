@@ -24,6 +24,10 @@ struct Stripes {
   int64_t *a;   // sums of J / J changes
   int64_t *b;   // counts
 };
+// Copies *dev into the mapped host mirror (device view host_dev), then stores
+// seq into *seq_dev, all with system-scope visibility.
+void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
+                    hipStream_t s);
 // Adds up the stripes into *out64 (if non-null) or *out32, clears them.
 void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s);
 int stripe_words();
@@ -72,11 +76,13 @@ void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
-// dj_stripes and the block weight changes into w; sets lock = moved if lock
-// != 0.
+// dj_stripes and the block weight changes into w (through the weight-delta
+// stripes wst, zero on entry and on return); sets lock = moved if lock != 0.
+constexpr int kWeightStripes = 32;
+int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *dj_stripes, hipStream_t s);
+                 int64_t *wst, int64_t *dj_stripes, hipStream_t s);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
 struct RebalanceBuffers {

@@ -121,7 +121,9 @@ struct DGraph {
 
 // Degree classes: vertices are processed by groups of G lanes (one arc per
 // lane) when deg <= G, by a whole workgroup with an LDS histogram otherwise.
-enum { CLS_ISO = 0, CLS_G8, CLS_G16, CLS_G32, CLS_G64, CLS_BIG, NCLS };
+// The enumeration order is the launch order of the class tiles: the longest
+// tiles (high degree) start first, so that they overlap with the rest.
+enum { CLS_BIG = 0, CLS_G64, CLS_G32, CLS_G16, CLS_G8, CLS_ISO, NCLS };
 __host__ __device__ constexpr int class_group(int cls) {
   return cls == CLS_G8 ? 8 : cls == CLS_G16 ? 16 : cls == CLS_G32 ? 32
        : cls == CLS_G64 ? 64 : 1;
@@ -153,6 +155,11 @@ class Arena {
   int device() const { return device_; }
   // pinned host staging for small read-backs
   void *host_stage(size_t bytes);
+  // Coherent host memory mapped into the device (kMappedBytes): kernels store
+  // into it through *dev_view; the host reads it while they run.
+  static constexpr size_t kMappedBytes = 4096;
+  void *host_mapped(void **dev_view);
+  int64_t next_publish() { return ++publish_seq_; }
 
  private:
   struct Chunk { char *ptr; size_t size; size_t base; };
@@ -161,6 +168,9 @@ class Arena {
   size_t top_ = 0;          // global offset over concatenated chunks
   void *host_ = nullptr;
   size_t host_size_ = 0;
+  void *mapped_ = nullptr;
+  void *mapped_dev_ = nullptr;
+  int64_t publish_seq_ = 0;
 };
 
 // Acquire an arena for the current device for the duration of a call.

@@ -45,6 +45,26 @@ void fill_u8(uint8_t *p, uint8_t v, int64_t n, hipStream_t s) { fill(p, v, n, s)
 void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill(p, v, n, s); }
 
 // ===========================================================================
+// status read-back: one thread copies the status words into mapped host
+// memory, then releases the sequence number the host is polling
+// ===========================================================================
+__global__ void k_publish(const Status *dev, Status *host, int64_t *seq_slot, int64_t seq) {
+  if (threadIdx.x != 0) return;
+  const int64_t *src = reinterpret_cast<const int64_t *>(dev);
+  int64_t *dst = reinterpret_cast<int64_t *>(host);
+  for (size_t i = 0; i < sizeof(Status) / sizeof(int64_t); ++i) dst[i] = src[i];
+  __threadfence_system();
+  __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+static_assert(sizeof(Status) % sizeof(int64_t) == 0, "Status is copied in 8-byte words");
+
+void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, dev, host_dev, seq_dev, seq);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
 // degree classes
 // ===========================================================================
 __global__ void k_classify(DGraph g, uint8_t *cls, int32_t *counts) {
@@ -215,8 +235,10 @@ __global__ __launch_bounds__(kThreads) void k_comm_cost(CostArgs A) {
       case CLS_BIG: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint32_t p = (uint32_t)A.part[v];
-        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-          x += (int64_t)A.g.w[e] * dist(A.h, p, (uint32_t)A.part[A.g.adj[e]]);
+        big_arcs(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
+            [&](int64_t, uint2 a) { x += (int64_t)a.y * dist(A.h, p, a.x); });
         break;
       }
       default: break;
@@ -381,8 +403,10 @@ __device__ __forceinline__ void big_histogram(const DGraph &g, const int32_t *pa
   __syncthreads();  // every wave is done reading the previous vertex's histogram
   for (int c = threadIdx.x; c <= ncodes; c += kThreads) X[c] = 0;
   __syncthreads();
-  for (int64_t e = g.xadj[v] + threadIdx.x; e < g.xadj[v + 1]; e += kThreads)
-    atomicAdd(&X[part[g.adj[e]] + 1], (uint32_t)g.w[e]);
+  big_arcs(
+      g.xadj[v], g.xadj[v + 1],
+      [&](int64_t e) { return make_uint2((uint32_t)part[g.adj[e]], (uint32_t)g.w[e]); },
+      [&](int64_t, uint2 a) { atomicAdd(&X[a.x + 1], a.y); });
   __syncthreads();
   block_scan_lds(X, ncodes + 1, sc);
 }
@@ -502,6 +526,11 @@ __device__ __forceinline__ int64_t lp2_arc(const LP2Args &A, int32_t v, int64_t 
   return (int64_t)A.g.w[e] * (dist(A.h, p, pu) - dist(A.h, t, pu));
 }
 
+struct Lp2Arc {
+  int32_t u, w, pu, tu;
+  int64_t gu;
+};
+
 template <int G>
 __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) {
   int32_t v;
@@ -545,8 +574,17 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
         }
         const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
         int64_t x = 0;
-        for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-          x += lp2_arc(A, v, gv, p, t, e);
+        big_arcs(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) {
+              const int32_t u = A.g.adj[e];
+              return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]};
+            },
+            [&](int64_t, const Lp2Arc &a) {
+              uint32_t pu = (uint32_t)a.pu;
+              if (a.gu != kNotInX && (a.gu > gv || (a.gu == gv && a.u < v))) pu = (uint32_t)a.tu;
+              x += (int64_t)a.w * (dist(A.h, p, pu) - dist(A.h, t, pu));
+            });
         x = block_sum64(x, sc);
         if (threadIdx.x == 0) A.moved[v] = x >= 0 ? 1 : 0;
         break;
@@ -588,7 +626,7 @@ struct ApplyArgs {
   const int32_t *target;
   const uint8_t *moved;
   uint8_t *lock;
-  int64_t *w;
+  int64_t *wst;  // weight-delta stripes [kWeightStripes][ncodes]
   int64_t *dj;
 };
 
@@ -659,8 +697,17 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
         if (m) {
           const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
           if (threadIdx.x == 0) apply_weights(A, v, p, t, dw);
-          for (int64_t e = A.g.xadj[v] + threadIdx.x; e < A.g.xadj[v + 1]; e += kThreads)
-            x += apply_arc(A, p, t, e);
+          big_arcs(
+              A.g.xadj[v], A.g.xadj[v + 1],
+              [&](int64_t e) {
+                const int32_t u = A.g.adj[e];
+                return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+              },
+              [&](int64_t, int4 a) {
+                const uint32_t old_u = (uint32_t)a.y;
+                if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
+                else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+              });
         }
         break;
       }
@@ -668,22 +715,43 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
   }
   x = block_sum64(x, sc);  // also orders the LDS weight deltas before the flush
   if (threadIdx.x == 0) stripe_add(A.dj, x);
+  // every workgroup touches the same few blocks: spread the flush over stripes
+  int64_t *wst = A.wst + (size_t)(blockIdx.x & (kWeightStripes - 1)) * ncodes;
   for (int c = threadIdx.x; c < ncodes; c += kThreads)
-    if (dw[c]) atomicAdd((unsigned long long *)&A.w[c], (unsigned long long)(int64_t)dw[c]);
+    if (dw[c]) atomicAdd((unsigned long long *)&wst[c], (unsigned long long)(int64_t)dw[c]);
 }
 
-__global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const uint8_t *moved) {
+// part <- target for the moved vertices; threads below ncodes also fold the
+// weight-delta stripes into w and clear them.
+__global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const uint8_t *moved,
+                         int32_t ncodes, int64_t *w, int64_t *wst) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < ncodes) {
+    int64_t a = 0;
+#pragma unroll 8
+    for (int st = 0; st < kWeightStripes; ++st) {
+      a += wst[(size_t)st * ncodes + v];
+      wst[(size_t)st * ncodes + v] = 0;
+    }
+    if (a) w[v] += a;
+  }
   if (v < n && moved[v]) part[v] = target[v];
+}
+
+int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
+  const int64_t words = (int64_t)kWeightStripes << h.bits;
+  int64_t *p = ar.alloc_n<int64_t>((size_t)words);
+  fill_i64(p, 0, words, s);
+  return p;
 }
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *dj_stripes, hipStream_t s) {
+                 int64_t *wst, int64_t *dj_stripes, hipStream_t s) {
   // capped: every workgroup flushes its LDS block-weight deltas once
   const unsigned nwg = capped_grid(cl);
   if (nwg == 0) return;
-  ApplyArgs A{g, cl, h, part, target, moved, lock, w, dj_stripes};
+  ApplyArgs A{g, cl, h, part, target, moved, lock, wst, dj_stripes};
   const size_t lds = sizeof(int32_t) * ((size_t)1 << h.bits);
   if (tl_timer) {
     hipEvent_t a, b;
@@ -693,8 +761,9 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
     hipLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), lds, s, A);
   }
   PM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
-                     moved);
+  const int32_t ncodes = 1 << h.bits;
+  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n > ncodes ? g.n : ncodes)), dim3(kThreads), 0, s,
+                     g.n, part, target, moved, ncodes, w, wst);
   PM_LAUNCH_CHECK();
 }
 
@@ -750,16 +819,21 @@ __device__ __forceinline__ bool is_source(const RebArgs &A, int32_t v, uint32_t 
   return !(2 * A.h.k * (int64_t)A.g.c[v] > 3 * (A.h.k * wp - A.total));
 }
 
-__device__ __forceinline__ void bw_add(int64_t *bw, int32_t ncodes, uint32_t code, int32_t bucket,
-                                       int64_t c) {
-  const size_t i = ((size_t)(blockIdx.x & (kBucketStripes - 1)) * ncodes + code) * kBuckets + bucket;
-  atomicAdd((unsigned long long *)&bw[i], (unsigned long long)c);
+// Source contributions to the bucket weights: key (block << 6 | bucket).
+struct BwAdd {
+  bool has = false;
+  uint32_t key = 0;
+  int64_t c = 0;
+};
+__device__ __forceinline__ void bw_flush(const RebArgs &A, const BwAdd &x) {
+  int64_t *bw = A.bw + (size_t)(blockIdx.x & (kBucketStripes - 1)) * ((size_t)kBuckets << A.h.bits);
+  wave_keyed_add(x.has, x.key, x.c, [=](uint32_t k) { return &bw[k]; });
 }
 
 // Final decision for a source v with best neighbour block (b, conn_b) or none
 // (b == 0xFFFFFFFF), conn to own block connp.
 __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
-                                           int64_t conn_b, int64_t connp) {
+                                           int64_t conn_b, int64_t connp, BwAdd &add) {
   if (b == 0xFFFFFFFFu) {
     const int32_t ne = A.st->n_eligible;
     if (ne <= 0) {
@@ -772,42 +846,48 @@ __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t
   const int32_t bucket = bucket_of(conn_b - connp);
   A.key[v] = (int32_t)((p << 6) | (uint32_t)bucket);
   A.dest[v] = (int32_t)b;
-  bw_add(A.bw, 1 << A.h.bits, p, bucket, A.g.c[v]);
+  add.has = true;
+  add.key = (p << 6) | (uint32_t)bucket;
+  add.c = A.g.c[v];
 }
 
 __device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) { A.key[v] = -1; }
 
+// One source per lane group; every lane of the wave reaches the bucket flush.
 template <int G>
 __device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) {
   int32_t v;
-  if (!group_vertex<G>(A.cl, cls, local, v)) return;
-  const int lane = threadIdx.x % G;
-  const uint32_t p = (uint32_t)A.part[v];
-  if (!is_source(A, v, p)) {
-    if (lane == 0) reb_not_source(A, v);
-    return;
+  BwAdd add;
+  if (group_vertex<G>(A.cl, cls, local, v)) {
+    const int lane = threadIdx.x % G;
+    const uint32_t p = (uint32_t)A.part[v];
+    if (!is_source(A, v, p)) {
+      if (lane == 0) reb_not_source(A, v);
+    } else {
+      const int64_t beg = A.g.xadj[v];
+      const int deg = (int)(A.g.xadj[v + 1] - beg);
+      const bool valid = lane < deg;
+      uint32_t bu = p;
+      int32_t wu = 0;
+      if (valid) {
+        bu = (uint32_t)A.part[A.g.adj[beg + lane]];
+        wu = A.g.w[beg + lane];
+      }
+      const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
+      const bool cand = valid && bu != p && A.w[bu] <= A.cap;
+      int64_t conn = 0;
+      for (int j = 0; j < deg; ++j) {
+        const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+        const int32_t wj = gshfl<G>(wu, j);
+        conn += bj == bu ? wj : 0;
+      }
+      int64_t val = cand ? conn : INT64_MIN;
+      uint32_t b = cand ? bu : 0xFFFFFFFFu;
+      gargmax<G>(val, b);
+      if (lane == 0) reb_decide(A, v, p, b, val, connp, add);
+    }
   }
-  const int64_t beg = A.g.xadj[v];
-  const int deg = (int)(A.g.xadj[v + 1] - beg);
-  const bool valid = lane < deg;
-  uint32_t bu = p;
-  int32_t wu = 0;
-  if (valid) {
-    bu = (uint32_t)A.part[A.g.adj[beg + lane]];
-    wu = A.g.w[beg + lane];
-  }
-  const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
-  const bool cand = valid && bu != p && A.w[bu] <= A.cap;
-  int64_t conn = 0;
-  for (int j = 0; j < deg; ++j) {
-    const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
-    const int32_t wj = gshfl<G>(wu, j);
-    conn += bj == bu ? wj : 0;
-  }
-  int64_t val = cand ? conn : INT64_MIN;
-  uint32_t b = cand ? bu : 0xFFFFFFFFu;
-  gargmax<G>(val, b);
-  if (lane == 0) reb_decide(A, v, p, b, val, connp);
+  bw_flush(A, add);
 }
 
 __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X,
@@ -831,23 +911,33 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
     }
   }
   block_argmax(val, b, sc);
-  if (threadIdx.x == 0) reb_decide(A, v, p, b, val, (int64_t)(X[p + 1] - X[p]));
+  if (threadIdx.x == 0) {
+    BwAdd add;
+    reb_decide(A, v, p, b, val, (int64_t)(X[p + 1] - X[p]), add);
+    if (add.has)
+      atomic_add_any(&A.bw[((size_t)(blockIdx.x & (kBucketStripes - 1)) << A.h.bits) * kBuckets +
+                           add.key],
+                     add.c);
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  const int cls = find_class(A.cl, blockIdx.x);
-  const int local = blockIdx.x - A.cl.wg[cls];
+  const int blk = blockIdx.x;
+  const int cls = find_class(A.cl, blk);
+  const int local = blk - A.cl.wg[cls];
   switch (cls) {
     case CLS_ISO: {
       const int idx = local * kThreads + threadIdx.x;
+      BwAdd add;
       if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
         const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
         const uint32_t p = (uint32_t)A.part[v];
-        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0);
+        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0, add);
         else reb_not_source(A, v);
       }
+      bw_flush(A, add);
       break;
     }
     case CLS_G8: reb_group<8>(A, cls, local); break;
@@ -965,25 +1055,29 @@ __global__ __launch_bounds__(kThreads) void k_kp_crit(KPArgs A) {
   }
 }
 
-// one workgroup per tile of consecutive ids: weight of critical members per key
+// Per-vertex pass: weight of the critical members per (key, tile), one
+// atomic per distinct key in a wave (a wave's 64 ids lie in one tile).
 __global__ __launch_bounds__(kThreads) void k_kp_tilesum(KPArgs A) {
-  extern __shared__ int32_t accl[];
-  const int32_t t = blockIdx.x;
-  for (int c = threadIdx.x; c < A.ncodes; c += kThreads) accl[c] = 0;
-  __syncthreads();
-  const int64_t lo = (int64_t)t * A.tile;
-  const int64_t hi = lo + A.tile < A.n ? lo + A.tile : A.n;
-  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
-    uint32_t K;
+  const int64_t v0 = (int64_t)blockIdx.x * kThreads + (threadIdx.x & ~63);
+  const int64_t v = v0 + (threadIdx.x & 63);
+  bool has = false;
+  uint32_t K = 0;
+  int64_t c = 0;
+  if (v < A.n) {
     int32_t b;
-    if (kp_element(A, (int32_t)v, K, b) && A.crit[K] == b) atomicAdd(&accl[K], A.vwgt[v]);
+    if (kp_element(A, (int32_t)v, K, b) && A.crit[K] == b) {
+      has = true;
+      c = A.vwgt[v];
+    }
   }
-  __syncthreads();
-  for (int c = threadIdx.x; c < A.ncodes; c += kThreads)
-    A.tsum[(size_t)c * A.ntiles + t] = accl[c];
+  const int32_t t = (int32_t)(v0 / A.tile);
+  int32_t *tsum = A.tsum;
+  const int32_t ntiles = A.ntiles;
+  wave_keyed_add(has, K, c, [=](uint32_t k) { return &tsum[(size_t)k * ntiles + t]; });
 }
 
-// one wave per key: the critical tile and the budget left inside it
+// one wave per key: the critical tile and the budget left inside it; clears
+// the key's row of tile sums for the next round
 __global__ __launch_bounds__(kThreads) void k_kp_tilecrit(KPArgs A) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int32_t K = blockIdx.x * (kThreads / 64) + wave;
@@ -992,10 +1086,13 @@ __global__ __launch_bounds__(kThreads) void k_kp_tilecrit(KPArgs A) {
   if (cb < 0 || cb >= kBuckets) return;
   const int64_t need = A.need[K];
   int64_t base = 0;
-  const int32_t *row = A.tsum + (size_t)K * A.ntiles;
+  bool found = false;
+  int32_t *row = A.tsum + (size_t)K * A.ntiles;
   for (int32_t t0 = 0; t0 < A.ntiles; t0 += 64) {
     const int32_t t = t0 + lane;
     const int64_t x = t < A.ntiles ? row[t] : 0;
+    if (x) row[t] = 0;
+    if (found) continue;
     int64_t incl = x;
     for (int o = 1; o < 64; o <<= 1) {
       const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
@@ -1008,29 +1105,38 @@ __global__ __launch_bounds__(kThreads) void k_kp_tilecrit(KPArgs A) {
         A.tcrit[K] = t;
         A.tneed[K] = need - (base + incl - x);
       }
-      return;
+      found = true;
+      continue;
     }
     base += gshfl64<64>(incl, 63);
   }
-  if (lane == 0) A.tcrit[K] = A.ntiles;  // every critical member passes
+  if (!found && lane == 0) A.tcrit[K] = A.ntiles;  // every critical member passes
 }
 
+// Outcome of element v (key K, bucket b).  Returns in (has, akey, aval) the
+// weight the outcome adds to a keyed accumulator: in a strong selection the
+// bucket weights of the destination, in an acceptance the accepted weight.
 __device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t K, int32_t b,
-                                           bool pass) {
+                                           bool pass, bool &has, uint32_t &akey, int64_t &aval) {
   if (A.pass == KP_SELECT) {
     if (pass) {
       const int32_t d = A.dest[v];
       A.moved[v] = 1;
       A.target[v] = d;
-      if (A.strong) bw_add(A.bw, A.ncodes, (uint32_t)d, b, A.vwgt[v]);
+      if (A.strong) {
+        has = true;
+        akey = ((uint32_t)d << 6) | (uint32_t)b;
+        aval = A.vwgt[v];
+      }
     } else {
       A.moved[v] = 0;
     }
   } else {
     if (pass) {
-      atomicAdd((unsigned long long *)&A.acc[(size_t)(blockIdx.x & (kBucketStripes - 1)) * A.ncodes + K],
-                (unsigned long long)(int64_t)A.vwgt[v]);
       A.reject[v] = 0;
+      has = true;
+      akey = K;
+      aval = A.vwgt[v];
     } else {
       A.moved[v] = 0;
       A.reject[v] = 1;
@@ -1038,63 +1144,100 @@ __device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t 
   }
 }
 
-// one workgroup per tile: final pass/fail of every element in the tile
+// The keyed adds of a wave (every lane of the wave calls it).
+__device__ __forceinline__ void kp_flush(const KPArgs &A, bool has, uint32_t akey, int64_t aval) {
+  const size_t stripe = blockIdx.x & (kBucketStripes - 1);
+  if (A.pass == KP_SELECT) {
+    int64_t *bw = A.bw + stripe * (size_t)A.ncodes * kBuckets;
+    wave_keyed_add(has, akey, aval, [=](uint32_t k) { return &bw[k]; });
+  } else {
+    int64_t *acc = A.acc + stripe * (size_t)A.ncodes;
+    wave_keyed_add(has, akey, aval, [=](uint32_t k) { return &acc[k]; });
+  }
+}
+
+// Per-vertex pass: the outcome of every element except the members of a key
+// inside that key's critical tile (those are left to k_kp_walk).
 __global__ __launch_bounds__(kThreads) void k_kp_decide(KPArgs A) {
-  extern __shared__ int64_t run[];
-  const int32_t t = blockIdx.x;
-  const int delta = A.pass == KP_SELECT ? 0 : 1;
-  for (int c = threadIdx.x; c < A.ncodes; c += kThreads) run[c] = 0;
-  const int64_t lo = (int64_t)t * A.tile;
-  const int64_t hi = lo + A.tile < A.n ? lo + A.tile : A.n;
-  // everything but the members of a key whose critical tile is this one
-  for (int64_t v = lo + threadIdx.x; v < hi; v += kThreads) {
+  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  bool has = false;
+  uint32_t akey = 0;
+  int64_t aval = 0;
+  if (v < A.n) {
     uint32_t K;
     int32_t b;
     if (!kp_element(A, (int32_t)v, K, b)) {
       if (A.pass == KP_SELECT) A.moved[v] = 0;
       else A.reject[v] = 0;
-      continue;
-    }
-    const int32_t cb = A.crit[K];
-    if (b != cb) {
-      kp_outcome(A, (int32_t)v, K, b, b < cb);
-      continue;
-    }
-    const int32_t tc = A.tcrit[K];
-    if (tc != t) kp_outcome(A, (int32_t)v, K, b, tc > t);
-  }
-  __syncthreads();
-  // members in this critical tile: id-ordered prefix per key, by wave 0
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x;
-  for (int64_t base = lo; base < hi; base += 64) {
-    const int64_t v = base + lane;
-    uint32_t K = 0;
-    int32_t b = 0;
-    bool mine = false;
-    int64_t c = 0;
-    if (v < hi && kp_element(A, (int32_t)v, K, b) && A.crit[K] == b && A.tcrit[K] == t) {
-      mine = true;
-      c = A.vwgt[v];
-    }
-    unsigned long long left = __ballot(mine);
-    while (left) {
-      const int leader = __ffsll((long long)left) - 1;
-      const uint32_t LK = (uint32_t)__shfl((int32_t)K, leader, 64);
-      const bool in = mine && K == LK;
-      const unsigned long long grp = __ballot(in);
-      int64_t x = in ? c : 0;
-      int64_t incl = x;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
-        if (lane >= o) incl += y;
+    } else {
+      const int32_t cb = A.crit[K];
+      if (b != cb) {
+        kp_outcome(A, (int32_t)v, K, b, b < cb, has, akey, aval);
+      } else {
+        const int32_t t = (int32_t)(v / A.tile);
+        const int32_t tc = A.tcrit[K];
+        if (tc != t) kp_outcome(A, (int32_t)v, K, b, tc > t, has, akey, aval);
       }
-      const int64_t before = run[LK];
-      if (in) kp_outcome(A, (int32_t)v, K, b, before + (incl - x) + delta * c < A.tneed[K]);
-      const int64_t tot = gshfl64<64>(incl, 63);
-      if (lane == 0) run[LK] = before + tot;
-      left &= ~grp;
     }
+  }
+  kp_flush(A, has, akey, aval);
+}
+
+// One workgroup per key with a critical tile: the members of the key's
+// critical bucket inside that tile, in id order.  The tile is taken in
+// chunks of 4096 ids, 16 consecutive ids per thread: member weights into
+// registers, a workgroup exclusive scan, then every thread decides its
+// members in order.
+constexpr int kWalkPer = 16;
+constexpr int kWalkChunk = kWalkPer * kThreads;
+__global__ __launch_bounds__(kThreads) void k_kp_walk(KPArgs A) {
+  __shared__ BlockScratch sc;
+  __shared__ uint32_t chunk_total;
+  const int32_t K = blockIdx.x;
+  const int32_t cb = A.crit[K];
+  if (cb < 0 || cb >= kBuckets) return;
+  const int32_t tc = A.tcrit[K];
+  if (tc >= A.ntiles) return;
+  const int64_t lo = (int64_t)tc * A.tile;
+  const int64_t hi = lo + A.tile < A.n ? lo + A.tile : A.n;
+  const int64_t need = A.tneed[K];
+  const int64_t delta = A.pass == KP_SELECT ? 0 : 1;
+  int64_t base = 0;  // member weight of the earlier chunks
+  for (int64_t c0 = lo; c0 < hi; c0 += kWalkChunk) {
+    const int64_t v0 = c0 + (int64_t)threadIdx.x * kWalkPer;
+    int32_t cw[kWalkPer];
+    uint32_t mem = 0;  // bit i: id v0 + i is a member
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kWalkPer; ++i) {
+      const int64_t v = v0 + i;
+      uint32_t Kv;
+      int32_t b;
+      cw[i] = 0;
+      if (v < hi && kp_element(A, (int32_t)v, Kv, b) && Kv == (uint32_t)K && b == cb) {
+        cw[i] = A.vwgt[v];
+        mem |= 1u << i;
+      }
+      sum += (uint32_t)cw[i];
+    }
+    const uint32_t excl = block_excl_scan(sum, sc);
+    if (threadIdx.x == kThreads - 1) chunk_total = excl + sum;
+    int64_t run = base + excl;
+#pragma unroll
+    for (int i = 0; i < kWalkPer; ++i) {
+      bool has = false;
+      uint32_t akey = 0;
+      int64_t aval = 0;
+      if (mem & (1u << i)) {
+        kp_outcome(A, (int32_t)(v0 + i), (uint32_t)K, cb, run + delta * cw[i] < need, has, akey,
+                   aval);
+        run += cw[i];
+      }
+      kp_flush(A, has, akey, aval);
+    }
+    __syncthreads();
+    base += chunk_total;
+    __syncthreads();  // chunk_total is rewritten by the next chunk
   }
 }
 
@@ -1194,6 +1337,7 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
   rb.rblock = ar.alloc_n<int32_t>(ncodes);
   fill_i64(rb.bw, 0, (int64_t)kBucketStripes * ncodes * kBuckets, s);
   fill_i64(rb.acc, 0, (int64_t)kBucketStripes * ncodes, s);
+  fill_i32(rb.tsum, 0, (int64_t)ncodes * (rb.ntiles > 0 ? rb.ntiles : 1), s);
   return rb;
 }
 
@@ -1201,12 +1345,15 @@ static void keyed_prefix(KPArgs A, hipStream_t s) {
   const unsigned waves_grid = (unsigned)((A.ncodes + (kThreads / 64) - 1) / (kThreads / 64));
   hipLaunchKernelGGL(k_kp_crit, dim3(waves_grid), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
-  if (A.ntiles <= 0) return;
-  hipLaunchKernelGGL(k_kp_tilesum, dim3(A.ntiles), dim3(kThreads), sizeof(int32_t) * A.ncodes, s, A);
+  if (A.n <= 0) return;
+  const unsigned flat = grid_for(A.n);
+  hipLaunchKernelGGL(k_kp_tilesum, dim3(flat), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_kp_tilecrit, dim3(waves_grid), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_kp_decide, dim3(A.ntiles), dim3(kThreads), sizeof(int64_t) * A.ncodes, s, A);
+  hipLaunchKernelGGL(k_kp_decide, dim3(flat), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_kp_walk, dim3(A.ncodes), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
 }
 
