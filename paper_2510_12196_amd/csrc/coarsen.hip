@@ -67,40 +67,41 @@ struct HemArgs {
   int32_t *pref;
 };
 
-__device__ __forceinline__ Cand hem_arc(const HemArgs &A, int32_t v, int32_t cv, int64_t e) {
-  Cand c{-1, 0, 1, 0};
-  const int32_t u = A.g.adj[e];
-  if (A.match[u] >= 0) return c;
-  const int32_t cu = A.g.c[u];
-  if ((int64_t)cu + cv > A.lmax) return c;
-  const uint32_t lo = (uint32_t)(u < v ? u : v), hi = (uint32_t)(u < v ? v : u);
-  c.u = u;
-  c.w = A.g.w[e];
-  c.cu = cu;
-  c.h = mix_hash(A.hseed, ((uint64_t)lo << 32) | hi);
-  return c;
-}
+struct HemN {
+  int32_t u, mu, cu, w;
+};
 
-template <int G>
+template <int G, int V>
 __device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) {
-  int32_t v;
-  if (!group_vertex<G>(A.cl, cls, local, v)) return;
-  const int lane = threadIdx.x % G;
-  if (A.match[v] >= 0) {
-    if (lane == 0) A.pref[v] = -1;
-    return;
-  }
-  const int64_t e = A.g.xadj[v] + lane;
-  Cand c{-1, 0, 1, 0};
-  if (e < A.g.xadj[v + 1]) c = hem_arc(A, v, A.g.c[v], e);
-  cand_reduce<G>(c, v);
-  if (lane == 0) A.pref[v] = c.u;
+  group_tiles<G, V>(
+      A.g.xadj, A.g.adj, A.cl, cls, local,
+      [&](int32_t v, bool &act) {
+        act = A.match[v] < 0;
+        return A.g.c[v];
+      },
+      [&](int32_t u, int64_t e) { return HemN{u, A.match[u], A.g.c[u], A.g.w[e]}; },
+      [&](int, bool ok, int32_t v, int32_t cv, bool act, int, bool valid, const HemN &a) {
+        if (!ok) return;
+        const int lane = threadIdx.x % G;
+        if (!act) {
+          if (lane == 0) A.pref[v] = -1;
+          return;
+        }
+        Cand c{-1, 0, 1, 0};
+        if (valid && a.mu < 0 && (int64_t)a.cu + cv <= A.lmax) {
+          const uint32_t lo = (uint32_t)(a.u < v ? a.u : v), hi = (uint32_t)(a.u < v ? v : a.u);
+          c = Cand{a.u, a.w, a.cu, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+        }
+        cand_reduce<G>(c, v);
+        if (lane == 0) A.pref[v] = c.u;
+      });
 }
 
 struct CandScratch {
   Cand c[kThreads / 64];
 };
 
+template <int V>
 __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
   __shared__ CandScratch sc;
   {  // one class tile per workgroup
@@ -108,16 +109,13 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
-      case CLS_ISO: {
-        const int idx = local * kThreads + threadIdx.x;
-        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
-          A.pref[A.cl.list[A.cl.off[CLS_ISO] + idx]] = -1;
+      case CLS_ISO:
+        iso_tiles<V>(A.cl, local, [&](int32_t v) { A.pref[v] = -1; });
         break;
-      }
-      case CLS_G8: hem_group<8>(A, cls, local); break;
-      case CLS_G16: hem_group<16>(A, cls, local); break;
-      case CLS_G32: hem_group<32>(A, cls, local); break;
-      case CLS_G64: hem_group<64>(A, cls, local); break;
+      case CLS_G8: hem_group<8, V>(A, cls, local); break;
+      case CLS_G16: hem_group<16, V>(A, cls, local); break;
+      case CLS_G32: hem_group<32, V>(A, cls, local); break;
+      case CLS_G64: hem_group<64, V>(A, cls, local); break;
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         if (A.match[v] >= 0) {
@@ -157,22 +155,30 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s) {
-  const unsigned nwg = classed_grid(cl);
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);
+  const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  HemArgs A{g, cl, lmax, hseed, match, pref};
+  HemArgs A{g, tc, lmax, hseed, match, pref};
+  auto kern = V == 2 ? k_hem_prefer<2> : k_hem_prefer<1>;
   if (tl_timer) {
     hipEvent_t a, b;
     tl_timer->pair(KT_HEM, a, b);
-    hipExtLaunchKernelGGL(k_hem_prefer, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+    hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
   } else {
-    hipLaunchKernelGGL(k_hem_prefer, dim3(nwg), dim3(kThreads), 0, s, A);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
   }
   PM_LAUNCH_CHECK();
 }
 
-// v and pref[v] are matched iff they prefer each other.
+// v and pref[v] are matched iff they prefer each other.  Every workgroup adds
+// (1 << 32) + its match count to one 64-bit counter; the workgroup that
+// completes the count (high half = grid size) stores st->count, clears the
+// counter and publishes.  A single atomic carries both the data and the
+// completion, so no fence is needed.
 __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
-                                                         int32_t *match, int64_t *stripes) {
+                                                         int32_t *match, uint64_t *counter,
+                                                         Status *st, Pub pub) {
   __shared__ BlockScratch sc;
   int64_t hits = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -185,18 +191,25 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
     }
   }
   hits = block_sum64(hits, sc);
-  if (threadIdx.x == 0) stripe_add(stripes, hits);
+  if (threadIdx.x == 0) {
+    const uint64_t add = (1ull << 32) + (uint64_t)hits;
+    const uint64_t now = atomicAdd((unsigned long long *)counter, (unsigned long long)add) + add;
+    if ((now >> 32) == gridDim.x) {
+      st->count = (int32_t)(now & 0xFFFFFFFFull);
+      atomicExch((unsigned long long *)counter, 0ull);
+      __threadfence();
+      publish_dev(st, pub);
+    }
+  }
 }
 
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes, Status *st,
-                hipStream_t s) {
-  if (n > 0) {
-    unsigned g = grid_for(n);
-    if (g > kMaxGrid) g = kMaxGrid;
-    hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, stripes);
-    PM_LAUNCH_CHECK();
-  }
-  fold_stripes(stripes, nullptr, &st->count, s);
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
+                const Pub &pub, hipStream_t s) {
+  unsigned g = grid_for(n > 0 ? n : 1);
+  if (g > kMaxGrid) g = kMaxGrid;
+  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st,
+                     pub);
+  PM_LAUNCH_CHECK();
 }
 
 // unmatched -> self; leader flag (the smaller member of a pair, or a single)

@@ -194,4 +194,67 @@ __device__ __forceinline__ bool group_vertex(const Classes &cl, int cls, int loc
 // Sum over the arcs of one vertex weighted by the lane group convention:
 // inside a G-group lane j owns arc xadj[v]+j (deg <= G by construction).
 
+// ISO tiles: V vertices per thread.
+template <int V, class F>
+__device__ __forceinline__ void iso_tiles(const Classes &cl, int local, F f) {
+  const int cnt = cl.off[CLS_ISO + 1] - cl.off[CLS_ISO];
+#pragma unroll
+  for (int r = 0; r < V; ++r) {
+    const int idx = (local * V + r) * kThreads + threadIdx.x;
+    if (idx < cnt) f(cl.list[cl.off[CLS_ISO] + idx]);
+  }
+}
+
+// ---- staged tiles: V vertices per lane group -------------------------------
+// A tile of class cls (G lanes per vertex, deg <= G) holds V * (kThreads / G)
+// vertices; lane group q handles slots r = 0..V-1, vertex index
+// (local * V + r) * (kThreads / G) + q of the class list.  The loads of the V
+// slots are issued level by level -- list entries; vload(v, act) and the row
+// bounds; the arc (adj, then nload(u, e)) of every active slot -- before any
+// slot is used, so that V dependent chains are in flight together.  use(r,
+// ok, v, vv, act, deg, valid, nv) runs per slot r with ok = the slot holds a
+// vertex, valid = this lane holds an arc of an active vertex; every lane of
+// the workgroup reaches it for every slot (group shuffles are allowed).
+template <int G, int V, class VL, class NL, class U>
+__device__ __forceinline__ void group_tiles(const int64_t *xadj, const int32_t *adj,
+                                            const Classes &cl, int cls, int local, VL vload,
+                                            NL nload, U use) {
+  constexpr int GPW = kThreads / G;
+  const int lane = threadIdx.x % G, grp = threadIdx.x / G;
+  const int cnt = cl.off[cls + 1] - cl.off[cls];
+  const int32_t *list = cl.list + cl.off[cls];
+  int32_t v[V];
+  bool ok[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) {
+    const int idx = (local * V + r) * GPW + grp;
+    ok[r] = idx < cnt;
+    v[r] = ok[r] ? list[idx] : 0;
+  }
+  decltype(vload(0, ok[0])) vv[V];
+  bool act[V];
+  int64_t beg[V];
+  int deg[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) {
+    act[r] = false;
+    deg[r] = 0;
+    beg[r] = 0;
+    if (ok[r]) {
+      vv[r] = vload(v[r], act[r]);
+      beg[r] = xadj[v[r]];
+      deg[r] = (int)(xadj[v[r] + 1] - beg[r]);
+    }
+  }
+  decltype(nload(0, (int64_t)0)) nv[V];
+  bool valid[V];
+#pragma unroll
+  for (int r = 0; r < V; ++r) {
+    valid[r] = act[r] && lane < deg[r];
+    if (valid[r]) nv[r] = nload(adj[beg[r] + lane], beg[r] + lane);
+  }
+#pragma unroll
+  for (int r = 0; r < V; ++r) use(r, ok[r], v[r], vv[r], act[r], deg[r], valid[r], nv[r]);
+}
+
 }  // namespace pm

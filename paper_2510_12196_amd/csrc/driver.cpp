@@ -79,8 +79,11 @@ struct Ctx {
   Status *mirror_dev = nullptr;
   int64_t *seq_dev = nullptr;
   const volatile int64_t *seq_host = nullptr;
+  uint64_t *counter = nullptr;  // completion counter of the matching commit
   explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
     dev = ar.alloc_n<Status>(1);
+    counter = ar.alloc_n<uint64_t>(1);
+    PM_HIP(hipMemsetAsync(counter, 0, sizeof(uint64_t), s));
     host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
     void *mdev = nullptr;
     char *m = static_cast<char *>(ar.host_mapped(&mdev));
@@ -93,13 +96,19 @@ struct Ctx {
     PM_HIP(hipMemsetAsync(dev, 0, sizeof(Status), s));
     PM_HIP(hipMemsetAsync(sp.a, 0, sizeof(int64_t) * 2 * (size_t)stripe_words(), s));
   }
-  // Status read-back: a one-thread kernel publishes the status into mapped
-  // host memory and the host polls its sequence number, which returns sooner
-  // than a copy plus a stream synchronisation.  A stream that fails or goes
-  // idle without publishing raises PM_EHIP.
+  // Status read-back: a kernel publishes the status into mapped host memory
+  // and the host polls its sequence number, which returns sooner than a copy
+  // plus a stream synchronisation.  next_pub() names a publication for a
+  // kernel that ends a step; wait() blocks until it has happened.  A stream
+  // that fails or goes idle without publishing raises PM_EHIP.
+  Pub next_pub() { return Pub{mirror_dev, seq_dev, ar.next_publish()}; }
   void pull() {
-    const int64_t seq = ar.next_publish();
-    publish_status(dev, mirror_dev, seq_dev, seq, s);
+    const Pub p = next_pub();
+    publish_status(dev, mirror_dev, seq_dev, p.seq, s);
+    wait(p);
+  }
+  void wait(const Pub &p) {
+    const int64_t seq = p.seq;
     for (uint64_t it = 1;; ++it) {
       if (__atomic_load_n(seq_host, __ATOMIC_ACQUIRE) == seq) break;
       __builtin_ia32_pause();
@@ -161,8 +170,15 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   fill_u8(lock, 0, n, s);
   block_weights(g, h, cur, w, s);
   comm_cost(g, cl, h, cur, cx.sp.a, cx.dev, s);
-  max_block(h, w, nullptr, cx.dev, s);
-  cx.pull();
+  // step epilogue: heaviest block, J change, eligible destinations, publication
+  StepEnd E{h, w, cx.sp.a, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev, {}};
+  {
+    StepEnd E0 = E;
+    E0.dj_stripes = nullptr;
+    E0.pub = cx.next_pub();
+    step_status(E0, s);
+    cx.wait(E0.pub);
+  }
   int64_t j_cur = cx.host->j, imb_cur = cx.host->maxw;
   if (n == 0) imb_cur = 0;
   int64_t j_best = j_cur, imb_best = imb_cur;
@@ -177,10 +193,11 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   while (i < 12 && bodies < 4096) {
     ++i;
     ++bodies;
+    E.pub = cx.next_pub();
     if (imb_cur <= lmax) {
       lp_phase1(g, cl, h, cur, lock, target, gain, s);
       lp_phase2(g, cl, h, cur, target, gain, moved, s);
-      apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, s);
+      apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, &E, s);
       iw = 0;
       ++R.st.lp_iterations;
     } else {
@@ -188,7 +205,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
       rebalance_round(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
                       cx.dev, s);
-      apply_moves(g, cl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, s);
+      apply_moves(g, cl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, &E, s);
       if (strong) {
         iw = 0;
         ++R.st.strong_iterations;
@@ -197,8 +214,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         ++R.st.weak_iterations;
       }
     }
-    max_block(h, w, cx.sp.a, cx.dev, s);
-    cx.pull();
+    cx.wait(E.pub);
     j_cur += cx.host->dj;
     imb_cur = cx.host->maxw;
     if (imb_cur <= lmax) {
@@ -268,8 +284,9 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   while (rounds < 64) {
     ++rounds;
     hem_prefer(g, L.cl, lmax, hseed, match, pref, s);
-    hem_commit(g.n, pref, match, cx.sp.b, cx.dev, s);
-    cx.pull();
+    const Pub pub = cx.next_pub();
+    hem_commit(g.n, pref, match, cx.counter, cx.dev, pub, s);
+    cx.wait(pub);
     const int32_t added = cx.host->count;
     matched += added;
     if (added == 0) break;
@@ -489,7 +506,7 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t
     lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s);
     lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
     apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w,
-                alloc_weight_stripes(*lease, hh, s), cx.sp.a, s);
+                alloc_weight_stripes(*lease, hh, s), cx.sp.a, nullptr, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     codes_to_ids(hh, target_out, target_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
@@ -522,12 +539,15 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
     int32_t *target = ar.alloc_n<int32_t>(n);
     RebalanceBuffers rb = alloc_rebalance(ar, n, hh, s);
     block_weights(dg, hh, codes, w, s);
+    step_status(
+        StepEnd{hh, w, nullptr, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev, Pub{nullptr, nullptr, 0}},
+        s);
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
                     moved_out, rb, cx.dev, s);
     apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s),
-                cx.sp.a, s);
+                cx.sp.a, nullptr, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;

@@ -12,11 +12,55 @@ struct Status {
   int64_t j;           // full J (comm_cost)
   int32_t count;       // generic counter (matches, sources, ...)
   int32_t count2;
-  int32_t n_eligible;  // blocks within the rebalancing cap
-  int32_t pad_;
+  int32_t n_elig_weak;   // blocks within the weak rebalancing cap (sigma)
+  int32_t n_elig_strong; // blocks within L_max
   int64_t resid_total; // strong rebalancing: total residual capacity
   int64_t aux;         // generic 64-bit result
 };
+
+// A status publication: the kernel that ends a step copies the Status into
+// mapped host memory (host, device view) and then stores seq into seq_slot;
+// the host polls seq_slot.  host == nullptr: no publication.
+struct Pub {
+  Status *host;
+  int64_t *seq_slot;
+  int64_t seq;
+};
+
+// End of a refinement step, run by one workgroup of the commit: the heaviest
+// block, the J change, the blocks eligible as rebalancing destinations for
+// the next step, then the publication.
+struct StepEnd {
+  Hier h;
+  const int64_t *w;      // block weights (final when the epilogue runs)
+  int64_t *dj_stripes;   // folded into st->dj (nullptr: st->dj untouched)
+  int64_t sigma, lmax;   // caps of weak and strong rebalancing
+  int32_t *elig_weak;    // blocks with w <= sigma, ascending
+  int32_t *elig_strong;  // blocks with w <= L_max, ascending
+  Status *st;
+  Pub pub;
+};
+// StepEnd alone, as one workgroup (the start of a level).
+void step_status(const StepEnd &E, hipStream_t s);
+
+// ---- device helpers for the epilogues ----------------------------------------
+// load through the device-coherent level (skips a possibly stale CU cache)
+__device__ __forceinline__ int64_t agent_load(const int64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t agent_load(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Thread 0 copies the status words to the host mirror, then releases seq.
+// The caller orders the status stores before (fence + barrier).
+__device__ __forceinline__ void publish_dev(const Status *st, const Pub &p) {
+  if (!p.host || threadIdx.x != 0) return;
+  const int64_t *src = reinterpret_cast<const int64_t *>(st);
+  int64_t *dst = reinterpret_cast<int64_t *>(p.host);
+  for (size_t i = 0; i < sizeof(Status) / sizeof(int64_t); ++i) dst[i] = agent_load(src + i);
+  __threadfence_system();
+  __hip_atomic_store(p.seq_slot, p.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // Striped accumulator buffers of one call (kStripes x 16 int64 each, zeroed
 // at creation and by every fold).
@@ -28,8 +72,10 @@ struct Stripes {
 // seq into *seq_dev, all with system-scope visibility.
 void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
                     hipStream_t s);
-// Adds up the stripes into *out64 (if non-null) or *out32, clears them.
-void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s);
+// Adds up the stripes into *out64 (if non-null) or *out32, clears them;
+// publishes if pub.host.
+void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s,
+                  const Pub &pub = Pub{nullptr, nullptr, 0}, const Status *st = nullptr);
 int stripe_words();
 unsigned classed_grid(const Classes &cl);   // one tile per workgroup
 unsigned capped_grid(const Classes &cl);    // at most kMaxGrid workgroups
@@ -54,6 +100,12 @@ extern thread_local KernelTimer *tl_timer;
 Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
                       Status *st_host, hipStream_t s);
 int32_t classes_workgroups(const Classes &cl);
+// The same classes laid out as tiles of V vertices per lane group (ISO: V
+// per thread); BIG keeps one vertex per workgroup.
+Classes tiled(const Classes &cl, int V);
+// Vertices per lane group of the staged kernels: 1 (PM_GROUP_V=2 selects
+// 2).
+int group_v();
 
 // ---- mapping conversion ---------------------------------------------------
 void ids_to_codes(const Hier &h, const int32_t *ids, int32_t *codes, int32_t n, hipStream_t s);
@@ -67,8 +119,6 @@ void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
                int64_t *stripes, Status *st, hipStream_t s);   // st->j = J
 void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
                    hipStream_t s);                     // w[0..2^bits)
-// st->maxw = heaviest block; if dj_stripes, also folds them into st->dj
-void max_block(const Hier &h, const int64_t *w, int64_t *dj_stripes, Status *st, hipStream_t s);
 
 // ---- label propagation (Algorithm 4) --------------------------------------
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
@@ -78,11 +128,14 @@ void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
 // dj_stripes and the block weight changes into w (through the weight-delta
 // stripes wst, zero on entry and on return); sets lock = moved if lock != 0.
+// With end != nullptr the commit's last workgroup runs the StepEnd epilogue
+// (end->w must be w, end->dj_stripes dj_stripes).
 constexpr int kWeightStripes = 32;
+int weight_stripes(const Hier &h);   // stripes in use for h (power of two)
 int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, hipStream_t s);
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
 struct RebalanceBuffers {
@@ -90,7 +143,8 @@ struct RebalanceBuffers {
   int32_t *dest;       // n: chosen destination
   uint8_t *reject;     // n: strong rounds, movers refused by their destination
   int64_t *pre;        // n: exclusive weight prefix of the refused movers
-  int32_t *elig;       // 2^bits: blocks within the cap, ascending
+  int32_t *elig_weak;  // 2^bits: blocks within sigma, ascending
+  int32_t *elig_strong;// 2^bits: blocks within L_max, ascending
   int64_t *bw;         // 8 x 2^bits x 64 bucket weights (kept zero between rounds)
   int64_t *acc;        // 8 x 2^bits accepted weights (kept zero between rounds)
   int32_t *crit;       // 2^bits
@@ -105,7 +159,9 @@ struct RebalanceBuffers {
 };
 RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_t s);
 // One weak/strong rebalancing round: writes moved/target for every vertex,
-// ready for apply_moves.  No host synchronisation.
+// ready for apply_moves.  The eligible destinations (rb.elig_*, counts in
+// *st_dev) must be those of the current weights (StepEnd / step_status).  No
+// host synchronisation.
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
@@ -114,8 +170,10 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s);
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int64_t *stripes, Status *st,
-                hipStream_t s);   // st->count = new matches
+// st->count = new matches, then the publication pub.  counter: 64-bit
+// completion counter, zero between launches.
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
+                const Pub &pub, hipStream_t s);
 // Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched
 // vertices and pairs each group in id order.  Returns the vertices matched.
 // Synchronises the stream.

@@ -12,6 +12,8 @@
 // do not depend on thread scheduling or on the order of entries in a row.
 #include <hip/hip_ext.h>
 
+#include <cstdlib>
+
 #include "device_util.h"
 #include "kernels.h"
 #include "prim.h"
@@ -48,19 +50,12 @@ void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill(p, v, n, s
 // status read-back: one thread copies the status words into mapped host
 // memory, then releases the sequence number the host is polling
 // ===========================================================================
-__global__ void k_publish(const Status *dev, Status *host, int64_t *seq_slot, int64_t seq) {
-  if (threadIdx.x != 0) return;
-  const int64_t *src = reinterpret_cast<const int64_t *>(dev);
-  int64_t *dst = reinterpret_cast<int64_t *>(host);
-  for (size_t i = 0; i < sizeof(Status) / sizeof(int64_t); ++i) dst[i] = src[i];
-  __threadfence_system();
-  __hip_atomic_store(seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
+__global__ void k_publish(const Status *dev, Pub pub) { publish_dev(dev, pub); }
 static_assert(sizeof(Status) % sizeof(int64_t) == 0, "Status is copied in 8-byte words");
 
 void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, dev, host_dev, seq_dev, seq);
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, dev, Pub{host_dev, seq_dev, seq});
   PM_LAUNCH_CHECK();
 }
 
@@ -117,6 +112,26 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
 
 int32_t classes_workgroups(const Classes &cl) { return cl.wg[NCLS]; }
 
+Classes tiled(const Classes &cl, int V) {
+  Classes t = cl;
+  t.wg[0] = 0;
+  for (int c = 0; c < NCLS; ++c) {
+    const int cnt = cl.off[c + 1] - cl.off[c];
+    const int per = class_per_wg(c) * (c == CLS_BIG ? 1 : V);
+    t.wg[c + 1] = t.wg[c] + (cnt + per - 1) / per;
+  }
+  return t;
+}
+
+int group_v() {
+  static const int v = [] {
+    const char *e = std::getenv("PM_GROUP_V");
+    const int x = e ? std::atoi(e) : 1;
+    return x == 2 ? 2 : 1;
+  }();
+  return v;
+}
+
 // ===========================================================================
 // id <-> code conversion
 // ===========================================================================
@@ -172,21 +187,31 @@ void check_ids(const Hier &h, const int32_t *ids, int32_t n, int64_t *stripes, S
 // ===========================================================================
 // striped accumulators
 // ===========================================================================
-__global__ __launch_bounds__(kThreads) void k_fold(int64_t *stripes, int64_t *out64,
-                                                   int32_t *out32) {
+// One workgroup; used standalone (k_fold) and as the last workgroup of a
+// producer kernel.
+__device__ __forceinline__ void fold_block(int64_t *stripes, int64_t *out64, int32_t *out32,
+                                           const Pub &pub, const Status *st) {
   __shared__ BlockScratch sc;
-  int64_t x = stripes[threadIdx.x * kStripeStride];
+  int64_t x = agent_load(&stripes[threadIdx.x * kStripeStride]);
   stripes[threadIdx.x * kStripeStride] = 0;
   x = block_sum64(x, sc);
   if (threadIdx.x == 0) {
     if (out64) *out64 = x;
     else *out32 = (int32_t)x;
+    __threadfence();
+    if (st) publish_dev(st, pub);
   }
 }
-static_assert(kStripes == kThreads, "one stripe per thread in k_fold");
+static_assert(kStripes == kThreads, "one stripe per thread in the folds");
 
-void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s) {
-  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kThreads), 0, s, stripes, out64, out32);
+__global__ __launch_bounds__(kThreads) void k_fold(int64_t *stripes, int64_t *out64,
+                                                   int32_t *out32, Pub pub, const Status *st) {
+  fold_block(stripes, out64, out32, pub, st);
+}
+
+void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s,
+                  const Pub &pub, const Status *st) {
+  hipLaunchKernelGGL(k_fold, dim3(1), dim3(kThreads), 0, s, stripes, out64, out32, pub, st);
   PM_LAUNCH_CHECK();
 }
 int stripe_words() { return kStripeWords; }
@@ -288,25 +313,51 @@ void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t 
   PM_LAUNCH_CHECK();
 }
 
-__global__ __launch_bounds__(kThreads) void k_max_block(const int64_t *w, int32_t ncodes,
-                                                        int64_t *dj_stripes, Status *st) {
-  __shared__ BlockScratch sc;
-  int64_t m = INT64_MIN;
-  for (int c = threadIdx.x; c < ncodes; c += kThreads) m = w[c] > m ? w[c] : m;
-  uint32_t dummy = 0;
-  block_argmax(m, dummy, sc);
-  if (threadIdx.x == 0) st->maxw = m;
-  if (dj_stripes) {
-    int64_t x = dj_stripes[threadIdx.x * kStripeStride];
-    dj_stripes[threadIdx.x * kStripeStride] = 0;
-    x = block_sum64(x, sc);
-    if (threadIdx.x == 0) st->dj = x;
-  }
+// Blocks with w <= cap, ascending, into list; count into *count.
+__device__ __forceinline__ void eligible_list(const Hier &h, const int64_t *w, int64_t cap,
+                                              int32_t *list, int32_t *count, BlockScratch &sc) {
+  const int32_t ncodes = 1 << h.bits;
+  const int per = (ncodes + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per;
+  const int hi = lo + per < ncodes ? lo + per : ncodes;
+  uint32_t cnt = 0;
+  for (int c = lo; c < hi; ++c) cnt += (code_valid(h, (uint32_t)c) && agent_load(&w[c]) <= cap) ? 1u : 0u;
+  uint32_t pos = block_excl_scan(cnt, sc);
+  for (int c = lo; c < hi; ++c)
+    if (code_valid(h, (uint32_t)c) && agent_load(&w[c]) <= cap) list[pos++] = c;
+  if (threadIdx.x == kThreads - 1) *count = (int32_t)pos;
 }
 
-void max_block(const Hier &h, const int64_t *w, int64_t *dj_stripes, Status *st, hipStream_t s) {
-  hipLaunchKernelGGL(k_max_block, dim3(1), dim3(kThreads), 0, s, w, (int32_t)(1 << h.bits),
-                     dj_stripes, st);
+// The StepEnd epilogue, by one workgroup.
+__device__ __forceinline__ void step_epilogue(const StepEnd &E) {
+  __shared__ BlockScratch sc;
+  const int32_t ncodes = 1 << E.h.bits;
+  int64_t m = INT64_MIN;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
+    const int64_t x = agent_load(&E.w[c]);
+    m = x > m ? x : m;
+  }
+  uint32_t dummy = 0;
+  block_argmax(m, dummy, sc);
+  if (threadIdx.x == 0) E.st->maxw = m;
+  if (E.dj_stripes) {
+    int64_t x = agent_load(&E.dj_stripes[threadIdx.x * kStripeStride]);
+    E.dj_stripes[threadIdx.x * kStripeStride] = 0;
+    x = block_sum64(x, sc);
+    if (threadIdx.x == 0) E.st->dj = x;
+  }
+  eligible_list(E.h, E.w, E.sigma, E.elig_weak, &E.st->n_elig_weak, sc);
+  __syncthreads();
+  eligible_list(E.h, E.w, E.lmax, E.elig_strong, &E.st->n_elig_strong, sc);
+  __threadfence();
+  __syncthreads();
+  publish_dev(E.st, E.pub);
+}
+
+__global__ __launch_bounds__(kThreads) void k_step_status(StepEnd E) { step_epilogue(E); }
+
+void step_status(const StepEnd &E, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_status, dim3(1), dim3(kThreads), 0, s, E);
   PM_LAUNCH_CHECK();
 }
 
@@ -328,55 +379,58 @@ struct LP1Args {
   int64_t *gain;
 };
 
-template <int G>
+struct Lp1V {
+  uint32_t p;
+};
+struct Lp1N {
+  uint32_t bu;
+  int32_t wu;
+};
+
+template <int G, int V>
 __device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) {
-  int32_t v;
-  if (!group_vertex<G>(A.cl, cls, local, v)) return;
-  const int lane = threadIdx.x % G;
-  const uint32_t p = (uint32_t)A.part[v];
-  if (A.lock[v]) {
-    if (lane == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
-    }
-    return;
-  }
-  const int64_t beg = A.g.xadj[v];
-  const int deg = (int)(A.g.xadj[v + 1] - beg);
-  const bool valid = lane < deg;
-  uint32_t bu = p;
-  int32_t wu = 0;
-  if (valid) {
-    bu = (uint32_t)A.part[A.g.adj[beg + lane]];
-    wu = A.g.w[beg + lane];
-  }
-  const bool cand = valid && bu != p;
-  if (!gor<G>(cand ? 1 : 0)) {
-    if (lane == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
-    }
-    return;
-  }
-  const int64_t costp = gsum64<G>((int64_t)wu * dist(A.h, p, bu));
-  int64_t cost = 0;
-  for (int j = 0; j < deg; ++j) {
-    const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
-    const int32_t wj = gshfl<G>(wu, j);
-    cost += (int64_t)wj * dist(A.h, bu, bj);
-  }
-  int64_t g = cand ? costp - cost : INT64_MIN;
-  uint32_t b = cand ? bu : 0xFFFFFFFFu;
-  gargmax<G>(g, b);
-  if (lane == 0) {
-    if (g >= 0) {
-      A.target[v] = (int32_t)b;
-      A.gain[v] = g;
-    } else {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
-    }
-  }
+  group_tiles<G, V>(
+      A.g.xadj, A.g.adj, A.cl, cls, local,
+      [&](int32_t v, bool &act) {
+        act = !A.lock[v];
+        return Lp1V{(uint32_t)A.part[v]};
+      },
+      [&](int32_t u, int64_t e) { return Lp1N{(uint32_t)A.part[u], A.g.w[e]}; },
+      [&](int, bool ok, int32_t v, const Lp1V &vv, bool act, int deg, bool valid,
+          const Lp1N &nv) {
+        if (!ok) return;
+        const int lane = threadIdx.x % G;
+        const uint32_t p = vv.p;
+        const uint32_t bu = valid ? nv.bu : p;
+        const int32_t wu = valid ? nv.wu : 0;
+        const bool cand = valid && bu != p;
+        if (!act || !gor<G>(cand ? 1 : 0)) {
+          if (lane == 0) {
+            A.target[v] = (int32_t)p;
+            A.gain[v] = kNotInX;
+          }
+          return;
+        }
+        const int64_t costp = gsum64<G>((int64_t)wu * dist(A.h, p, bu));
+        int64_t cost = 0;
+        for (int j = 0; j < deg; ++j) {
+          const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+          const int32_t wj = gshfl<G>(wu, j);
+          cost += (int64_t)wj * dist(A.h, bu, bj);
+        }
+        int64_t g = cand ? costp - cost : INT64_MIN;
+        uint32_t b = cand ? bu : 0xFFFFFFFFu;
+        gargmax<G>(g, b);
+        if (lane == 0) {
+          if (g >= 0) {
+            A.target[v] = (int32_t)b;
+            A.gain[v] = g;
+          } else {
+            A.target[v] = (int32_t)p;
+            A.gain[v] = kNotInX;
+          }
+        }
+      });
 }
 
 // cost(c) from the exclusive prefix X over the connectivity histogram:
@@ -456,6 +510,7 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X
   }
 }
 
+template <int V>
 __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
@@ -464,19 +519,16 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
-      case CLS_ISO: {
-        const int idx = local * kThreads + threadIdx.x;
-        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+      case CLS_ISO:
+        iso_tiles<V>(A.cl, local, [&](int32_t v) {
           A.target[v] = A.part[v];
           A.gain[v] = kNotInX;
-        }
+        });
         break;
-      }
-      case CLS_G8: lp1_group<8>(A, cls, local); break;
-      case CLS_G16: lp1_group<16>(A, cls, local); break;
-      case CLS_G32: lp1_group<32>(A, cls, local); break;
-      case CLS_G64: lp1_group<64>(A, cls, local); break;
+      case CLS_G8: lp1_group<8, V>(A, cls, local); break;
+      case CLS_G16: lp1_group<16, V>(A, cls, local); break;
+      case CLS_G32: lp1_group<32, V>(A, cls, local); break;
+      case CLS_G64: lp1_group<64, V>(A, cls, local); break;
       default: lp1_big(A, local, X, sc); break;
     }
   }
@@ -486,16 +538,19 @@ static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << 
 
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s) {
-  const unsigned nwg = classed_grid(cl);
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);
+  const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP1Args A{g, cl, h, part, lock, target, gain};
+  LP1Args A{g, tc, h, part, lock, target, gain};
+  auto kern = V == 2 ? k_lp_phase1<2> : k_lp_phase1<1>;
   if (tl_timer) {
     hipEvent_t a, b;
     tl_timer->pair(KT_LP1, a, b);
     tl_timer->bytes[KT_LP1] += 12.0 * (double)g.nnz + 25.0 * (double)g.n;
-    hipExtLaunchKernelGGL(k_lp_phase1, dim3(nwg), dim3(kThreads), big_lds(h), s, a, b, 0, A);
+    hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, a, b, 0, A);
   } else {
-    hipLaunchKernelGGL(k_lp_phase1, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
   }
   PM_LAUNCH_CHECK();
 }
@@ -517,37 +572,45 @@ struct LP2Args {
   uint8_t *moved;
 };
 
-__device__ __forceinline__ int64_t lp2_arc(const LP2Args &A, int32_t v, int64_t gv, uint32_t p,
-                                           uint32_t t, int64_t e) {
-  const int32_t u = A.g.adj[e];
-  const int64_t gu = A.gain[u];
-  uint32_t pu = (uint32_t)A.part[u];
-  if (gu != kNotInX && (gu > gv || (gu == gv && u < v))) pu = (uint32_t)A.target[u];
-  return (int64_t)A.g.w[e] * (dist(A.h, p, pu) - dist(A.h, t, pu));
-}
-
 struct Lp2Arc {
   int32_t u, w, pu, tu;
   int64_t gu;
 };
 
-template <int G>
+struct Lp2V {
+  int64_t gv;
+  uint32_t p, t;
+};
+
+template <int G, int V>
 __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) {
-  int32_t v;
-  if (!group_vertex<G>(A.cl, cls, local, v)) return;
-  const int lane = threadIdx.x % G;
-  const int64_t gv = A.gain[v];
-  if (gv == kNotInX) {
-    if (lane == 0) A.moved[v] = 0;
-    return;
-  }
-  const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-  const int64_t e = A.g.xadj[v] + lane;
-  int64_t x = e < A.g.xadj[v + 1] ? lp2_arc(A, v, gv, p, t, e) : 0;
-  x = gsum64<G>(x);
-  if (lane == 0) A.moved[v] = x >= 0 ? 1 : 0;
+  group_tiles<G, V>(
+      A.g.xadj, A.g.adj, A.cl, cls, local,
+      [&](int32_t v, bool &act) {
+        const Lp2V x{A.gain[v], (uint32_t)A.part[v], (uint32_t)A.target[v]};
+        act = x.gv != kNotInX;
+        return x;
+      },
+      [&](int32_t u, int64_t e) { return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]}; },
+      [&](int, bool ok, int32_t v, const Lp2V &vv, bool act, int, bool valid, const Lp2Arc &a) {
+        if (!ok) return;
+        const int lane = threadIdx.x % G;
+        if (!act) {
+          if (lane == 0) A.moved[v] = 0;
+          return;
+        }
+        int64_t x = 0;
+        if (valid) {
+          uint32_t pu = (uint32_t)a.pu;
+          if (a.gu != kNotInX && (a.gu > vv.gv || (a.gu == vv.gv && a.u < v))) pu = (uint32_t)a.tu;
+          x = (int64_t)a.w * (dist(A.h, vv.p, pu) - dist(A.h, vv.t, pu));
+        }
+        x = gsum64<G>(x);
+        if (lane == 0) A.moved[v] = x >= 0 ? 1 : 0;
+      });
 }
 
+template <int V>
 __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
   __shared__ BlockScratch sc;
   {  // one class tile per workgroup
@@ -555,16 +618,13 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
-      case CLS_ISO: {
-        const int idx = local * kThreads + threadIdx.x;
-        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO])
-          A.moved[A.cl.list[A.cl.off[CLS_ISO] + idx]] = 0;
+      case CLS_ISO:
+        iso_tiles<V>(A.cl, local, [&](int32_t v) { A.moved[v] = 0; });
         break;
-      }
-      case CLS_G8: lp2_group<8>(A, cls, local); break;
-      case CLS_G16: lp2_group<16>(A, cls, local); break;
-      case CLS_G32: lp2_group<32>(A, cls, local); break;
-      case CLS_G64: lp2_group<64>(A, cls, local); break;
+      case CLS_G8: lp2_group<8, V>(A, cls, local); break;
+      case CLS_G16: lp2_group<16, V>(A, cls, local); break;
+      case CLS_G32: lp2_group<32, V>(A, cls, local); break;
+      case CLS_G64: lp2_group<64, V>(A, cls, local); break;
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const int64_t gv = A.gain[v];
@@ -595,15 +655,18 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
 
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s) {
-  const unsigned nwg = classed_grid(cl);
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);
+  const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP2Args A{g, cl, h, part, target, gain, moved};
+  LP2Args A{g, tc, h, part, target, gain, moved};
+  auto kern = V == 2 ? k_lp_phase2<2> : k_lp_phase2<1>;
   if (tl_timer) {
     hipEvent_t a, b;
     tl_timer->pair(KT_LP2, a, b);
-    hipExtLaunchKernelGGL(k_lp_phase2, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
+    hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
   } else {
-    hipLaunchKernelGGL(k_lp_phase2, dim3(nwg), dim3(kThreads), 0, s, A);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
   }
   PM_LAUNCH_CHECK();
 }
@@ -626,20 +689,10 @@ struct ApplyArgs {
   const int32_t *target;
   const uint8_t *moved;
   uint8_t *lock;
-  int64_t *wst;  // weight-delta stripes [kWeightStripes][ncodes]
+  int64_t *wst;  // weight-delta stripes [nstripes][ncodes]
+  int32_t nstripes;
   int64_t *dj;
 };
-
-__device__ __forceinline__ int64_t apply_arc(const ApplyArgs &A, uint32_t p, uint32_t t,
-                                             int64_t e) {
-  const int32_t u = A.g.adj[e];
-  const uint32_t old_u = (uint32_t)A.part[u];
-  if (A.moved[u]) {
-    const uint32_t new_u = (uint32_t)A.target[u];
-    return (int64_t)A.g.w[e] * (dist(A.h, t, new_u) - dist(A.h, p, old_u));
-  }
-  return 2 * (int64_t)A.g.w[e] * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
-}
 
 // block weight deltas go to the workgroup's LDS copy first
 __device__ __forceinline__ void apply_weights(const ApplyArgs &A, int32_t v, uint32_t p,
@@ -649,21 +702,38 @@ __device__ __forceinline__ void apply_weights(const ApplyArgs &A, int32_t v, uin
   atomicAdd(&dw[p], -c);
 }
 
-template <int G>
+struct ApV {
+  uint32_t p, t;
+};
+
+template <int G, int V>
 __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local,
                                                int32_t *dw) {
-  int32_t v;
-  if (!group_vertex<G>(A.cl, cls, local, v)) return 0;
-  const int lane = threadIdx.x % G;
-  const uint8_t m = A.moved[v];
-  if (A.lock && lane == 0) A.lock[v] = m;
-  if (!m) return 0;
-  const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-  if (lane == 0) apply_weights(A, v, p, t, dw);
-  const int64_t e = A.g.xadj[v] + lane;
-  return e < A.g.xadj[v + 1] ? apply_arc(A, p, t, e) : 0;
+  int64_t x = 0;
+  group_tiles<G, V>(
+      A.g.xadj, A.g.adj, A.cl, cls, local,
+      [&](int32_t v, bool &act) {
+        act = A.moved[v] != 0;
+        return ApV{(uint32_t)A.part[v], (uint32_t)A.target[v]};
+      },
+      [&](int32_t u, int64_t e) {
+        return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+      },
+      [&](int, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, int4 a) {
+        if (!ok) return;
+        const int lane = threadIdx.x % G;
+        if (A.lock && lane == 0) A.lock[v] = act ? 1 : 0;
+        if (!act) return;
+        if (lane == 0) apply_weights(A, v, vv.p, vv.t, dw);
+        if (!valid) return;
+        const uint32_t old_u = (uint32_t)a.y;
+        if (a.w) x += (int64_t)a.x * (dist(A.h, vv.t, (uint32_t)a.z) - dist(A.h, vv.p, old_u));
+        else x += 2 * (int64_t)a.x * (dist(A.h, vv.t, old_u) - dist(A.h, vv.p, old_u));
+      });
+  return x;
 }
 
+template <int V>
 __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
   extern __shared__ int32_t dw[];
   __shared__ BlockScratch sc;
@@ -676,20 +746,17 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
     const int cls = find_class(A.cl, blk);
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
-      case CLS_ISO: {
-        const int idx = local * kThreads + threadIdx.x;
-        if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+      case CLS_ISO:
+        iso_tiles<V>(A.cl, local, [&](int32_t v) {
           const uint8_t m = A.moved[v];
           if (A.lock) A.lock[v] = m;
           if (m) apply_weights(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v], dw);
-        }
+        });
         break;
-      }
-      case CLS_G8: x += apply_group<8>(A, cls, local, dw); break;
-      case CLS_G16: x += apply_group<16>(A, cls, local, dw); break;
-      case CLS_G32: x += apply_group<32>(A, cls, local, dw); break;
-      case CLS_G64: x += apply_group<64>(A, cls, local, dw); break;
+      case CLS_G8: x += apply_group<8, V>(A, cls, local, dw); break;
+      case CLS_G16: x += apply_group<16, V>(A, cls, local, dw); break;
+      case CLS_G32: x += apply_group<32, V>(A, cls, local, dw); break;
+      case CLS_G64: x += apply_group<64, V>(A, cls, local, dw); break;
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint8_t m = A.moved[v];
@@ -716,26 +783,40 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
   x = block_sum64(x, sc);  // also orders the LDS weight deltas before the flush
   if (threadIdx.x == 0) stripe_add(A.dj, x);
   // every workgroup touches the same few blocks: spread the flush over stripes
-  int64_t *wst = A.wst + (size_t)(blockIdx.x & (kWeightStripes - 1)) * ncodes;
+  int64_t *wst = A.wst + (size_t)(blockIdx.x & (A.nstripes - 1)) * ncodes;
   for (int c = threadIdx.x; c < ncodes; c += kThreads)
     if (dw[c]) atomicAdd((unsigned long long *)&wst[c], (unsigned long long)(int64_t)dw[c]);
 }
 
-// part <- target for the moved vertices; threads below ncodes also fold the
-// weight-delta stripes into w and clear them.
-__global__ void k_commit(int32_t n, int32_t *part, const int32_t *target, const uint8_t *moved,
-                         int32_t ncodes, int64_t *w, int64_t *wst) {
+// part <- target for the moved vertices.  Workgroup 0 also folds the
+// weight-delta stripes into w (all written by the previous launch) and, with
+// has_end, runs the StepEnd epilogue: nothing it reads is written by the
+// other workgroups of this launch, so no cross-workgroup ordering is needed.
+__global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part,
+                                                     const int32_t *target, const uint8_t *moved,
+                                                     int32_t ncodes, int32_t nstripes, int64_t *w,
+                                                     int64_t *wst, int has_end, StepEnd E) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < ncodes) {
-    int64_t a = 0;
-#pragma unroll 8
-    for (int st = 0; st < kWeightStripes; ++st) {
-      a += wst[(size_t)st * ncodes + v];
-      wst[(size_t)st * ncodes + v] = 0;
-    }
-    if (a) w[v] += a;
-  }
   if (v < n && moved[v]) part[v] = target[v];
+  if (blockIdx.x != 0) return;
+  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
+    int64_t a = 0;
+    for (int st = 0; st < nstripes; ++st) {
+      a += wst[(size_t)st * ncodes + c];
+      wst[(size_t)st * ncodes + c] = 0;
+    }
+    if (a) w[c] += a;
+  }
+  __syncthreads();
+  if (has_end) step_epilogue(E);
+}
+
+// Weight-delta stripes: at most kWeightStripes, and at most 8192 words in all
+// so that one workgroup folds them quickly.
+int weight_stripes(const Hier &h) {
+  int sc = kWeightStripes;
+  while (sc > 1 && ((int64_t)sc << h.bits) > 8192) sc >>= 1;
+  return sc;
 }
 
 int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
@@ -747,23 +828,30 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, hipStream_t s) {
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s) {
   // capped: every workgroup flushes its LDS block-weight deltas once
-  const unsigned nwg = capped_grid(cl);
-  if (nwg == 0) return;
-  ApplyArgs A{g, cl, h, part, target, moved, lock, wst, dj_stripes};
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);
+  const unsigned nwg = capped_grid(tc);
+  const int nstripes = weight_stripes(h);
+  ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes};
+  auto kern = V == 2 ? k_apply<2> : k_apply<1>;
   const size_t lds = sizeof(int32_t) * ((size_t)1 << h.bits);
-  if (tl_timer) {
-    hipEvent_t a, b;
-    tl_timer->pair(KT_APPLY, a, b);
-    hipExtLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
-  } else {
-    hipLaunchKernelGGL(k_apply, dim3(nwg), dim3(kThreads), lds, s, A);
+  if (nwg > 0) {
+    if (tl_timer) {
+      hipEvent_t a, b;
+      tl_timer->pair(KT_APPLY, a, b);
+      hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
+    } else {
+      hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, A);
+    }
+    PM_LAUNCH_CHECK();
   }
-  PM_LAUNCH_CHECK();
   const int32_t ncodes = 1 << h.bits;
-  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n > ncodes ? g.n : ncodes)), dim3(kThreads), 0, s,
-                     g.n, part, target, moved, ncodes, w, wst);
+  StepEnd E{};
+  if (end) E = *end;
+  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
+                     moved, ncodes, nstripes, w, wst, end ? 1 : 0, E);
   PM_LAUNCH_CHECK();
 }
 
@@ -801,6 +889,7 @@ struct RebArgs {
   int64_t total;
   uint64_t hseed;
   const int32_t *elig;
+  const int32_t *n_elig;
   const Status *st;
   int32_t *key;
   int32_t *dest;
@@ -835,7 +924,7 @@ __device__ __forceinline__ void bw_flush(const RebArgs &A, const BwAdd &x) {
 __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
                                            int64_t conn_b, int64_t connp, BwAdd &add) {
   if (b == 0xFFFFFFFFu) {
-    const int32_t ne = A.st->n_eligible;
+    const int32_t ne = *A.n_elig;
     if (ne <= 0) {
       A.key[v] = -1;
       return;
@@ -853,41 +942,51 @@ __device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t
 
 __device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) { A.key[v] = -1; }
 
-// One source per lane group; every lane of the wave reaches the bucket flush.
-template <int G>
+// V sources per lane group; every lane of the wave reaches the bucket flush.
+struct RbN {
+  uint32_t bu;
+  int32_t wu;
+  bool capok;
+};
+
+template <int G, int V>
 __device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) {
-  int32_t v;
-  BwAdd add;
-  if (group_vertex<G>(A.cl, cls, local, v)) {
-    const int lane = threadIdx.x % G;
-    const uint32_t p = (uint32_t)A.part[v];
-    if (!is_source(A, v, p)) {
-      if (lane == 0) reb_not_source(A, v);
-    } else {
-      const int64_t beg = A.g.xadj[v];
-      const int deg = (int)(A.g.xadj[v + 1] - beg);
-      const bool valid = lane < deg;
-      uint32_t bu = p;
-      int32_t wu = 0;
-      if (valid) {
-        bu = (uint32_t)A.part[A.g.adj[beg + lane]];
-        wu = A.g.w[beg + lane];
-      }
-      const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
-      const bool cand = valid && bu != p && A.w[bu] <= A.cap;
-      int64_t conn = 0;
-      for (int j = 0; j < deg; ++j) {
-        const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
-        const int32_t wj = gshfl<G>(wu, j);
-        conn += bj == bu ? wj : 0;
-      }
-      int64_t val = cand ? conn : INT64_MIN;
-      uint32_t b = cand ? bu : 0xFFFFFFFFu;
-      gargmax<G>(val, b);
-      if (lane == 0) reb_decide(A, v, p, b, val, connp, add);
-    }
-  }
-  bw_flush(A, add);
+  BwAdd add[V];
+  group_tiles<G, V>(
+      A.g.xadj, A.g.adj, A.cl, cls, local,
+      [&](int32_t v, bool &act) {
+        const uint32_t p = (uint32_t)A.part[v];
+        act = is_source(A, v, p);
+        return p;
+      },
+      [&](int32_t u, int64_t e) {
+        const uint32_t bu = (uint32_t)A.part[u];
+        return RbN{bu, A.g.w[e], A.w[bu] <= A.cap};
+      },
+      [&](int r, bool ok, int32_t v, uint32_t p, bool act, int deg, bool valid, const RbN &nv) {
+        if (!ok) return;
+        const int lane = threadIdx.x % G;
+        if (!act) {
+          if (lane == 0) reb_not_source(A, v);
+          return;
+        }
+        const uint32_t bu = valid ? nv.bu : p;
+        const int32_t wu = valid ? nv.wu : 0;
+        const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
+        const bool cand = valid && bu != p && nv.capok;
+        int64_t conn = 0;
+        for (int j = 0; j < deg; ++j) {
+          const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+          const int32_t wj = gshfl<G>(wu, j);
+          conn += bj == bu ? wj : 0;
+        }
+        int64_t val = cand ? conn : INT64_MIN;
+        uint32_t b = cand ? bu : 0xFFFFFFFFu;
+        gargmax<G>(val, b);
+        if (lane == 0) reb_decide(A, v, p, b, val, connp, add[r]);
+      });
+#pragma unroll
+  for (int r = 0; r < V; ++r) bw_flush(A, add[r]);
 }
 
 __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X,
@@ -921,6 +1020,7 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
   }
 }
 
+template <int V>
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
@@ -929,39 +1029,27 @@ __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   const int local = blk - A.cl.wg[cls];
   switch (cls) {
     case CLS_ISO: {
-      const int idx = local * kThreads + threadIdx.x;
-      BwAdd add;
-      if (idx < A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO]) {
-        const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
-        const uint32_t p = (uint32_t)A.part[v];
-        if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0, add);
-        else reb_not_source(A, v);
+      const int cnt = A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO];
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int idx = (local * V + r) * kThreads + threadIdx.x;
+        BwAdd add;
+        if (idx < cnt) {
+          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
+          const uint32_t p = (uint32_t)A.part[v];
+          if (is_source(A, v, p)) reb_decide(A, v, p, 0xFFFFFFFFu, 0, 0, add);
+          else reb_not_source(A, v);
+        }
+        bw_flush(A, add);
       }
-      bw_flush(A, add);
       break;
     }
-    case CLS_G8: reb_group<8>(A, cls, local); break;
-    case CLS_G16: reb_group<16>(A, cls, local); break;
-    case CLS_G32: reb_group<32>(A, cls, local); break;
-    case CLS_G64: reb_group<64>(A, cls, local); break;
+    case CLS_G8: reb_group<8, V>(A, cls, local); break;
+    case CLS_G16: reb_group<16, V>(A, cls, local); break;
+    case CLS_G32: reb_group<32, V>(A, cls, local); break;
+    case CLS_G64: reb_group<64, V>(A, cls, local); break;
     default: reb_big(A, local, X, sc); break;
   }
-}
-
-// Blocks within the cap, ascending (one workgroup over all codes).
-__global__ __launch_bounds__(kThreads) void k_reb_eligible(Hier h, const int64_t *w, int64_t cap,
-                                                           int32_t *elig, Status *st) {
-  __shared__ BlockScratch sc;
-  const int32_t ncodes = 1 << h.bits;
-  const int per = (ncodes + kThreads - 1) / kThreads;
-  const int lo = threadIdx.x * per;
-  const int hi = lo + per < ncodes ? lo + per : ncodes;
-  uint32_t cnt = 0;
-  for (int c = lo; c < hi; ++c) cnt += (code_valid(h, (uint32_t)c) && w[c] <= cap) ? 1u : 0u;
-  uint32_t pos = block_excl_scan(cnt, sc);
-  for (int c = lo; c < hi; ++c)
-    if (code_valid(h, (uint32_t)c) && w[c] <= cap) elig[pos++] = c;
-  if (threadIdx.x == kThreads - 1) st->n_eligible = (int32_t)pos;
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,17 +1246,21 @@ __device__ __forceinline__ void kp_flush(const KPArgs &A, bool has, uint32_t ake
 
 // Per-vertex pass: the outcome of every element except the members of a key
 // inside that key's critical tile (those are left to k_kp_walk).
-__global__ __launch_bounds__(kThreads) void k_kp_decide(KPArgs A) {
-  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+__device__ __forceinline__ void kp_decide(const KPArgs &A, int blk) {
+  const int64_t v = (int64_t)blk * kThreads + threadIdx.x;
   bool has = false;
   uint32_t akey = 0;
   int64_t aval = 0;
   if (v < A.n) {
     uint32_t K;
     int32_t b;
+    // The selection clears every reject flag; the acceptance writes flags of
+    // elements only.  (In the acceptance, the walk workgroups of the same
+    // launch clear moved[] of refused members, so a vertex may look like a
+    // non-element here; it must then be left alone.)
+    if (A.pass == KP_SELECT) A.reject[v] = 0;
     if (!kp_element(A, (int32_t)v, K, b)) {
       if (A.pass == KP_SELECT) A.moved[v] = 0;
-      else A.reject[v] = 0;
     } else {
       const int32_t cb = A.crit[K];
       if (b != cb) {
@@ -1190,10 +1282,9 @@ __global__ __launch_bounds__(kThreads) void k_kp_decide(KPArgs A) {
 // members in order.
 constexpr int kWalkPer = 16;
 constexpr int kWalkChunk = kWalkPer * kThreads;
-__global__ __launch_bounds__(kThreads) void k_kp_walk(KPArgs A) {
+__device__ __forceinline__ void kp_walk(const KPArgs &A, int32_t K) {
   __shared__ BlockScratch sc;
   __shared__ uint32_t chunk_total;
-  const int32_t K = blockIdx.x;
   const int32_t cb = A.crit[K];
   if (cb < 0 || cb >= kBuckets) return;
   const int32_t tc = A.tcrit[K];
@@ -1239,6 +1330,13 @@ __global__ __launch_bounds__(kThreads) void k_kp_walk(KPArgs A) {
     base += chunk_total;
     __syncthreads();  // chunk_total is rewritten by the next chunk
   }
+}
+
+// The first `flat` workgroups decide per vertex, the next ncodes walk one key
+// each (the two sets of elements are disjoint).
+__global__ __launch_bounds__(kThreads) void k_kp_final(KPArgs A, int flat) {
+  if ((int)blockIdx.x < flat) kp_decide(A, blockIdx.x);
+  else kp_walk(A, (int32_t)blockIdx.x - flat);
 }
 
 // residual capacities r_b = L_max - c(b) - accepted_b > 0, ascending blocks;
@@ -1325,7 +1423,8 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
   rb.dest = ar.alloc_n<int32_t>(n);
   rb.reject = ar.alloc_n<uint8_t>(n);
   rb.pre = ar.alloc_n<int64_t>(n);
-  rb.elig = ar.alloc_n<int32_t>(ncodes);
+  rb.elig_weak = ar.alloc_n<int32_t>(ncodes);
+  rb.elig_strong = ar.alloc_n<int32_t>(ncodes);
   rb.bw = ar.alloc_n<int64_t>((size_t)kBucketStripes * ncodes * kBuckets);
   rb.acc = ar.alloc_n<int64_t>((size_t)kBucketStripes * ncodes);
   rb.crit = ar.alloc_n<int32_t>(ncodes);
@@ -1351,9 +1450,7 @@ static void keyed_prefix(KPArgs A, hipStream_t s) {
   PM_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_kp_tilecrit, dim3(waves_grid), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_kp_decide, dim3(flat), dim3(kThreads), 0, s, A);
-  PM_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_kp_walk, dim3(A.ncodes), dim3(kThreads), 0, s, A);
+  hipLaunchKernelGGL(k_kp_final, dim3(flat + A.ncodes), dim3(kThreads), 0, s, A, (int)flat);
   PM_LAUNCH_CHECK();
 }
 
@@ -1361,16 +1458,31 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s) {
-  const unsigned nwg = classed_grid(cl);
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);
+  const unsigned nwg = classed_grid(tc);
   const int64_t n = g.n;
   if (n <= 0) return;
   const int32_t ncodes = 1 << h.bits;
   const int64_t cap = strong ? lmax : sigma;
-  hipLaunchKernelGGL(k_reb_eligible, dim3(1), dim3(kThreads), 0, s, h, w, cap, rb.elig, st_dev);
-  PM_LAUNCH_CHECK();
   if (nwg > 0) {
-    RebArgs A{g, cl, h, part, w, lmax, cap, total, hseed, rb.elig, st_dev, rb.key, rb.dest, rb.bw};
-    hipLaunchKernelGGL(k_reb_select, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+    RebArgs A{g,
+              tc,
+              h,
+              part,
+              w,
+              lmax,
+              cap,
+              total,
+              hseed,
+              strong ? rb.elig_strong : rb.elig_weak,
+              strong ? &st_dev->n_elig_strong : &st_dev->n_elig_weak,
+              st_dev,
+              rb.key,
+              rb.dest,
+              rb.bw};
+    auto kern = V == 2 ? k_reb_select<2> : k_reb_select<1>;
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
     PM_LAUNCH_CHECK();
   }
   KPArgs K{};

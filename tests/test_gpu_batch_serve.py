@@ -52,6 +52,21 @@ def test_batch_equals_plain_and_oracle(pm, pmo, members):
             assert rc == rc_h and np.array_equal(host(part, m.graph.n), part_h), i
 
 
+def test_batch_repeated_equals_plain(pm, members):
+    """Two more batched runs of every member: concurrent jobs change the
+    timing of every kernel, so a result that depends on the order of device
+    work shows up as a mismatch with the plain run."""
+    dgs = [pm.DeviceGraph.from_host(m.graph) for m in members]
+    inst = [(dg, m.a, m.d, m.eps, m.seed) for dg, m in zip(dgs, members)]
+    plain = [pm.pm_map(*x) for x in inst]
+    for rep in range(2):
+        say("batch repeat", rep)
+        res = pm.pm_map_batch(inst, workers=8)
+        for i, (m, (rc, part, job), (rc_p, part_p, st_p)) in enumerate(zip(members, res, plain)):
+            assert rc == rc_p and job.j_final == st_p.j_final, (rep, i)
+            assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n)), (rep, i)
+
+
 def test_batch_worker_count_does_not_change_results(pm, members):
     sub = members[:24]
     dgs = [pm.DeviceGraph.from_host(m.graph) for m in sub]
