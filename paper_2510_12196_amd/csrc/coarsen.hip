@@ -71,20 +71,36 @@ struct HemN {
   int32_t u, mu, cu, w;
 };
 
+// Whether v must (re)compute its preference this round.  Candidates only
+// leave (neighbours get matched, weights are fixed), so the best candidate
+// of the previous round stays the best while it is unmatched, and a vertex
+// without candidates keeps none: only a vertex whose preferred partner was
+// matched since, or that has none yet (kPrefUnknown), looks again.  A
+// matched vertex gets -1 (its stale preference must not pair it again).
+constexpr int32_t kPrefUnknown = -2;
+struct HemV {
+  int32_t cv;
+  bool matched;
+};
+__device__ __forceinline__ HemV hem_vertex(const HemArgs &A, int32_t v, bool &act) {
+  const int32_t m = A.match[v];
+  const int32_t p = A.pref[v];
+  act = m < 0 && (p == kPrefUnknown || (p >= 0 && A.match[p] >= 0));
+  return HemV{A.g.c[v], m >= 0};
+}
+
 template <int G, int V>
 __device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) {
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
-      [&](int32_t v, bool &act) {
-        act = A.match[v] < 0;
-        return A.g.c[v];
-      },
+      [&](int32_t v, bool &act) { return hem_vertex(A, v, act); },
       [&](int32_t u, int64_t e) { return HemN{u, A.match[u], A.g.c[u], A.g.w[e]}; },
-      [&](int, bool ok, int32_t v, int32_t cv, bool act, int, bool valid, const HemN &a) {
+      [&](int, bool ok, int32_t v, const HemV &hv, bool act, int, bool valid, const HemN &a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
+        const int32_t cv = hv.cv;
         if (!act) {
-          if (lane == 0) A.pref[v] = -1;
+          if (lane == 0 && hv.matched) A.pref[v] = -1;
           return;
         }
         Cand c{-1, 0, 1, 0};
@@ -118,11 +134,13 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
       case CLS_G64: hem_group<64, V>(A, cls, local); break;
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-        if (A.match[v] >= 0) {
-          if (threadIdx.x == 0) A.pref[v] = -1;
+        bool act;
+        const HemV hv = hem_vertex(A, v, act);
+        if (!act) {
+          if (threadIdx.x == 0 && hv.matched) A.pref[v] = -1;
           break;
         }
-        const int32_t cv = A.g.c[v];
+        const int32_t cv = hv.cv;
         Cand best{-1, 0, 1, 0};
         big_arcs(
             A.g.xadj[v], A.g.xadj[v + 1],
@@ -171,14 +189,17 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
   PM_LAUNCH_CHECK();
 }
 
-// v and pref[v] are matched iff they prefer each other.  Every workgroup adds
-// (1 << 32) + its match count to one 64-bit counter; the workgroup that
-// completes the count (high half = grid size) stores st->count, clears the
-// counter and publishes.  A single atomic carries both the data and the
-// completion, so no fence is needed.
+// v and pref[v] are matched iff they prefer each other.  The count goes up a
+// two-level tree of 64-bit counters, each word (1 << 32) x workgroups done +
+// matches: workgroup b adds to leaf b % 64; the workgroup that completes a
+// leaf clears it and adds the leaf's total to the root; the one that
+// completes the root stores st->count and clears the root.  Each step is one
+// atomic that carries both the data and the completion, so no fence is
+// needed, and no address sees more than 64 atomics.
+constexpr int kHemLeaves = 64;
 __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
                                                          int32_t *match, uint64_t *counter,
-                                                         Status *st, Pub pub) {
+                                                         Status *st) {
   __shared__ BlockScratch sc;
   int64_t hits = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -191,24 +212,29 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
     }
   }
   hits = block_sum64(hits, sc);
-  if (threadIdx.x == 0) {
-    const uint64_t add = (1ull << 32) + (uint64_t)hits;
-    const uint64_t now = atomicAdd((unsigned long long *)counter, (unsigned long long)add) + add;
-    if ((now >> 32) == gridDim.x) {
-      st->count = (int32_t)(now & 0xFFFFFFFFull);
-      atomicExch((unsigned long long *)counter, 0ull);
-      __threadfence();
-      publish_dev(st, pub);
-    }
-  }
+  if (threadIdx.x != 0) return;
+  const unsigned G = gridDim.x;
+  const unsigned leaf = blockIdx.x % kHemLeaves;
+  const unsigned leaf_wgs = (G - leaf + kHemLeaves - 1) / kHemLeaves;
+  const unsigned leaves = G < (unsigned)kHemLeaves ? G : (unsigned)kHemLeaves;
+  unsigned long long *lp = (unsigned long long *)&counter[1 + leaf];
+  const uint64_t add = (1ull << 32) + (uint64_t)hits;
+  const uint64_t l = atomicAdd(lp, (unsigned long long)add) + add;
+  if ((l >> 32) != leaf_wgs) return;
+  atomicExch(lp, 0ull);
+  unsigned long long *rp = (unsigned long long *)&counter[0];
+  const uint64_t radd = (1ull << 32) + (l & 0xFFFFFFFFull);
+  const uint64_t r = atomicAdd(rp, (unsigned long long)radd) + radd;
+  if ((r >> 32) != leaves) return;
+  atomicExch(rp, 0ull);
+  st->count = (int32_t)(r & 0xFFFFFFFFull);
 }
 
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
-                const Pub &pub, hipStream_t s) {
+                hipStream_t s) {
   unsigned g = grid_for(n > 0 ? n : 1);
   if (g > kMaxGrid) g = kMaxGrid;
-  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st,
-                     pub);
+  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st);
   PM_LAUNCH_CHECK();
 }
 

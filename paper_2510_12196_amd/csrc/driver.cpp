@@ -82,8 +82,8 @@ struct Ctx {
   uint64_t *counter = nullptr;  // completion counter of the matching commit
   explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
     dev = ar.alloc_n<Status>(1);
-    counter = ar.alloc_n<uint64_t>(1);
-    PM_HIP(hipMemsetAsync(counter, 0, sizeof(uint64_t), s));
+    counter = ar.alloc_n<uint64_t>(65);
+    PM_HIP(hipMemsetAsync(counter, 0, sizeof(uint64_t) * 65, s));
     host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
     void *mdev = nullptr;
     char *m = static_cast<char *>(ar.host_mapped(&mdev));
@@ -171,13 +171,12 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   block_weights(g, h, cur, w, s);
   comm_cost(g, cl, h, cur, cx.sp.a, cx.dev, s);
   // step epilogue: heaviest block, J change, eligible destinations, publication
-  StepEnd E{h, w, cx.sp.a, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev, {}};
+  StepEnd E{h, w, cx.sp.a, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev};
   {
     StepEnd E0 = E;
     E0.dj_stripes = nullptr;
-    E0.pub = cx.next_pub();
     step_status(E0, s);
-    cx.wait(E0.pub);
+    cx.pull();
   }
   int64_t j_cur = cx.host->j, imb_cur = cx.host->maxw;
   if (n == 0) imb_cur = 0;
@@ -193,7 +192,6 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   while (i < 12 && bodies < 4096) {
     ++i;
     ++bodies;
-    E.pub = cx.next_pub();
     if (imb_cur <= lmax) {
       lp_phase1(g, cl, h, cur, lock, target, gain, s);
       lp_phase2(g, cl, h, cur, target, gain, moved, s);
@@ -214,7 +212,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         ++R.st.weak_iterations;
       }
     }
-    cx.wait(E.pub);
+    cx.pull();
     j_cur += cx.host->dj;
     imb_cur = cx.host->maxw;
     if (imb_cur <= lmax) {
@@ -278,15 +276,15 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   const DGraph &g = L.g;
   hipStream_t s = cx.s;
   fill_i32(match, -1, g.n, s);
+  fill_i32(pref, -2, g.n, s);  // no preference computed yet
   const uint64_t hseed = mix_hash(seed ^ kTagMatch, (uint64_t)(int64_t)level);
   int32_t rounds = 0;
   int64_t matched = 0;
   while (rounds < 64) {
     ++rounds;
     hem_prefer(g, L.cl, lmax, hseed, match, pref, s);
-    const Pub pub = cx.next_pub();
-    hem_commit(g.n, pref, match, cx.counter, cx.dev, pub, s);
-    cx.wait(pub);
+    hem_commit(g.n, pref, match, cx.counter, cx.dev, s);
+    cx.pull();
     const int32_t added = cx.host->count;
     matched += added;
     if (added == 0) break;
@@ -539,9 +537,7 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
     int32_t *target = ar.alloc_n<int32_t>(n);
     RebalanceBuffers rb = alloc_rebalance(ar, n, hh, s);
     block_weights(dg, hh, codes, w, s);
-    step_status(
-        StepEnd{hh, w, nullptr, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev, Pub{nullptr, nullptr, 0}},
-        s);
+    step_status(StepEnd{hh, w, nullptr, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev}, s);
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,

@@ -28,17 +28,16 @@ struct Pub {
 };
 
 // End of a refinement step, run by one workgroup of the commit: the heaviest
-// block, the J change, the blocks eligible as rebalancing destinations for
-// the next step, then the publication.
+// block, the J change and the blocks eligible as rebalancing destinations
+// for the next step, into the device status.
 struct StepEnd {
   Hier h;
-  const int64_t *w;      // block weights (final when the epilogue runs)
+  int64_t *w;            // block weights (final when the epilogue runs)
   int64_t *dj_stripes;   // folded into st->dj (nullptr: st->dj untouched)
   int64_t sigma, lmax;   // caps of weak and strong rebalancing
   int32_t *elig_weak;    // blocks with w <= sigma, ascending
   int32_t *elig_strong;  // blocks with w <= L_max, ascending
   Status *st;
-  Pub pub;
 };
 // StepEnd alone, as one workgroup (the start of a level).
 void step_status(const StepEnd &E, hipStream_t s);
@@ -170,10 +169,10 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s);
-// st->count = new matches, then the publication pub.  counter: 64-bit
-// completion counter, zero between launches.
+// st->count = new matches.  counter: 65 64-bit completion counters, zero
+// between launches.
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
-                const Pub &pub, hipStream_t s);
+                hipStream_t s);
 // Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched
 // vertices and pairs each group in id order.  Returns the vertices matched.
 // Synchronises the stream.

@@ -313,51 +313,128 @@ void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t 
   PM_LAUNCH_CHECK();
 }
 
-// Blocks with w <= cap, ascending, into list; count into *count.
-__device__ __forceinline__ void eligible_list(const Hier &h, const int64_t *w, int64_t cap,
-                                              int32_t *list, int32_t *count, BlockScratch &sc) {
-  const int32_t ncodes = 1 << h.bits;
+template <int NS>
+__device__ __forceinline__ int64_t stripe_sum(const int64_t *wst, int32_t ncodes, int c) {
+  int64_t x[NS];
+#pragma unroll
+  for (int st = 0; st < NS; ++st) x[st] = wst[(size_t)st * ncodes + c];
+  int64_t d = 0;
+#pragma unroll
+  for (int st = 0; st < NS; ++st) d += x[st];
+  return d;
+}
+
+// The StepEnd epilogue, by one workgroup: one round of loads (the block
+// weights and their pending stripes, the J-change stripes, the status words),
+// reductions and scans in LDS only (wl: ncodes words), then every global
+// store at the end, so that no barrier waits for a store.  wst:
+// weight-delta stripes to fold into w first (nullptr: none).  full = false:
+// only the fold.  (The host publication is a launch of its own: a
+// system-scope fence here would write back the L2 this launch has dirtied.)
+__device__ __forceinline__ void step_epilogue(const StepEnd &E, int64_t *wst, int nstripes,
+                                              int64_t *wl, bool full) {
+  __shared__ int64_t red_m[kThreads / 64], red_d[kThreads / 64];
+  __shared__ uint32_t red_u[kThreads / 64];
+  const int32_t ncodes = 1 << E.h.bits;
   const int per = (ncodes + kThreads - 1) / kThreads;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < ncodes ? lo + per : ncodes;
-  uint32_t cnt = 0;
-  for (int c = lo; c < hi; ++c) cnt += (code_valid(h, (uint32_t)c) && agent_load(&w[c]) <= cap) ? 1u : 0u;
-  uint32_t pos = block_excl_scan(cnt, sc);
-  for (int c = lo; c < hi; ++c)
-    if (code_valid(h, (uint32_t)c) && agent_load(&w[c]) <= cap) list[pos++] = c;
-  if (threadIdx.x == kThreads - 1) *count = (int32_t)pos;
-}
-
-// The StepEnd epilogue, by one workgroup.
-__device__ __forceinline__ void step_epilogue(const StepEnd &E) {
-  __shared__ BlockScratch sc;
-  const int32_t ncodes = 1 << E.h.bits;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // ---- loads
+  Status S{};
+  if (full && threadIdx.x == 0) S = *E.st;
+  int64_t dj = (full && E.dj_stripes) ? E.dj_stripes[threadIdx.x * kStripeStride] : 0;
+  uint32_t changed = 0;  // bit c - lo: weight changed
   int64_t m = INT64_MIN;
-  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
-    const int64_t x = agent_load(&E.w[c]);
-    m = x > m ? x : m;
+  for (int c = lo; c < hi; ++c) {
+    int64_t a = E.w[c];
+    if (wst) {
+      int64_t d;
+      switch (nstripes) {  // unrolled per count: all stripe loads in flight together
+        case 32: d = stripe_sum<32>(wst, ncodes, c); break;
+        case 16: d = stripe_sum<16>(wst, ncodes, c); break;
+        case 8: d = stripe_sum<8>(wst, ncodes, c); break;
+        case 4: d = stripe_sum<4>(wst, ncodes, c); break;
+        case 2: d = stripe_sum<2>(wst, ncodes, c); break;
+        default: d = stripe_sum<1>(wst, ncodes, c); break;
+      }
+      if (d) changed |= 1u << (c - lo);
+      a += d;
+    }
+    wl[c] = a;
+    m = a > m ? a : m;
   }
-  uint32_t dummy = 0;
-  block_argmax(m, dummy, sc);
-  if (threadIdx.x == 0) E.st->maxw = m;
-  if (E.dj_stripes) {
-    int64_t x = agent_load(&E.dj_stripes[threadIdx.x * kStripeStride]);
-    E.dj_stripes[threadIdx.x * kStripeStride] = 0;
-    x = block_sum64(x, sc);
-    if (threadIdx.x == 0) E.st->dj = x;
+  if (full) {
+    // ---- LDS only: heaviest block, J change, eligible counts (two packed
+    // 16-bit counts; each list has at most 2^13 entries)
+    uint32_t cnt = 0;
+    for (int c = lo; c < hi; ++c) {
+      if (!code_valid(E.h, (uint32_t)c)) continue;
+      if (wl[c] <= E.sigma) cnt += 1u;
+      if (wl[c] <= E.lmax) cnt += 1u << 16;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t om = gxor64<64>(m, o);
+      m = om > m ? om : m;
+    }
+    dj = gsum64<64>(dj);
+    uint32_t incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int32_t)incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) red_u[wave] = incl;
+    if (lane == 0) {
+      red_m[wave] = m;
+      red_d[wave] = dj;
+    }
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (int i = 0; i < kThreads / 64; ++i) {
+      if (i < wave) off += red_u[i];
+      tot += red_u[i];
+      m = red_m[i] > m ? red_m[i] : m;
+    }
+    dj = 0;
+    for (int i = 0; i < kThreads / 64; ++i) dj += red_d[i];
+    uint32_t pos = off + incl - cnt;
+    // ---- stores
+    uint32_t pw = pos & 0xFFFFu, ps = pos >> 16;
+    for (int c = lo; c < hi; ++c) {
+      if (!code_valid(E.h, (uint32_t)c)) continue;
+      if (wl[c] <= E.sigma) E.elig_weak[pw++] = c;
+      if (wl[c] <= E.lmax) E.elig_strong[ps++] = c;
+    }
+    if (E.dj_stripes) E.dj_stripes[threadIdx.x * kStripeStride] = 0;
+    if (threadIdx.x == 0) {
+      S.maxw = m;
+      if (E.dj_stripes) S.dj = dj;
+      S.n_elig_weak = (int32_t)(tot & 0xFFFFu);
+      S.n_elig_strong = (int32_t)(tot >> 16);
+      E.st->maxw = S.maxw;
+      E.st->dj = S.dj;
+      E.st->n_elig_weak = S.n_elig_weak;
+      E.st->n_elig_strong = S.n_elig_strong;
+    }
   }
-  eligible_list(E.h, E.w, E.sigma, E.elig_weak, &E.st->n_elig_weak, sc);
-  __syncthreads();
-  eligible_list(E.h, E.w, E.lmax, E.elig_strong, &E.st->n_elig_strong, sc);
-  __threadfence();
-  __syncthreads();
-  publish_dev(E.st, E.pub);
+  if (wst) {
+    for (int c = lo; c < hi; ++c) {
+      if (!(changed & (1u << (c - lo)))) continue;
+      E.w[c] = wl[c];
+#pragma unroll
+      for (int st = 0; st < kWeightStripes; ++st)
+        if (st < nstripes) wst[(size_t)st * ncodes + c] = 0;
+    }
+  }
 }
 
-__global__ __launch_bounds__(kThreads) void k_step_status(StepEnd E) { step_epilogue(E); }
+__global__ __launch_bounds__(kThreads) void k_step_status(StepEnd E) {
+  extern __shared__ int64_t wl[];
+  step_epilogue(E, nullptr, 0, wl, true);
+}
 
 void step_status(const StepEnd &E, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_status, dim3(1), dim3(kThreads), 0, s, E);
+  hipLaunchKernelGGL(k_step_status, dim3(1), dim3(kThreads), sizeof(int64_t) << E.h.bits, s, E);
   PM_LAUNCH_CHECK();
 }
 
@@ -794,21 +871,12 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
 // other workgroups of this launch, so no cross-workgroup ordering is needed.
 __global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part,
                                                      const int32_t *target, const uint8_t *moved,
-                                                     int32_t ncodes, int32_t nstripes, int64_t *w,
-                                                     int64_t *wst, int has_end, StepEnd E) {
+                                                     int32_t nstripes, int64_t *wst, int has_end,
+                                                     StepEnd E) {
+  extern __shared__ int64_t wl[];
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n && moved[v]) part[v] = target[v];
-  if (blockIdx.x != 0) return;
-  for (int c = threadIdx.x; c < ncodes; c += kThreads) {
-    int64_t a = 0;
-    for (int st = 0; st < nstripes; ++st) {
-      a += wst[(size_t)st * ncodes + c];
-      wst[(size_t)st * ncodes + c] = 0;
-    }
-    if (a) w[c] += a;
-  }
-  __syncthreads();
-  if (has_end) step_epilogue(E);
+  if (blockIdx.x == 0) step_epilogue(E, wst, nstripes, wl, has_end != 0);
 }
 
 // Weight-delta stripes: at most kWeightStripes, and at most 8192 words in all
@@ -847,11 +915,12 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
     }
     PM_LAUNCH_CHECK();
   }
-  const int32_t ncodes = 1 << h.bits;
   StepEnd E{};
   if (end) E = *end;
-  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
-                     moved, ncodes, nstripes, w, wst, end ? 1 : 0, E);
+  E.h = h;
+  E.w = w;
+  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), sizeof(int64_t) << h.bits, s,
+                     g.n, part, target, moved, nstripes, wst, end ? 1 : 0, E);
   PM_LAUNCH_CHECK();
 }
 
