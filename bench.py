@@ -96,6 +96,19 @@ def summarize_pmc(d):
     print(f"source_digest: {source_digest()}")
 
 
+def _phase_share(stats):
+    tot = sum(s.total_ms for _, s in stats)
+    if tot <= 0:
+        return None
+    out = {}
+    for f, name in (("coarsen_ms", "coarsening"), ("contract_ms", "contraction"),
+                    ("initial_ms", "initial_partitioning"), ("uncoarsen_ms", "uncontraction"),
+                    ("refine_ms", "refine_and_rebalance")):
+        out[name] = round(100.0 * sum(getattr(s, f) for _, s in stats) / tot, 2)
+    out["misc"] = round(100.0 - sum(out.values()), 2)
+    return out
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -201,6 +214,9 @@ def main():
         "phase_ms": {f: round(avg(f), 3) for f in
                      ["coarsen_ms", "contract_ms", "initial_ms", "uncoarsen_ms", "refine_ms",
                       "total_ms"]},
+        # shares of the map time per phase, as in the paper's Table 2
+        # (misc: everything outside the five phases)
+        "phase_share": _phase_share(stats),
         "levels": s0.levels,
         "level_n": list(s0.level_n[: s0.levels]),
         "level_iterations": list(s0.level_iterations[: s0.levels]),

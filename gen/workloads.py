@@ -3,8 +3,9 @@
 Each workload is a task graph plus a machine hierarchy a = a_1:...:a_l
 (a_1 innermost: PEs per processor), level distances d = d_1:...:d_l and an
 imbalance eps, following the experimental setup of Section 5 of the paper
-(d = 1:10:100, eps = 3 %).  The graphs stand in for the paper's instance set
-(Table 1), which is not available here.
+(d = 1:10:100, eps = 3 %, hierarchies 4:8:{1..6}).  The graphs stand in for
+the paper's instance set (Table 1), which is not available here; rgg23/24
+and del23/24 follow its description of those four instances.
 """
 from __future__ import annotations
 
@@ -40,6 +41,11 @@ class Workload:
                 "k": self.k, "graph_seed": self.gseed}
 
 
+def paper_radius(n: int) -> float:
+    """Connection radius of the paper's rgg23/rgg24: 0.55 sqrt(ln n / n)."""
+    return 0.55 * float(np.sqrt(np.log(n) / n))
+
+
 @functools.lru_cache(maxsize=4)
 def _build(kind, size, gseed):
     if kind == "grid":
@@ -48,6 +54,12 @@ def _build(kind, size, gseed):
         return graphs.rgg(size[0], gseed)
     if kind == "rmat":
         return graphs.rmat(size[0], size[1], gseed)
+    if kind == "rggp":
+        n = size[0]
+        return graphs.rgg_radius(n, gseed, paper_radius(n), strips=max(1, n >> 20))
+    if kind == "del":
+        n = size[0]
+        return graphs.delaunay(n, gseed, strips=max(1, n >> 20))
     raise ValueError(kind)
 
 
@@ -65,6 +77,15 @@ WORKLOADS = {
     "rgg17": Workload("rgg17", "rgg", (1 << 17,), (4, 8, 8), D3, gseed=0xC2),
     "rmat14": Workload("rmat14", "rmat", (14, 1 << 17), (4, 16, 8), D3, gseed=0xC3),
     "rmat17": Workload("rmat17", "rmat", (17, 1 << 20), (4, 16, 8), D3, gseed=0xC3),
+    # stand-ins of the paper's largest mesh instances (unit weights, radius
+    # 0.55 sqrt(ln n / n) resp. Delaunay), hierarchy 4:8:6 (k = 192)
+    "rgg23": Workload("rgg23", "rggp", (1 << 23,), (4, 8, 6), D3, gseed=0xC6),
+    "rgg24": Workload("rgg24", "rggp", (1 << 24,), (4, 8, 6), D3, gseed=0xC6),
+    "del23": Workload("del23", "del", (1 << 23,), (4, 8, 6), D3, gseed=0xC7),
+    "del24": Workload("del24", "del", (1 << 24,), (4, 8, 6), D3, gseed=0xC7),
+    # the same shapes at 2^16 for parity runs
+    "rgg16p": Workload("rgg16p", "rggp", (1 << 16,), (4, 8, 6), D3, gseed=0xC6),
+    "del16": Workload("del16", "del", (1 << 16,), (4, 8, 6), D3, gseed=0xC7),
 }
 
 

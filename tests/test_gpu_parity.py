@@ -242,6 +242,19 @@ def test_map_parity(pm, pmo, name, a, d):
         assert np.array_equal(host(part_d), part_h)
 
 
+@pytest.mark.parametrize("name", ["rgg16p", "del16"])
+def test_map_parity_paper_shapes(pm, pmo, name):
+    """The paper's rgg and Delaunay instance shapes at 2^16, hierarchy 4:8:6."""
+    w = gen.get(name)
+    g = w.graph()
+    say("map", name, w.a, "seed 1")
+    rc_h, part_h, st_h = pmo.map_graph(g, w.a, w.d, w.eps, 1)
+    rc_d, part_d, st_d = pm.pm_map(dev(pm, g), w.a, w.d, w.eps, 1)
+    assert rc_d == rc_h
+    assert st_d.j_final == st_h.j_final
+    assert np.array_equal(host(part_d), part_h)
+
+
 def test_map_grid_all_paper_seeds(pm, pmo):
     w = gen.get("grid64")
     g = w.graph()
