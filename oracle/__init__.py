@@ -72,7 +72,34 @@ _SIGS = {
     "pmo_contract": (_I64, [_I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "pmo_initial_partition": (None, [_I32, _P, _P, _P, _I32, _P, _P]),
     "pmo_map": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _P, _P]),
+    "pmo_lp_round_v": (None, [_I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pmo_rebalance_v": (None, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _I32, _I64, _I64,
+                               _U64, _I32, _I32, _P, _P, _P]),
+    "pmo_refine_v": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _I32, _P, _P,
+                            _P]),
+    "pmo_map_v": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _P, _P, _P]),
 }
+
+
+class Variants(ctypes.Structure):
+    """Refinement variants (pmo_variants): jet_c = (num, den) enables Jet's
+    relaxed first filter with c = num/den; j_rebalance rebalances by J."""
+    _fields_ = [("jet_c_num", ctypes.c_int32), ("jet_c_den", ctypes.c_int32),
+                ("j_rebalance", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+def variants(jet_c=None, j_rebalance=False):
+    v = Variants()
+    if jet_c:
+        v.jet_c_num, v.jet_c_den = int(jet_c[0]), int(jet_c[1])
+    else:
+        v.jet_c_num, v.jet_c_den = 0, 1
+    v.j_rebalance = 1 if j_rebalance else 0
+    return v
+
+
+def _var(v):
+    return ctypes.byref(v) if v is not None else None
 
 
 def lib():
@@ -156,8 +183,9 @@ def hash64(seed: int, word: int) -> int:
     return int(lib().pmo_hash(seed & (2**64 - 1), word & (2**64 - 1)))
 
 
-def lp_round(g, a, d, part, lock):
-    """One label-propagation round.  Returns (part', lock', target, gain, moved)."""
+def lp_round(g, a, d, part, lock, var=None):
+    """One label-propagation round.  Returns (part', lock', target, gain, moved).
+    var: Variants or None."""
     lv, a, d = _hier(a, d)
     part = _i32(part).copy()
     lock = np.ascontiguousarray(np.asarray(lock, dtype=np.uint8)).copy()
@@ -165,31 +193,37 @@ def lp_round(g, a, d, part, lock):
     target = np.empty(n, np.int32)
     gn = np.empty(n, np.int64)
     moved = np.empty(n, np.uint8)
-    lib().pmo_lp_round(n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), lv, _ptr(a),
-                       _ptr(d), _ptr(part), _ptr(lock), _ptr(target), _ptr(gn),
-                       _ptr(moved))
+    lib().pmo_lp_round_v(n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), lv, _ptr(a),
+                         _ptr(d), _ptr(part), _ptr(lock), _ptr(target), _ptr(gn),
+                         _ptr(moved), _var(var))
     return part, lock, target, gn, moved
 
 
 def rebalance(g, k, part, strong: bool, lmax_: int, sigma_: int, seed: int,
-              level: int, it: int):
-    """One weak/strong rebalancing round.  Returns (part', moved)."""
+              level: int, it: int, a=None, d=None, var=None):
+    """One weak/strong rebalancing round.  Returns (part', moved).  a, d (the
+    hierarchy) are needed by the J-objective variant only."""
     part = _i32(part).copy()
     moved = np.empty(g.n, np.uint8)
-    lib().pmo_rebalance(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
-                        k, int(bool(strong)), lmax_, sigma_, seed & (2**64 - 1), level, it,
-                        _ptr(part), _ptr(moved))
+    if a is None:
+        lv, ap, dp = 0, None, None
+    else:
+        lv, a, d = _hier(a, d)
+        ap, dp = _ptr(a), _ptr(d)
+    lib().pmo_rebalance_v(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                          lv, ap, dp, k, int(bool(strong)), lmax_, sigma_,
+                          seed & (2**64 - 1), level, it, _ptr(part), _ptr(moved), _var(var))
     return part, moved
 
 
-def refine(g, a, d, eps, seed, part, level: int = 0):
+def refine(g, a, d, eps, seed, part, level: int = 0, var=None):
     """Algorithm-6 refinement.  Returns (status, part, RefineStats)."""
     lv, a, d = _hier(a, d)
     part = _i32(part).copy()
     st = RefineStats()
-    rc = lib().pmo_refine(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
-                          lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1), level,
-                          _ptr(part), ctypes.byref(st))
+    rc = lib().pmo_refine_v(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                            lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1), level,
+                            _ptr(part), ctypes.byref(st), _var(var))
     return int(rc), part, st
 
 
@@ -229,12 +263,12 @@ def initial_partition(g, a):
     return part
 
 
-def map_graph(g, a, d, eps, seed):
+def map_graph(g, a, d, eps, seed, var=None):
     """Full multilevel mapping.  Returns (status, part, MapStats)."""
     lv, a, d = _hier(a, d)
     part = np.empty(g.n, np.int32)
     st = MapStats()
-    rc = lib().pmo_map(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
-                       lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1),
-                       _ptr(part), ctypes.byref(st))
+    rc = lib().pmo_map_v(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                         lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1),
+                         _ptr(part), ctypes.byref(st), _var(var))
     return int(rc), part, st

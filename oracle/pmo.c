@@ -210,6 +210,21 @@ void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                   const int32_t *adjwgt, int32_t levels, const int32_t *a,
                   const int32_t *d, int32_t *part, uint8_t *lock,
                   int32_t *target_out, int64_t *gain_out, uint8_t *moved_out) {
+  pmo_lp_round_v(n, xadj, adjncy, adjwgt, levels, a, d, part, lock, target_out,
+                 gain_out, moved_out, NULL);
+}
+
+/* Label propagation round (Algorithm 4).  With the relaxed first filter of
+ * Jet (variants->jet_c_num > 0, Section 3.2 after Algorithm 4), a vertex also
+ * enters X when its best gain is negative but -G < floor(c * conn(v,Pi(v))),
+ * c = jet_c_num / jet_c_den; the second filter is unchanged. */
+void pmo_lp_round_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                    const int32_t *adjwgt, int32_t levels, const int32_t *a,
+                    const int32_t *d, int32_t *part, uint8_t *lock,
+                    int32_t *target_out, int64_t *gain_out, uint8_t *moved_out,
+                    const pmo_variants *var) {
+  const int64_t jet_num = var ? var->jet_c_num : 0;
+  const int64_t jet_den = (var && var->jet_c_den > 0) ? var->jet_c_den : 1;
   int64_t maxdeg = max_degree(n, xadj);
   blk_w *row = (blk_w *)xmalloc(sizeof(blk_w) * (size_t)maxdeg);
   int32_t *blocks = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)maxdeg);
@@ -222,11 +237,14 @@ void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
     if (lock[v]) continue;
     int32_t p = part[v];
     int64_t r = connectivity(xadj, adjncy, adjwgt, part, v, row, blocks, conns);
-    int64_t best_g = 0;
+    int64_t best_g = 0, conn_own = 0;
     int32_t best_b = -1;
     for (int64_t i = 0; i < r; ++i) {
       int32_t b = blocks[i];
-      if (b == p) continue;
+      if (b == p) {
+        conn_own = conns[i];
+        continue;
+      }
       int64_t g = 0;
       for (int64_t j = 0; j < r; ++j)
         g += conns[j] * (pmo_distance(levels, a, d, p, blocks[j]) -
@@ -236,7 +254,8 @@ void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
         best_b = b;
       }
     }
-    if (best_b >= 0 && best_g >= 0) {
+    const int passes = best_g >= 0 || (jet_num > 0 && -best_g < (jet_num * conn_own) / jet_den);
+    if (best_b >= 0 && passes) {
       target_out[v] = best_b;
       gain_out[v] = best_g;
     }
@@ -332,6 +351,24 @@ void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    int32_t strong, int64_t lmax, int64_t sigma, uint64_t seed,
                    int32_t level, int32_t iter, int32_t *part,
                    uint8_t *moved_out) {
+  pmo_rebalance_v(n, xadj, adjncy, adjwgt, vwgt, 0, NULL, NULL, k, strong, lmax,
+                  sigma, seed, level, iter, part, moved_out, NULL);
+}
+
+/* J-objective rebalancing (variants->j_rebalance, the variant of Section 3.2
+ * that the authors tried): the loss of a move to block b is the J gain of
+ * eq. 1, G_b(v) = sum_x conn(v,x) (D(Pi(v),x) - D(b,x)); the destination is
+ * the neighbour block within the cap with the largest J gain (smaller id on
+ * ties), else the pseudo-random block, whose loss is its J gain as well.
+ * Everything else is as in pmo_rebalance.  levels/a/d are only read by the
+ * variant. */
+void pmo_rebalance_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                     const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                     const int32_t *a, const int32_t *d, int64_t k,
+                     int32_t strong, int64_t lmax, int64_t sigma, uint64_t seed,
+                     int32_t level, int32_t iter, int32_t *part,
+                     uint8_t *moved_out, const pmo_variants *var) {
+  const int jobj = var && var->j_rebalance;
   int64_t *w = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
   pmo_block_weights(n, vwgt, part, k, w);
   int64_t total = 0;
@@ -365,25 +402,54 @@ void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
       ++cnt;
     }
     qsort(row, (size_t)cnt, sizeof(blk_w), cmp_blkw);
-    int64_t conn_own = 0, best_conn = -1;
-    int32_t t = -1;
+    /* merge to (block, conn) pairs, ascending block (a row's sum stays
+     * below 2^31: all edge weights together do) */
+    int64_t r = 0;
     for (int64_t i = 0; i < cnt;) {
       int32_t b = row[i].b;
       int64_t c = 0;
       while (i < cnt && row[i].b == b) c += row[i++].w;
-      if (b == p) conn_own = c;
-      else if (w[b] <= cap && c > best_conn) {
-        best_conn = c;
+      row[r].b = b;
+      row[r].w = c;
+      ++r;
+    }
+    int64_t conn_own = 0, best_val = 0;
+    int32_t t = -1;
+    for (int64_t i = 0; i < r; ++i) {
+      int32_t b = row[i].b;
+      int64_t c = row[i].w;
+      if (b == p) {
+        conn_own = c;
+        continue;
+      }
+      if (w[b] > cap) continue;
+      int64_t val = c;
+      if (jobj) {
+        val = 0;
+        for (int64_t j = 0; j < r; ++j)
+          val += (int64_t)row[j].w * (pmo_distance(levels, a, d, p, row[j].b) -
+                                      pmo_distance(levels, a, d, b, row[j].b));
+      }
+      if (t < 0 || val > best_val) {
+        best_val = val;
         t = b;
       }
     }
-    int64_t conn_t = best_conn;
+    int64_t g;
     if (t < 0) {
       if (nelig == 0) continue;
       t = elig[pmo_hash(hseed, (uint64_t)v) % (uint64_t)nelig];
-      conn_t = 0; /* not a neighbour block */
+      if (jobj) {
+        g = 0;
+        for (int64_t j = 0; j < r; ++j)
+          g += (int64_t)row[j].w * (pmo_distance(levels, a, d, p, row[j].b) -
+                                    pmo_distance(levels, a, d, t, row[j].b));
+      } else {
+        g = -conn_own; /* not a neighbour block: conn(v,t) = 0 */
+      }
+    } else {
+      g = jobj ? best_val : best_val - conn_own;
     }
-    int64_t g = conn_t - conn_own;
     int32_t bucket = g > 0 ? 0 : (g == 0 ? 1 : 2 + floor_log2_u64((uint64_t)(-g)));
     dest[v] = t;
     items[nitems].key1 = p;
@@ -522,6 +588,15 @@ int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    const int32_t *a, const int32_t *d, int64_t eps_ppm,
                    uint64_t seed, int32_t level, int32_t *part,
                    pmo_refine_stats *stats) {
+  return pmo_refine_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, eps_ppm, seed,
+                      level, part, stats, NULL);
+}
+
+int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                     const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                     const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                     uint64_t seed, int32_t level, int32_t *part,
+                     pmo_refine_stats *stats, const pmo_variants *var) {
   int64_t k = pmo_num_pes(levels, a);
   int64_t total = 0;
   for (int32_t v = 0; v < n; ++v) total += vwgt[v];
@@ -550,18 +625,18 @@ int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
     ++i;
     ++bodies;
     if (imb_cur <= lmax) {
-      pmo_lp_round(n, xadj, adjncy, adjwgt, levels, a, d, cur, lock, target,
-                   gain, moved);
+      pmo_lp_round_v(n, xadj, adjncy, adjwgt, levels, a, d, cur, lock, target,
+                     gain, moved, var);
       iw = 0;
       ++st.lp_iterations;
     } else if (iw < REFINE_WEAK_ROUNDS) {
-      pmo_rebalance(n, xadj, adjncy, adjwgt, vwgt, k, 0, lmax, sigma, seed,
-                    level, bodies, cur, moved);
+      pmo_rebalance_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, k, 0, lmax,
+                      sigma, seed, level, bodies, cur, moved, var);
       ++iw;
       ++st.weak_iterations;
     } else {
-      pmo_rebalance(n, xadj, adjncy, adjwgt, vwgt, k, 1, lmax, sigma, seed,
-                    level, bodies, cur, moved);
+      pmo_rebalance_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, k, 1, lmax,
+                      sigma, seed, level, bodies, cur, moved, var);
       iw = 0;
       ++st.strong_iterations;
     }
@@ -976,6 +1051,15 @@ int32_t pmo_map(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                 const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                 const int32_t *a, const int32_t *d, int64_t eps_ppm,
                 uint64_t seed, int32_t *part_out, pmo_map_stats *stats) {
+  return pmo_map_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, eps_ppm, seed,
+                   part_out, stats, NULL);
+}
+
+int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                  const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                  const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                  uint64_t seed, int32_t *part_out, pmo_map_stats *stats,
+                  const pmo_variants *var) {
   double t0 = now_seconds();
   int64_t k = pmo_num_pes(levels, a);
   int64_t total = 0;
@@ -1033,8 +1117,8 @@ int32_t pmo_map(int32_t n, const int64_t *xadj, const int32_t *adjncy,
     level_graph *g = &lv[s];
     pmo_refine_stats rs;
     double r0 = now_seconds();
-    status = pmo_refine(g->n, g->xadj, g->adjncy, g->adjwgt, g->vwgt, levels,
-                        a, d, eps_ppm, seed, s, part, &rs);
+    status = pmo_refine_v(g->n, g->xadj, g->adjncy, g->adjwgt, g->vwgt, levels,
+                          a, d, eps_ppm, seed, s, part, &rs, var);
     tr += now_seconds() - r0;
     st.level_iterations[s] = rs.iterations;
     st.j_final = rs.j_final;

@@ -55,6 +55,17 @@ typedef struct {
   double total_seconds;
 } pmo_map_stats;
 
+/* Refinement variants (Section 3.2): all zero = the method as evaluated.
+ *   jet_c_num / jet_c_den: with jet_c_num > 0, Jet's relaxed first filter of
+ *     label propagation, c = jet_c_num / jet_c_den (jet_c_den > 0);
+ *   j_rebalance: rebalancing by the J gain instead of the edge-cut loss. */
+typedef struct {
+  int32_t jet_c_num;
+  int32_t jet_c_den;
+  int32_t j_rebalance;
+  int32_t pad_;
+} pmo_variants;
+
 /* ---- hierarchy and objective (Section 2) ---- */
 int64_t pmo_num_pes(int32_t levels, const int32_t *a);
 int32_t pmo_distance(int32_t levels, const int32_t *a, const int32_t *d,
@@ -84,6 +95,22 @@ void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    int32_t level, int32_t iter, int32_t *part,
                    uint8_t *moved_out);
 int64_t pmo_sigma(int64_t lmax, int64_t total_weight, int64_t k);
+void pmo_lp_round_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                    const int32_t *adjwgt, int32_t levels, const int32_t *a,
+                    const int32_t *d, int32_t *part, uint8_t *lock,
+                    int32_t *target_out, int64_t *gain_out, uint8_t *moved_out,
+                    const pmo_variants *var);
+void pmo_rebalance_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                     const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                     const int32_t *a, const int32_t *d, int64_t k,
+                     int32_t strong, int64_t lmax, int64_t sigma, uint64_t seed,
+                     int32_t level, int32_t iter, int32_t *part,
+                     uint8_t *moved_out, const pmo_variants *var);
+int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                     const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                     const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                     uint64_t seed, int32_t level, int32_t *part,
+                     pmo_refine_stats *stats, const pmo_variants *var);
 int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                    const int32_t *a, const int32_t *d, int64_t eps_ppm,
@@ -108,6 +135,11 @@ int32_t pmo_map(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                 const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                 const int32_t *a, const int32_t *d, int64_t eps_ppm,
                 uint64_t seed, int32_t *part_out, pmo_map_stats *stats);
+int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                  const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                  const int32_t *a, const int32_t *d, int64_t eps_ppm,
+                  uint64_t seed, int32_t *part_out, pmo_map_stats *stats,
+                  const pmo_variants *var);
 
 #ifdef __cplusplus
 }

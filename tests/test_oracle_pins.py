@@ -556,3 +556,91 @@ def test_map_balance_and_levels(pmo, name, seed):
     assert ns[0] == g.n and all(x > y for x, y in zip(ns, ns[1:]))
     for x, y in zip(ns, ns[1:]):
         assert 20 * y <= 19 * x
+
+
+# ----------------------------------------------------------------------------
+# refinement variants (Section 3.2): Jet's relaxed first filter, J-objective
+# rebalancing
+# ----------------------------------------------------------------------------
+
+def test_jet_filter_hand_example(pmo):
+    # edges (0,1) w 3, (0,2) w 2; blocks [0,0,1,1]; l = 1, d = 1 (gain =
+    # conn(b) - conn(own)).  Vertex 0: gain to block 1 is 2 - 3 = -1, so it
+    # enters X only when -G = 1 < floor(c * conn(0, own) = c * 3): c = 1 yes,
+    # c = 1/2 no.  Vertex 2: gain 2 - 0 = 2.  Phase 2: vertex 2 ranks before
+    # vertex 0 (higher gain); 0's re-evaluated gain counts 2 at block 0:
+    # 3*(0-1) + 2*(0-1) = -5 < 0; 2's counts 0 at its block 0: 2*(1-0) = 2.
+    g = gen.from_edges(4, [0, 0], [1, 2], [3, 2], [1, 1, 1, 1])
+    part0 = [0, 0, 1, 1]
+    nin = np.iinfo(np.int64).min
+    for c, gains, targets in (((1, 1), [-1, nin, 2, nin], [1, 0, 0, 1]),
+                              ((1, 2), [nin, nin, 2, nin], [0, 0, 0, 1])):
+        part, lock, target, gain, moved = pmo.lp_round(g, (2,), (1,), part0, [0] * 4,
+                                                       pmo.variants(jet_c=c))
+        assert gain.tolist() == gains, c
+        assert target.tolist() == targets, c
+        assert moved.tolist() == [0, 0, 1, 0]
+        assert part.tolist() == [0, 0, 0, 1]
+
+
+@pytest.mark.parametrize("name", ["rgg14", "rmat14"])
+def test_jet_filter_with_vanishing_c_is_the_standard_method(pmo, name):
+    # floor(c * conn) = 0 for every vertex, so no negative move passes
+    w = gen.get(name)
+    g = w.graph()
+    base = pmo.map_graph(g, w.a, w.d, w.eps, 1)
+    var = pmo.map_graph(g, w.a, w.d, w.eps, 1, pmo.variants(jet_c=(1, 1 << 30)))
+    assert base[0] == var[0] and base[2].j_final == var[2].j_final
+    assert np.array_equal(base[1], var[1])
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_j_rebalance_with_one_unit_level_is_edge_cut_rebalance(pmo, strong):
+    # l = 1, d = 1: G_b(v) = conn(v,b) - conn(v,Pi(v)), the edge-cut loss
+    g = gen.get("rmat14").graph()
+    k = 64
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    part = gen.random_mapping(g.n, k, 5)
+    part[: g.n // 10] = 3
+    std = pmo.rebalance(g, k, part, strong, lm, sg, 7, 0, 1)
+    var = pmo.rebalance(g, k, part, strong, lm, sg, 7, 0, 1, a=(k,), d=(1,),
+                        var=pmo.variants(j_rebalance=True))
+    assert np.array_equal(std[0], var[0]) and np.array_equal(std[1], var[1])
+    base = pmo.map_graph(g, (k,), (1,), 0.03, 2)
+    jv = pmo.map_graph(g, (k,), (1,), 0.03, 2, pmo.variants(j_rebalance=True))
+    assert np.array_equal(base[1], jv[1]) and base[2].j_final == jv[2].j_final
+
+
+def test_j_rebalance_destinations_maximise_the_gain(pmo):
+    # every mover of a weak J-objective round goes to the eligible neighbour
+    # block of largest gain (eq. 1, pmo_gain), smaller id on ties, or, without
+    # one, to some block within sigma
+    g = gen.get("rgg14").graph()
+    a, d = (4, 4, 4), (1, 10, 100)
+    k = 64
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    part = gen.random_balanced_mapping(g.n, k, 4)
+    # overload block 9 with vertices spread over the whole graph, so that its
+    # sources have other neighbour blocks
+    part[np.random.Generator(np.random.PCG64(6)).choice(g.n, g.n // 16, replace=False)] = 9
+    w0 = pmo.block_weights(g, part, k)
+    p2, moved = pmo.rebalance(g, k, part, False, lm, sg, 3, 0, 1, a=a, d=d,
+                              var=pmo.variants(j_rebalance=True))
+    mv = np.nonzero(moved)[0]
+    assert len(mv) > 0
+    checked = 0
+    for v in mv[:400]:
+        nb = {int(part[u]) for u in g.adjncy[g.xadj[v]:g.xadj[v + 1]]}
+        cand = sorted(b for b in nb if b != part[v] and w0[b] <= sg)
+        if cand:
+            gains = [pmo.gain(g, part, a, d, int(v), b) for b in cand]
+            best = cand[int(np.argmax(gains))]  # first maximum = smaller id
+            assert p2[v] == best
+            checked += 1
+        else:
+            assert w0[p2[v]] <= sg
+    assert checked > 0
