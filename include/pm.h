@@ -87,6 +87,28 @@ typedef struct pm_hierarchy {
   int32_t d[PM_MAX_LEVELS];
 } pm_hierarchy;
 
+/* Refinement variants (Section 3.2, the alternatives the paper discusses).
+ *   PM_VARIANT_JET_FILTER: Jet's relaxed first filter of label propagation --
+ *     a vertex whose best gain G is negative still enters the first-filter
+ *     set when -G < floor(c * conn(v, own block)), c = jet_c_num / jet_c_den
+ *     (1 <= jet_c_num <= 2^15, jet_c_den >= 1); the second filter is
+ *     unchanged.
+ *   PM_VARIANT_J_REBALANCE: rebalancing ranks moves by the gain of equation
+ *     (1) instead of the edge-cut loss: the destination is the neighbour block
+ *     within the cap with the largest gain (smaller block on ties), and the
+ *     bucket of every source comes from that gain (for the pseudo-random
+ *     destination too).
+ * A NULL pm_options pointer, or variants = 0, is the method as evaluated.
+ * Invalid bits or constants: PM_EINVAL.  Host struct. */
+#define PM_VARIANT_JET_FILTER 1u
+#define PM_VARIANT_J_REBALANCE 2u
+typedef struct pm_options {
+  uint32_t variants;
+  int32_t jet_c_num;
+  int32_t jet_c_den;
+  int32_t reserved;        /* 0 */
+} pm_options;
+
 /* Statistics of one refinement run (Algorithm 6).  Host struct. */
 typedef struct pm_refine_stats {
   int64_t j_initial;         /* J of the input mapping                    */
@@ -160,6 +182,10 @@ int pm_block_weights(const pm_graph *g, const pm_hierarchy *h,
 int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part,
                 uint8_t *lock, int32_t *target_out, int64_t *gain_out,
                 uint8_t *moved_out, void *stream);
+/* pm_lp_round with refinement variants (opts may be NULL). */
+int pm_lp_round_ex(const pm_graph *g, const pm_hierarchy *h, int32_t *part,
+                   uint8_t *lock, int32_t *target_out, int64_t *gain_out,
+                   uint8_t *moved_out, const pm_options *opts, void *stream);
 
 /* One weak (strong = 0) or strong (strong = 1) rebalancing round (Section
  * 3.2, Rebalancing, Algorithm 5) with the edge-cut loss; lmax and sigma as
@@ -168,6 +194,11 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part,
 int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong,
                  int64_t lmax, int64_t sigma, uint64_t seed, int32_t level,
                  int32_t iter, int32_t *part, uint8_t *moved_out, void *stream);
+/* pm_rebalance with refinement variants (opts may be NULL). */
+int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong,
+                    int64_t lmax, int64_t sigma, uint64_t seed, int32_t level,
+                    int32_t iter, int32_t *part, uint8_t *moved_out,
+                    const pm_options *opts, void *stream);
 
 /* Refinement (Section 3.2, Algorithm 6): label propagation while balanced,
  * otherwise up to two weak then one strong rebalancing; keeps the best
@@ -178,6 +209,10 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong,
 int pm_refine(const pm_graph *g, const pm_hierarchy *h, double eps,
               uint64_t seed, int32_t level, int32_t *part,
               pm_refine_stats *stats, void *stream);
+/* pm_refine with refinement variants (opts may be NULL). */
+int pm_refine_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
+                 uint64_t seed, int32_t level, int32_t *part,
+                 pm_refine_stats *stats, const pm_options *opts, void *stream);
 
 /* Heavy-edge matching rounds (Section 3.2, Matching): rating w^2/(c(u)c(v)),
  * exact comparison with a hash tie-break, mutual preference, rounds until no
@@ -211,6 +246,10 @@ int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h,
 int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps,
            uint64_t seed, int32_t *part_out, pm_map_stats *stats,
            uint32_t flags, void *stream);
+/* pm_map with refinement variants at every level (opts may be NULL). */
+int pm_map_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
+              uint64_t seed, int32_t *part_out, pm_map_stats *stats,
+              uint32_t flags, const pm_options *opts, void *stream);
 
 /* ---------------------------------------------------------------------------
  * Many instances.  A job is one independent mapping instance: a device graph,

@@ -96,6 +96,11 @@ _SIGS = {
     "pm_contract": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pm_initial_partition": (ctypes.c_int, [_P, _P, _P, _P]),
     "pm_map": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P]),
+    "pm_lp_round_ex": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pm_rebalance_ex": (ctypes.c_int, [_P, _P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _P,
+                                       _P]),
+    "pm_refine_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P]),
+    "pm_map_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P, _P]),
     "pm_map_batch": (ctypes.c_int, [_P, _I32, _I32, _P]),
     "pm_job_footprint": (_I64, [_P, _P]),
     "pm_server_create": (_P, [_I64, _I32]),
@@ -144,6 +149,32 @@ def _torch():
 def _stream():
     torch = _torch()
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+PM_VARIANT_JET_FILTER = 1
+PM_VARIANT_J_REBALANCE = 2
+
+
+class PmOptions(ctypes.Structure):
+    _fields_ = [("variants", ctypes.c_uint32), ("jet_c_num", ctypes.c_int32),
+                ("jet_c_den", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def options(jet_c=None, j_rebalance: bool = False) -> PmOptions:
+    """Refinement variants: jet_c = (num, den) enables Jet's relaxed first
+    filter with c = num/den; j_rebalance ranks rebalancing moves by the J
+    gain."""
+    o = PmOptions()
+    if jet_c:
+        o.variants |= PM_VARIANT_JET_FILTER
+        o.jet_c_num, o.jet_c_den = int(jet_c[0]), int(jet_c[1])
+    if j_rebalance:
+        o.variants |= PM_VARIANT_J_REBALANCE
+    return o
+
+
+def _opt(o):
+    return ctypes.byref(o) if o is not None else None
 
 
 def hierarchy(a, d) -> PmHierarchy:
@@ -234,7 +265,7 @@ def pm_block_weights(g: DeviceGraph, a, d, part):
     return w
 
 
-def pm_lp_round(g: DeviceGraph, a, d, part, lock):
+def pm_lp_round(g: DeviceGraph, a, d, part, lock, opts: PmOptions = None):
     """One label-propagation round; part and lock are updated in place.
     Returns (target, gain, moved)."""
     torch = _torch()
@@ -242,32 +273,34 @@ def pm_lp_round(g: DeviceGraph, a, d, part, lock):
     gain = torch.empty(g.n, dtype=torch.int64, device=part.device)
     moved = torch.empty(g.n, dtype=torch.uint8, device=part.device)
     gs, hs = g.struct(), hierarchy(a, d)
-    _check(lib().pm_lp_round(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
-                             _dev(lock, "uint8", g.n), _dev(target, "int32"), _dev(gain, "int64"),
-                             _dev(moved, "uint8"), _stream()), "pm_lp_round")
+    _check(lib().pm_lp_round_ex(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
+                                _dev(lock, "uint8", g.n), _dev(target, "int32"),
+                                _dev(gain, "int64"), _dev(moved, "uint8"), _opt(opts), _stream()),
+           "pm_lp_round")
     return target, gain, moved
 
 
 def pm_rebalance(g: DeviceGraph, a, d, part, strong: bool, lmax: int, sigma: int, seed: int,
-                 level: int, it: int):
+                 level: int, it: int, opts: PmOptions = None):
     """One rebalancing round; part is updated in place.  Returns moved flags."""
     torch = _torch()
     moved = torch.empty(g.n, dtype=torch.uint8, device=part.device)
     gs, hs = g.struct(), hierarchy(a, d)
-    _check(lib().pm_rebalance(ctypes.byref(gs), ctypes.byref(hs), int(bool(strong)), int(lmax),
-                              int(sigma), seed & (2**64 - 1), int(level), int(it),
-                              _dev(part, "int32", g.n), _dev(moved, "uint8"), _stream()),
-           "pm_rebalance")
+    _check(lib().pm_rebalance_ex(ctypes.byref(gs), ctypes.byref(hs), int(bool(strong)),
+                                 int(lmax), int(sigma), seed & (2**64 - 1), int(level), int(it),
+                                 _dev(part, "int32", g.n), _dev(moved, "uint8"), _opt(opts),
+                                 _stream()), "pm_rebalance")
     return moved
 
 
-def pm_refine(g: DeviceGraph, a, d, eps: float, seed: int, part, level: int = 0):
+def pm_refine(g: DeviceGraph, a, d, eps: float, seed: int, part, level: int = 0,
+              opts: PmOptions = None):
     """Refinement (Algorithm 6) in place.  Returns (status, PmRefineStats)."""
     st = PmRefineStats()
     gs, hs = g.struct(), hierarchy(a, d)
-    rc = _check(lib().pm_refine(ctypes.byref(gs), ctypes.byref(hs), float(eps),
-                                seed & (2**64 - 1), int(level), _dev(part, "int32", g.n),
-                                ctypes.byref(st), _stream()), "pm_refine")
+    rc = _check(lib().pm_refine_ex(ctypes.byref(gs), ctypes.byref(hs), float(eps),
+                                   seed & (2**64 - 1), int(level), _dev(part, "int32", g.n),
+                                   ctypes.byref(st), _opt(opts), _stream()), "pm_refine")
     return rc, st
 
 
@@ -313,17 +346,22 @@ def pm_initial_partition(g: DeviceGraph, a, d):
 
 
 def pm_map(g: DeviceGraph, a, d, eps: float, seed: int, part=None, validate: bool = False,
-           kernel_times: bool = False):
+           kernel_times: bool = False, opts: PmOptions = None):
     """Full multilevel mapping.  Returns (status, part, PmMapStats)."""
     torch = _torch()
     if part is None:
         part = torch.empty(g.n, dtype=torch.int32, device=g.vwgt.device)
     st = PmMapStats()
     gs, hs = g.struct(), hierarchy(a, d)
-    rc = _check(lib().pm_map(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
-                             _dev(part, "int32", g.n), ctypes.byref(st),
-                             (PM_FLAG_VALIDATE if validate else 0)
-                             | (PM_FLAG_KERNEL_TIMES if kernel_times else 0), _stream()), "pm_map")
+    flags = (PM_FLAG_VALIDATE if validate else 0) | (PM_FLAG_KERNEL_TIMES if kernel_times else 0)
+    if opts is None:
+        rc = lib().pm_map(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
+                          _dev(part, "int32", g.n), ctypes.byref(st), flags, _stream())
+    else:
+        rc = lib().pm_map_ex(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
+                             _dev(part, "int32", g.n), ctypes.byref(st), flags, _opt(opts),
+                             _stream())
+    _check(rc, "pm_map")
     return rc, part, st
 
 
@@ -407,7 +445,8 @@ class PmServer:
         self.close()
 
 
-__all__ = ["DeviceGraph", "PmError", "PmGraph", "PmHierarchy", "PmMapStats", "PmRefineStats",
+__all__ = ["PmOptions", "options", "PM_VARIANT_JET_FILTER", "PM_VARIANT_J_REBALANCE",
+           "DeviceGraph", "PmError", "PmGraph", "PmHierarchy", "PmMapStats", "PmRefineStats",
            "hierarchy", "lib", "pm_version", "pm_release", "pm_comm_cost", "pm_block_weights",
            "pm_lp_round", "pm_rebalance", "pm_refine", "pm_hem", "pm_contract",
            "pm_initial_partition", "pm_map", "PmMapJob", "make_job", "pm_map_batch",

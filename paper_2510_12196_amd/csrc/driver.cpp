@@ -57,6 +57,21 @@ int64_t sigma_of(int64_t lmax, int64_t total, int64_t k) {
   return lmax - 100 > avg ? lmax - 100 : avg;
 }
 
+Variants variants_of(const pm_options *o) {
+  Variants v;
+  if (!o) return v;
+  if (o->variants & ~(PM_VARIANT_JET_FILTER | PM_VARIANT_J_REBALANCE))
+    throw Error(PM_EINVAL, "unknown variant bits");
+  if (o->variants & PM_VARIANT_JET_FILTER) {
+    if (o->jet_c_num < 1 || o->jet_c_num > (1 << 15) || o->jet_c_den < 1)
+      throw Error(PM_EINVAL, "jet filter needs 1 <= c_num <= 2^15 and c_den >= 1");
+    v.jet_num = o->jet_c_num;
+    v.jet_den = o->jet_c_den;
+  }
+  v.j_rebalance = (o->variants & PM_VARIANT_J_REBALANCE) != 0;
+  return v;
+}
+
 DGraph view(const pm_graph *g) {
   if (!g) throw Error(PM_EINVAL, "graph is NULL");
   if (g->n < 0 || g->nnz < 0) throw Error(PM_EINVAL, "negative graph size");
@@ -146,7 +161,7 @@ struct RefineResult {
 
 static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, const Hier &h,
                                  int64_t lmax, int64_t sigma, int64_t total, uint64_t seed,
-                                 int32_t level, int32_t *best) {
+                                 int32_t level, int32_t *best, const Variants &var) {
   Arena &ar = cx.ar;
   hipStream_t s = cx.s;
   const size_t mark = ar.mark();
@@ -193,7 +208,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     ++i;
     ++bodies;
     if (imb_cur <= lmax) {
-      lp_phase1(g, cl, h, cur, lock, target, gain, s);
+      lp_phase1(g, cl, h, cur, lock, target, gain, s, var);
       lp_phase2(g, cl, h, cur, target, gain, moved, s);
       apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, &E, s);
       iw = 0;
@@ -202,7 +217,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       const bool strong = iw >= 2;
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
       rebalance_round(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
-                      cx.dev, s);
+                      cx.dev, s, var);
       apply_moves(g, cl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, &E, s);
       if (strong) {
         iw = 0;
@@ -483,7 +498,14 @@ int pm_block_weights(const pm_graph *g, const pm_hierarchy *h, const int32_t *pa
 
 int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t *lock,
                 int32_t *target_out, int64_t *gain_out, uint8_t *moved_out, void *stream) {
+  return pm_lp_round_ex(g, h, part, lock, target_out, gain_out, moved_out, nullptr, stream);
+}
+
+int pm_lp_round_ex(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t *lock,
+                   int32_t *target_out, int64_t *gain_out, uint8_t *moved_out,
+                   const pm_options *opts, void *stream) {
   return guarded([&] {
+    const Variants var = variants_of(opts);
     check_device();
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
@@ -501,7 +523,7 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t
     Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
     int64_t *w = lease->alloc_n<int64_t>((size_t)1 << hh.bits);
     block_weights(dg, hh, codes, w, s);
-    lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s);
+    lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s, var);
     lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
     apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w,
                 alloc_weight_stripes(*lease, hh, s), cx.sp.a, nullptr, s);
@@ -515,7 +537,15 @@ int pm_lp_round(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint8_t
 int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64_t lmax,
                  int64_t sigma, uint64_t seed, int32_t level, int32_t iter, int32_t *part,
                  uint8_t *moved_out, void *stream) {
+  return pm_rebalance_ex(g, h, strong, lmax, sigma, seed, level, iter, part, moved_out, nullptr,
+                         stream);
+}
+
+int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64_t lmax,
+                    int64_t sigma, uint64_t seed, int32_t level, int32_t iter, int32_t *part,
+                    uint8_t *moved_out, const pm_options *opts, void *stream) {
   return guarded([&] {
+    const Variants var = variants_of(opts);
     check_device();
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
@@ -541,7 +571,7 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
-                    moved_out, rb, cx.dev, s);
+                    moved_out, rb, cx.dev, s, var);
     apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s),
                 cx.sp.a, nullptr, s);
     codes_to_ids(hh, codes, part, dg.n, s);
@@ -552,7 +582,14 @@ int pm_rebalance(const pm_graph *g, const pm_hierarchy *h, int32_t strong, int64
 
 int pm_refine(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, int32_t level,
               int32_t *part, pm_refine_stats *stats, void *stream) {
+  return pm_refine_ex(g, h, eps, seed, level, part, stats, nullptr, stream);
+}
+
+int pm_refine_ex(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+                 int32_t level, int32_t *part, pm_refine_stats *stats, const pm_options *opts,
+                 void *stream) {
   return guarded([&] {
+    const Variants var = variants_of(opts);
     check_device();
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
@@ -570,7 +607,7 @@ int pm_refine(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t see
     ids_to_codes(hh, part, best, dg.n, s);
     int32_t *list = ar.alloc_n<int32_t>(dg.n);
     Classes cl = build_classes(ar, dg, list, cx.dev, cx.host, s);
-    RefineResult R = refine_level(cx, dg, cl, hh, lmax, sigma, total, seed, level, best);
+    RefineResult R = refine_level(cx, dg, cl, hh, lmax, sigma, total, seed, level, best, var);
     codes_to_ids(hh, best, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     if (stats) *stats = R.st;
@@ -650,9 +687,16 @@ int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h, int32_t *part
 
 int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, int32_t *part_out,
            pm_map_stats *stats, uint32_t flags, void *stream) {
+  return pm_map_ex(g, h, eps, seed, part_out, stats, flags, nullptr, stream);
+}
+
+int pm_map_ex(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+              int32_t *part_out, pm_map_stats *stats, uint32_t flags, const pm_options *opts,
+              void *stream) {
   return guarded([&] {
+    const Variants var = variants_of(opts);
     check_device();
-    return map_impl(g, h, eps, seed, part_out, stats, flags, as_stream(stream));
+    return map_impl(g, h, eps, seed, part_out, stats, flags, as_stream(stream), var);
   });
 }
 
@@ -661,7 +705,8 @@ int pm_map(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed, 
 namespace pm {
 // The whole multilevel mapping on stream `stream` (throws Error).
 int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
-             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream) {
+             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream,
+             const Variants &var) {
   {
     const auto t_start = std::chrono::steady_clock::now();
     const DGraph dg = view(g);
@@ -759,7 +804,7 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
     int32_t status = PM_OK;
     for (int lv = t;; --lv) {
       const Level &L = levels[lv];
-      RefineResult R = refine_level(cx, L.g, L.cl, hh, lmax, sigma, total, seed, lv, part);
+      RefineResult R = refine_level(cx, L.g, L.cl, hh, lmax, sigma, total, seed, lv, part, var);
       st.refine_ms += R.st.refine_ms;
       st.refine_arcs += R.st.arcs_processed;
       st.level_iterations[lv] = R.st.iterations;

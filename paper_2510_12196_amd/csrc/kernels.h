@@ -119,9 +119,19 @@ void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
                    hipStream_t s);                     // w[0..2^bits)
 
+// ---- refinement variants (Section 3.2) ----------------------------------------
+// jet_num > 0: Jet's relaxed first filter, c = jet_num / jet_den;
+// j_rebalance: rebalancing by the J gain instead of the edge-cut loss.
+struct Variants {
+  int64_t jet_num = 0;
+  int64_t jet_den = 1;
+  bool j_rebalance = false;
+};
+
 // ---- label propagation (Algorithm 4) --------------------------------------
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s);
+               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
+               const Variants &var = Variants{});
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
@@ -164,7 +174,8 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
-                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s);
+                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
+                     const Variants &var = Variants{});
 
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
@@ -198,7 +209,8 @@ void project(int32_t n, const int32_t *cmap, const int32_t *coarse, int32_t *fin
 // ---- whole mapping ------------------------------------------------------------
 // The multilevel mapping of one instance on `stream` (throws Error).
 int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
-             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream);
+             int32_t *part_out, pm_map_stats *stats, uint32_t flags, hipStream_t stream,
+             const Variants &var = Variants{});
 
 // ---- misc -----------------------------------------------------------------
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);

@@ -454,7 +454,14 @@ struct LP1Args {
   const uint8_t *lock;
   int32_t *target;
   int64_t *gain;
+  int64_t jet_num;  // > 0: relaxed filter -G < floor(jet_num * conn(v,own) / jet_den)
+  int64_t jet_den;
 };
+
+// First filter: G >= 0, or with Jet's relaxed filter -G < floor(c conn_own).
+__device__ __forceinline__ bool lp1_pass(const LP1Args &A, int64_t g, int64_t conn_own) {
+  return g >= 0 || (A.jet_num > 0 && -g < (A.jet_num * conn_own) / A.jet_den);
+}
 
 struct Lp1V {
   uint32_t p;
@@ -498,8 +505,9 @@ __device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) 
         int64_t g = cand ? costp - cost : INT64_MIN;
         uint32_t b = cand ? bu : 0xFFFFFFFFu;
         gargmax<G>(g, b);
+        const int64_t conn_own = A.jet_num > 0 ? gsum64<G>(valid && bu == p ? wu : 0) : 0;
         if (lane == 0) {
-          if (g >= 0) {
+          if (lp1_pass(A, g, conn_own)) {
             A.target[v] = (int32_t)b;
             A.gain[v] = g;
           } else {
@@ -577,7 +585,7 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X
   }
   block_argmax(g, b, sc);
   if (threadIdx.x == 0) {
-    if (g >= 0) {
+    if (lp1_pass(A, g, (int64_t)connp)) {
       A.target[v] = (int32_t)b;
       A.gain[v] = g;
     } else {
@@ -614,12 +622,13 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
 static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << h.bits) + 1); }
 
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s) {
+               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
+               const Variants &var) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP1Args A{g, tc, h, part, lock, target, gain};
+  LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1};
   auto kern = V == 2 ? k_lp_phase1<2> : k_lp_phase1<1>;
   if (tl_timer) {
     hipEvent_t a, b;
@@ -963,6 +972,7 @@ struct RebArgs {
   int32_t *key;
   int32_t *dest;
   int64_t *bw;   // bucket weight stripes [stripe][code][bucket]
+  int32_t jrb;   // loss = J gain of eq. 1 (variant) instead of the edge-cut loss
 };
 
 __device__ __forceinline__ int32_t bucket_of(int64_t g) {
@@ -990,23 +1000,38 @@ __device__ __forceinline__ void bw_flush(const RebArgs &A, const BwAdd &x) {
 
 // Final decision for a source v with best neighbour block (b, conn_b) or none
 // (b == 0xFFFFFFFF), conn to own block connp.
-__device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
-                                           int64_t conn_b, int64_t connp, BwAdd &add) {
-  if (b == 0xFFFFFFFFu) {
-    const int32_t ne = *A.n_elig;
-    if (ne <= 0) {
-      A.key[v] = -1;
-      return;
-    }
-    b = (uint32_t)A.elig[mix_hash(A.hseed, (uint64_t)v) % (uint64_t)ne];
-    conn_b = 0;
-  }
-  const int32_t bucket = bucket_of(conn_b - connp);
+// Source v of block p goes to b with loss g (bucket, key, destination).
+__device__ __forceinline__ void reb_finish(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
+                                           int64_t g, BwAdd &add) {
+  const int32_t bucket = bucket_of(g);
   A.key[v] = (int32_t)((p << 6) | (uint32_t)bucket);
   A.dest[v] = (int32_t)b;
   add.has = true;
   add.key = (p << 6) | (uint32_t)bucket;
   add.c = A.g.c[v];
+}
+
+// The pseudo-random destination among the blocks within the cap (false:
+// there is none).
+__device__ __forceinline__ bool reb_random(const RebArgs &A, int32_t v, uint32_t &b) {
+  const int32_t ne = *A.n_elig;
+  if (ne <= 0) return false;
+  b = (uint32_t)A.elig[mix_hash(A.hseed, (uint64_t)v) % (uint64_t)ne];
+  return true;
+}
+
+// Edge-cut loss: destination b with connection conn_b, or none (b ==
+// 0xFFFFFFFF: the random block, connection 0); connp = conn(v, p).
+__device__ __forceinline__ void reb_decide(const RebArgs &A, int32_t v, uint32_t p, uint32_t b,
+                                           int64_t conn_b, int64_t connp, BwAdd &add) {
+  if (b == 0xFFFFFFFFu) {
+    if (!reb_random(A, v, b)) {
+      A.key[v] = -1;
+      return;
+    }
+    conn_b = 0;
+  }
+  reb_finish(A, v, p, b, conn_b - connp, add);
 }
 
 __device__ __forceinline__ void reb_not_source(const RebArgs &A, int32_t v) { A.key[v] = -1; }
@@ -1041,8 +1066,32 @@ __device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) 
         }
         const uint32_t bu = valid ? nv.bu : p;
         const int32_t wu = valid ? nv.wu : 0;
-        const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
         const bool cand = valid && bu != p && nv.capok;
+        if (A.jrb) {
+          // J gain of eq. 1: cost(p) - cost(b), cost(x) = sum_j w_j D(x, b_j)
+          const int64_t costp = gsum64<G>((int64_t)wu * dist(A.h, p, bu));
+          int64_t cost = 0;
+          for (int j = 0; j < deg; ++j) {
+            const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
+            const int32_t wj = gshfl<G>(wu, j);
+            cost += (int64_t)wj * dist(A.h, bu, bj);
+          }
+          int64_t val = cand ? costp - cost : INT64_MIN;
+          uint32_t b = cand ? bu : 0xFFFFFFFFu;
+          gargmax<G>(val, b);
+          if (b == 0xFFFFFFFFu) {  // group-uniform
+            uint32_t br;
+            if (!reb_random(A, v, br)) {
+              if (lane == 0) reb_not_source(A, v);
+              return;
+            }
+            val = costp - gsum64<G>((int64_t)wu * dist(A.h, br, bu));
+            b = br;
+          }
+          if (lane == 0) reb_finish(A, v, p, b, val, add[r]);
+          return;
+        }
+        const int64_t connp = gsum64<G>(bu == p ? (int64_t)wu : 0);
         int64_t conn = 0;
         for (int j = 0; j < deg; ++j) {
           const uint32_t bj = (uint32_t)gshfl<G>((int32_t)bu, j);
@@ -1068,20 +1117,30 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
   }
   const int32_t ncodes = 1 << A.h.bits;
   big_histogram(A.g, A.part, v, X, ncodes, sc);
+  const int64_t costp = A.jrb ? level_cost(A.h, X, p, ncodes) : 0;
   int64_t val = INT64_MIN;
   uint32_t b = 0xFFFFFFFFu;
   for (int c = threadIdx.x; c < ncodes; c += kThreads) {
     const uint32_t conn = X[c + 1] - X[c];
     if ((uint32_t)c == p || conn == 0 || A.w[c] > A.cap) continue;
-    if ((int64_t)conn > val) {
-      val = conn;
+    const int64_t x = A.jrb ? costp - level_cost(A.h, X, (uint32_t)c, ncodes) : (int64_t)conn;
+    if (x > val) {
+      val = x;
       b = (uint32_t)c;
     }
   }
   block_argmax(val, b, sc);
   if (threadIdx.x == 0) {
     BwAdd add;
-    reb_decide(A, v, p, b, val, (int64_t)(X[p + 1] - X[p]), add);
+    if (!A.jrb) {
+      reb_decide(A, v, p, b, val, (int64_t)(X[p + 1] - X[p]), add);
+    } else if (b != 0xFFFFFFFFu) {
+      reb_finish(A, v, p, b, val, add);
+    } else if (reb_random(A, v, b)) {
+      reb_finish(A, v, p, b, costp - level_cost(A.h, X, b, ncodes), add);
+    } else {
+      reb_not_source(A, v);
+    }
     if (add.has)
       atomic_add_any(&A.bw[((size_t)(blockIdx.x & (kBucketStripes - 1)) << A.h.bits) * kBuckets +
                            add.key],
@@ -1526,7 +1585,8 @@ static void keyed_prefix(KPArgs A, hipStream_t s) {
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
-                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s) {
+                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
+                     const Variants &var) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
@@ -1549,7 +1609,8 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
               st_dev,
               rb.key,
               rb.dest,
-              rb.bw};
+              rb.bw,
+              var.j_rebalance ? 1 : 0};
     auto kern = V == 2 ? k_reb_select<2> : k_reb_select<1>;
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
     PM_LAUNCH_CHECK();

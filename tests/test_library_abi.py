@@ -60,6 +60,7 @@ def test_struct_layouts_match_header():
     assert pm.PmMapStats.refine_arcs.offset + 8 == pm.PmMapStats.kernel_launches.offset
     # pm_map_job: graph 48, hierarchy 68 (+4 padding), eps, seed, part, 2 x int32, j, ms
     assert ctypes.sizeof(pm.PmMapJob) == 168 and pm.PmMapJob.eps.offset == 120
+    assert ctypes.sizeof(pm.PmOptions) == 16
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
