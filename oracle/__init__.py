@@ -24,7 +24,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_POSIX_C_SOURCE=199309L",
-                               "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC])
+                               "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -72,6 +72,9 @@ _SIGS = {
     "pmo_contract": (_I64, [_I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P]),
     "pmo_initial_partition": (None, [_I32, _P, _P, _P, _I32, _P, _P]),
     "pmo_map": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _P, _P]),
+    "pmo_subgraphs": (_I64, [_I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
+    "pmo_adaptive_eps_ppm": (_I64, [_I64, _I64, _I64, _I64, _I64, _I32]),
+    "pmo_hm": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _I64, _U64, _P]),
     "pmo_lp_round_v": (None, [_I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pmo_rebalance_v": (None, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _I32, _I64, _I64,
                                _U64, _I32, _I32, _P, _P, _P]),
@@ -272,3 +275,35 @@ def map_graph(g, a, d, eps, seed, var=None):
                          lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1),
                          _ptr(part), ctypes.byref(st), _var(var))
     return int(rc), part, st
+
+
+def subgraphs(g, part, parts: int):
+    """Induced subgraphs of a partition (Algorithm 1).  Returns a dict with
+    vstart, estart, order, xadj, adjncy, adjwgt, vwgt (blocks concatenated)."""
+    part = _i32(part)
+    n = g.n
+    vstart = np.empty(parts + 1, np.int32)
+    estart = np.empty(parts + 1, np.int64)
+    order = np.empty(max(n, 1), np.int32)
+    xo = np.empty(n + parts, np.int64)
+    ao = np.empty(max(g.nnz, 1), np.int32)
+    wo = np.empty(max(g.nnz, 1), np.int32)
+    vo = np.empty(max(n, 1), np.int32)
+    m = lib().pmo_subgraphs(n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                            _ptr(part), parts, _ptr(vstart), _ptr(estart), _ptr(order),
+                            _ptr(xo), _ptr(ao), _ptr(wo), _ptr(vo))
+    return {"vstart": vstart, "estart": estart, "order": order[:n], "xadj": xo,
+            "adjncy": ao[:m], "adjwgt": wo[:m], "vwgt": vo[:n]}
+
+
+def adaptive_eps_ppm(eps_ppm: int, kp: int, k: int, cv: int, cvp: int, d: int) -> int:
+    return int(lib().pmo_adaptive_eps_ppm(eps_ppm, kp, k, cv, cvp, d))
+
+
+def hm(g, a, eps, seed):
+    """Recursive hierarchical multisection (Algorithm 2).  Returns (status, part)."""
+    a = _i32(a)
+    part = np.empty(max(g.n, 1), np.int32)
+    rc = lib().pmo_hm(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                      a.shape[0], _ptr(a), eps_to_ppm(eps), seed & (2**64 - 1), _ptr(part))
+    return int(rc), part[: g.n]

@@ -24,6 +24,7 @@
 #include <stdlib.h>
 #include <string.h>
 #include <time.h>
+#include <math.h>
 
 #define NOT_IN_X INT64_MIN
 
@@ -1145,4 +1146,155 @@ int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
   st.total_seconds = now_seconds() - t0;
   if (stats) *stats = st;
   return status;
+}
+
+/* ======================================================================
+ * Hierarchical multisection (Section 3.1, Algorithms 1 and 2)
+ * ====================================================================== */
+
+/* The induced subgraphs of a partition into `parts` blocks (Algorithm 1, all
+ * blocks at once).  Block b's vertices are the vertices v with part[v] = b in
+ * ascending id order; its local id of v is v's rank among them.  Outputs, all
+ * blocks concatenated in block order:
+ *   vstart[parts+1]  first position of each block in order[]
+ *   estart[parts+1]  first arc of each block
+ *   order[n]         original id at every position
+ *   xadj_out[n+parts] block b's row offsets (relative to estart[b]) at
+ *                    xadj_out[vstart[b] + b .. vstart[b+1] + b]
+ *   adjncy_out, adjwgt_out: each row keeps the neighbours of the same block
+ *                    in the original row order, as local ids
+ *   vwgt_out[n]      vertex weights by position
+ * Returns the number of arcs kept. */
+int64_t pmo_subgraphs(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                      const int32_t *adjwgt, const int32_t *vwgt, const int32_t *part,
+                      int32_t parts, int32_t *vstart, int64_t *estart, int32_t *order,
+                      int64_t *xadj_out, int32_t *adjncy_out, int32_t *adjwgt_out,
+                      int32_t *vwgt_out) {
+  int32_t *local = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t b = 0; b <= parts; ++b) vstart[b] = 0;
+  for (int32_t v = 0; v < n; ++v) ++vstart[part[v] + 1];
+  for (int32_t b = 0; b < parts; ++b) vstart[b + 1] += vstart[b];
+  int32_t *fill = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(parts > 0 ? parts : 1));
+  for (int32_t b = 0; b < parts; ++b) fill[b] = vstart[b];
+  for (int32_t v = 0; v < n; ++v) {
+    int32_t b = part[v];
+    local[v] = fill[b] - vstart[b];
+    order[fill[b]++] = v;
+  }
+  int64_t arcs = 0;
+  for (int32_t b = 0; b < parts; ++b) {
+    estart[b] = arcs;
+    int64_t rel = 0;
+    for (int32_t j = vstart[b]; j < vstart[b + 1]; ++j) {
+      int32_t v = order[j];
+      xadj_out[j + b] = rel;
+      vwgt_out[j] = vwgt[v];
+      for (int64_t e = xadj[v]; e < xadj[v + 1]; ++e) {
+        int32_t u = adjncy[e];
+        if (part[u] != b) continue;
+        adjncy_out[arcs] = local[u];
+        adjwgt_out[arcs] = adjwgt[e];
+        ++arcs;
+        ++rel;
+      }
+    }
+    xadj_out[vstart[b + 1] + b] = rel;
+  }
+  estart[parts] = arcs;
+  free(fill);
+  free(local);
+  return arcs;
+}
+
+/* Adaptive imbalance for a subgraph of weight cvp that will end up in kp of
+ * the k blocks, d hierarchy levels from the bottom (equation (2)):
+ * eps' = ((1 + eps) kp c(V) / (k c(V')))^(1/d) - 1, in parts per million,
+ * rounded, never negative. */
+int64_t pmo_adaptive_eps_ppm(int64_t eps_ppm, int64_t kp, int64_t k, int64_t cv,
+                             int64_t cvp, int32_t d) {
+  if (cvp <= 0 || d <= 0) return eps_ppm;
+  double eps = (double)eps_ppm / 1e6;
+  double base = ((1.0 + eps) * (double)kp) * (double)cv / ((double)k * (double)cvp);
+  double e = pow(base, 1.0 / (double)d) - 1.0;
+  int64_t ppm = llround(e * 1e6);
+  return ppm > 0 ? ppm : 0;
+}
+
+typedef struct {
+  int32_t levels;
+  const int32_t *a;
+  int64_t k, cv, eps_ppm;
+  uint64_t seed;
+  int32_t *part_out;
+  int32_t status;
+} hm_ctx;
+
+static void hm_rec(hm_ctx *c, int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                   const int32_t *adjwgt, const int32_t *vwgt, const int32_t *orig,
+                   int32_t i, int64_t base) {
+  int64_t kp = 1;
+  for (int32_t j = 0; j < i; ++j) kp *= c->a[j];
+  int64_t cvp = 0;
+  for (int32_t v = 0; v < n; ++v) cvp += vwgt[v];
+  int64_t ppm = pmo_adaptive_eps_ppm(c->eps_ppm, kp, c->k, c->cv, cvp, i);
+  int32_t ai = c->a[i - 1], one = 1;
+  int32_t *part = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t st = pmo_map(n, xadj, adjncy, adjwgt, vwgt, 1, &ai, &one, ppm, c->seed, part, NULL);
+  if (st > c->status) c->status = st;
+  int64_t pstride = kp / ai; /* P_{i-1} */
+  if (i == 1) {
+    for (int32_t v = 0; v < n; ++v) c->part_out[orig[v]] = (int32_t)(base + part[v]);
+    free(part);
+    return;
+  }
+  int64_t nnz = xadj[n];
+  int32_t *vstart = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(ai > 0 ? ai + 1 : 1));
+  int64_t *estart = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(ai > 0 ? ai + 1 : 1));
+  int32_t *order = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *sx = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)(n > 0 ? n + ai : ai));
+  int32_t *sa = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int32_t *sw = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+  int32_t *sv = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  int32_t *so = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  pmo_subgraphs(n, xadj, adjncy, adjwgt, vwgt, part, ai, vstart, estart, order, sx, sa, sw, sv);
+  for (int32_t j = 0; j < n; ++j) so[j] = orig[order[j]];
+  for (int32_t b = 0; b < ai; ++b)
+    hm_rec(c, vstart[b + 1] - vstart[b], sx + vstart[b] + b, sa + estart[b], sw + estart[b],
+           sv + vstart[b], so + vstart[b], i - 1, base + (int64_t)b * pstride);
+  free(vstart);
+  free(estart);
+  free(order);
+  free(sx);
+  free(sa);
+  free(sw);
+  free(sv);
+  free(so);
+  free(part);
+}
+
+/* Recursive hierarchical multisection (Algorithm 2): partition the graph into
+ * a_l blocks with the adaptive imbalance of equation (2), build the induced
+ * subgraphs, partition each into a_{l-1} blocks, and so on down to a_1.  The
+ * graph partitioner is pmo_map with the one-level hierarchy (a_i) and d = 1,
+ * where J is twice the edge cut.  A vertex's block is the mixed-radix number
+ * of its digits, a_1 least significant.  Returns 1 if any partitioning call
+ * ended imbalanced, else 0. */
+int32_t pmo_hm(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+               const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+               const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out) {
+  hm_ctx c;
+  c.levels = levels;
+  c.a = a;
+  c.k = pmo_num_pes(levels, a);
+  c.cv = 0;
+  for (int32_t v = 0; v < n; ++v) c.cv += vwgt[v];
+  c.eps_ppm = eps_ppm;
+  c.seed = seed;
+  c.part_out = part_out;
+  c.status = 0;
+  int32_t *orig = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  for (int32_t v = 0; v < n; ++v) orig[v] = v;
+  hm_rec(&c, n, xadj, adjncy, adjwgt, vwgt, orig, levels, 0);
+  free(orig);
+  return c.status;
 }

@@ -141,6 +141,18 @@ int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                   uint64_t seed, int32_t *part_out, pmo_map_stats *stats,
                   const pmo_variants *var);
 
+/* ---- hierarchical multisection (Section 3.1, Algorithms 1 and 2) ---- */
+int64_t pmo_subgraphs(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                      const int32_t *adjwgt, const int32_t *vwgt, const int32_t *part,
+                      int32_t parts, int32_t *vstart, int64_t *estart, int32_t *order,
+                      int64_t *xadj_out, int32_t *adjncy_out, int32_t *adjwgt_out,
+                      int32_t *vwgt_out);
+int64_t pmo_adaptive_eps_ppm(int64_t eps_ppm, int64_t kp, int64_t k, int64_t cv,
+                             int64_t cvp, int32_t d);
+int32_t pmo_hm(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+               const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+               const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -644,3 +644,85 @@ def test_j_rebalance_destinations_maximise_the_gain(pmo):
         else:
             assert w0[p2[v]] <= sg
     assert checked > 0
+
+
+# ----------------------------------------------------------------------------
+# hierarchical multisection (Section 3.1, Algorithms 1 and 2)
+# ----------------------------------------------------------------------------
+
+def test_subgraphs_hand_example(pmo):
+    # path 0-1-2-3-4 (weights 1..4), blocks [1,0,1,1,0]: block 0 = {1,4} with
+    # no inner edge; block 1 = {0,2,3} with the edge 2-3 (weight 3) only
+    g = gen.from_edges(5, [0, 1, 2, 3], [1, 2, 3, 4], [1, 2, 3, 4], [5, 6, 7, 8, 9])
+    s = pmo.subgraphs(g, [1, 0, 1, 1, 0], 2)
+    assert s["vstart"].tolist() == [0, 2, 5]
+    assert s["estart"].tolist() == [0, 0, 2]
+    assert s["order"].tolist() == [1, 4, 0, 2, 3]
+    # block 0 rows at xadj[0..2], block 1 rows at xadj[3..6]
+    assert s["xadj"].tolist() == [0, 0, 0, 0, 0, 1, 2]
+    assert s["adjncy"].tolist() == [2, 1]          # local ids: 2 -> 1, 3 -> 2
+    assert s["adjwgt"].tolist() == [3, 3]
+    assert s["vwgt"].tolist() == [6, 9, 5, 7, 8]
+
+
+@pytest.mark.parametrize("name", ["rgg14", "rmat14"])
+def test_subgraphs_are_the_induced_subgraphs(pmo, name):
+    g = gen.get(name).graph()
+    parts = 7
+    part = gen.random_mapping(g.n, parts, 9)
+    s = pmo.subgraphs(g, part, parts)
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    inner = part[src] == part[g.adjncy]
+    assert s["estart"][-1] == int(inner.sum())
+    for b in range(parts):
+        lo, hi = s["vstart"][b], s["vstart"][b + 1]
+        verts = s["order"][lo:hi]
+        assert np.array_equal(verts, np.nonzero(part == b)[0])   # id order
+        x = s["xadj"][lo + b: hi + b + 1]
+        adj = s["adjncy"][s["estart"][b]: s["estart"][b + 1]]
+        wgt = s["adjwgt"][s["estart"][b]: s["estart"][b + 1]]
+        for j in range(0, len(verts), max(1, len(verts) // 50)):
+            v = verts[j]
+            row = g.adjncy[g.xadj[v]:g.xadj[v + 1]]
+            keep = part[row] == b
+            assert np.array_equal(verts[adj[x[j]:x[j + 1]]], row[keep])
+            assert np.array_equal(wgt[x[j]:x[j + 1]], g.adjwgt[g.xadj[v]:g.xadj[v + 1]][keep])
+
+
+def test_adaptive_imbalance_closed_forms(pmo):
+    # top level of l = 3 with eps = 3 %: 1.03^(1/3) - 1 = 0.00990163...
+    assert pmo.adaptive_eps_ppm(30000, 256, 256, 1000, 1000, 3) == 9902
+    # one level left, a subgraph of exactly its share: eps unchanged
+    assert pmo.adaptive_eps_ppm(30000, 8, 256, 32000, 1000, 1) == 30000
+    # a subgraph 1 % heavier than its share, two levels left
+    want = round(((1.03 * 64 * 100000) / (256 * 25250)) ** 0.5 * 1e6 - 1e6)
+    assert pmo.adaptive_eps_ppm(30000, 64, 256, 100000, 25250, 2) == want
+    # never negative
+    assert pmo.adaptive_eps_ppm(30000, 8, 256, 32000, 2000, 1) == 0
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14"])
+def test_hm_with_one_level_is_the_edge_cut_partitioner(pmo, name):
+    g = gen.get(name).graph()
+    rc, part = pmo.hm(g, (16,), 0.03, 3)
+    rc2, part2, _ = pmo.map_graph(g, (16,), (1,), 0.03, 3)
+    assert rc == rc2 and np.array_equal(part, part2)
+
+
+@pytest.mark.parametrize("name,a", [("rgg14", (4, 8, 8)), ("rmat14", (4, 16, 8)),
+                                    ("grid64", (2, 2, 4)), ("rgg14", (4, 8, 3))])
+def test_hm_is_hierarchical_and_balanced(pmo, name, a):
+    g = gen.get(name).graph()
+    k = int(np.prod(a))
+    rc, part = pmo.hm(g, a, 0.03, 1)
+    assert part.min() >= 0 and part.max() < k
+    # the top-level digit is one partition of the whole graph into a_l blocks:
+    # it equals the edge-cut partitioner with the adaptive imbalance of the
+    # top level
+    top = part // (k // a[-1])
+    ppm = pmo.adaptive_eps_ppm(30000, k, k, int(g.vwgt.sum()), int(g.vwgt.sum()), len(a))
+    rc2, top2, _ = pmo.map_graph(g, (a[-1],), (1,), ppm / 1e6, 1)
+    assert np.array_equal(top, top2)
+    if rc == 0:
+        w = pmo.block_weights(g, part, k)
+        assert w.max() <= pmo.lmax(int(g.vwgt.sum()), k, 0.03)
