@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise pass over 512 MiB (known traffic: 512 MiB "
                          "read, 512 MiB written) for scaling hardware byte counters")
+    ap.add_argument("--hm", action="store_true",
+                    help="time hierarchical multisection (GPU-HM) on the workload beside the "
+                         "multilevel mapping")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="summarise rocprofv3 --pmc counter CSVs under DIR and exit")
     args = ap.parse_args()
@@ -152,6 +155,8 @@ def main():
     log(f"workload {w.name}: n={g.n} arcs={g.nnz} k={w.k} built in {time.perf_counter() - t:.1f}s")
     dg = pm.DeviceGraph.from_host(g)
     torch.cuda.synchronize()
+    if args.hm:
+        return bench_hm(args, w, g, dg)
 
     def step(i, kernel_times):
         return pm.pm_map(dg, w.a, w.d, w.eps, 1 + i % 5, kernel_times=kernel_times)
@@ -257,6 +262,68 @@ def main():
         }
         line["parity_seed1"] = parity
         log(f"oracle: {ocpu:.2f}s, parity {parity}")
+    print(json.dumps(line), flush=True)
+
+
+def bench_hm(args, w, g, dg):
+    """Hierarchical multisection (Section 3.1, the GPU-HM variant): every
+    level's subgraphs partitioned by the multilevel mapper with (a_i), d = 1
+    and the adaptive imbalance of equation (2).  Timed beside the multilevel
+    mapping of the same graph and seeds; J of both under the full hierarchy."""
+    import statistics as stt
+
+    import numpy as np
+    import torch
+
+    import paper_2510_12196_amd as pm
+    for i in range(args.warmup):
+        rc, part, j, calls = pm.pm_map_hm(dg, w.a, w.d, w.eps, 1 + i % 5)
+        log(f"warmup {i}: rc={rc} J={j} calls={calls}")
+    torch.cuda.synchronize()
+    hm_ms, hm_j, im_ms, im_j, rcs = [], [], [], [], set()
+    first = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        t = time.perf_counter()
+        rc, part, j, calls = pm.pm_map_hm(dg, w.a, w.d, w.eps, 1 + i % 5)
+        torch.cuda.synchronize()
+        hm_ms.append((time.perf_counter() - t) * 1e3)
+        hm_j.append(j)
+        rcs.add(rc)
+        if i == 0:
+            first = (rc, part.cpu().numpy())
+    wall = time.perf_counter() - t0
+    for i in range(args.steps):
+        t = time.perf_counter()
+        rc, part, st = pm.pm_map(dg, w.a, w.d, w.eps, 1 + i % 5)
+        torch.cuda.synchronize()
+        im_ms.append((time.perf_counter() - t) * 1e3)
+        im_j.append(st.j_final)
+    log(f"hm {stt.median(hm_ms):.2f} ms, multilevel {stt.median(im_ms):.2f} ms")
+    line = {
+        "metric": "hierarchical multisection time", "value": round(stt.median(hm_ms), 3),
+        "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {**w.describe(), "n": g.n, "arcs": g.nnz, "seeds": "1..5 cyclic",
+                   "partitioner": "multilevel mapper, (a_i), d=1"},
+        "hm_partitioning_calls": calls,
+        "hm_J_mean": round(stt.fmean(hm_j), 1), "multilevel_J_mean": round(stt.fmean(im_j), 1),
+        "J_ratio_hm_over_multilevel": round(stt.fmean(hm_j) / stt.fmean(im_j), 4),
+        "multilevel_ms_median": round(stt.median(im_ms), 3),
+        "status": sorted(rcs),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        log("cpu baseline: oracle hm, seed 1, single thread")
+        t = time.perf_counter()
+        orc, opart = oracle.hm(g, w.a, w.eps, 1)
+        ocpu = time.perf_counter() - t
+        line["cpu_baseline"] = {"value": round(ocpu * 1e3, 1), "unit": "ms", "cores": 1,
+                                "kind": "oracle", "sample": f"one hm of {w.name} (seed 1)"}
+        line["parity_seed1"] = bool(orc == first[0] and np.array_equal(first[1], opart))
+        log(f"oracle: {ocpu:.2f}s, parity {line['parity_seed1']}")
     print(json.dumps(line), flush=True)
 
 

@@ -251,6 +251,40 @@ int pm_map_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
               uint64_t seed, int32_t *part_out, pm_map_stats *stats,
               uint32_t flags, const pm_options *opts, void *stream);
 
+/* Induced subgraphs of a partition (Section 3.1, Algorithm 1), all blocks at
+ * once.  Block b's vertices are numbered in ascending input id order; its
+ * subgraph keeps every arc whose two ends lie in b, in the input row order,
+ * with the local ids and the arc weights.  part: device int32[n], every id in
+ * [0, parts) (else PM_EINVAL, nothing defined written).  Outputs (device,
+ * caller-allocated): vstart int32[parts+1] first position of each block in
+ * order; estart int64[parts+1] first arc of each block; order int32[n] input
+ * id per position; xadj_out int64[n+parts], block b's row offsets (relative to
+ * its first arc) at [vstart[b]+b, vstart[b+1]+b]; adjncy_out and adjwgt_out
+ * int32[nnz] (estart[parts] arcs used); vwgt_out int32[n] by position.
+ * arcs_out: host, may be NULL, total arcs kept. */
+int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts,
+                 int32_t *vstart, int64_t *estart, int32_t *order,
+                 int64_t *xadj_out, int32_t *adjncy_out, int32_t *adjwgt_out,
+                 int32_t *vwgt_out, int64_t *arcs_out, void *stream);
+
+/* Hierarchical multisection (Section 3.1, Algorithm 2, the GPU-HM variant):
+ * partition into a_l blocks, then every block's induced subgraph into
+ * a_{l-1} blocks, down to a_1; the partitioner is pm_map with the one-level
+ * hierarchy (a_i) and d = 1.  A subgraph of weight c(V') that ends up in k'
+ * = a_1 ... a_i of the k blocks, i levels from the bottom, gets the adaptive
+ * imbalance of equation (2), eps' = ((1 + eps) k' c(V) / (k c(V')))^(1/i) - 1,
+ * taken in whole parts per million (rounded, at least 0).  A vertex's block
+ * is the mixed-radix number of its digits, a_1 least significant.  h is
+ * checked as for pm_map; the partitioning reads only h->levels and h->a, and
+ * j_out (host, may be NULL) receives J of the result under all of h.  The subgraphs of one level run
+ * concurrently on `workers` threads (<= 0: 8), each with a stream of its
+ * own; the result does not depend on the count.  part_out: device int32[n].
+ * calls_out: host, may be NULL, number of partitioning calls.  Returns PM_OK
+ * or PM_WARN_IMBALANCED if any partitioning call ended above its L_max. */
+int pm_map_hm(const pm_graph *g, const pm_hierarchy *h, double eps,
+              uint64_t seed, int32_t workers, int32_t *part_out,
+              int64_t *j_out, int32_t *calls_out, void *stream);
+
 /* ---------------------------------------------------------------------------
  * Many instances.  A job is one independent mapping instance: a device graph,
  * its own hierarchy, eps and seed, and a device output array.  Every job is

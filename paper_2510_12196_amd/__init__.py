@@ -101,6 +101,8 @@ _SIGS = {
                                        _P]),
     "pm_refine_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P]),
     "pm_map_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P, _P]),
+    "pm_subgraphs": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "pm_map_hm": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P]),
     "pm_map_batch": (ctypes.c_int, [_P, _I32, _I32, _P]),
     "pm_job_footprint": (_I64, [_P, _P]),
     "pm_server_create": (_P, [_I64, _I32]),
@@ -363,6 +365,47 @@ def pm_map(g: DeviceGraph, a, d, eps: float, seed: int, part=None, validate: boo
                              _stream())
     _check(rc, "pm_map")
     return rc, part, st
+
+
+def pm_subgraphs(g: DeviceGraph, part, parts: int):
+    """Induced subgraphs of every block of `part` (device tensors).  Returns a
+    dict with vstart, estart, order, xadj, adjncy, adjwgt, vwgt (the layout
+    the C-ABI documents; arcs trimmed to the ones kept)."""
+    torch = _torch()
+    dev = g.vwgt.device
+    n, nnz, parts = g.n, g.nnz, int(parts)
+    vstart = torch.empty(parts + 1, dtype=torch.int32, device=dev)
+    estart = torch.empty(parts + 1, dtype=torch.int64, device=dev)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    xadj = torch.empty(n + parts, dtype=torch.int64, device=dev)
+    adj = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    wgt = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+    vw = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    arcs = ctypes.c_int64(0)
+    gs = g.struct()
+    _check(lib().pm_subgraphs(ctypes.byref(gs), _dev(part, "int32", n), parts,
+                              _dev(vstart, "int32"), _dev(estart, "int64"), _dev(order, "int32"),
+                              _dev(xadj, "int64"), _dev(adj, "int32"), _dev(wgt, "int32"),
+                              _dev(vw, "int32"), ctypes.byref(arcs), _stream()), "pm_subgraphs")
+    m = int(arcs.value)
+    return {"vstart": vstart, "estart": estart, "order": order[:n], "xadj": xadj,
+            "adjncy": adj[:m], "adjwgt": wgt[:m], "vwgt": vw[:n]}
+
+
+def pm_map_hm(g: DeviceGraph, a, d, eps: float, seed: int, workers: int = 8, part=None):
+    """Hierarchical multisection with the multilevel mapper as partitioner.
+    Returns (status, part, J under (a, d), number of partitioning calls)."""
+    torch = _torch()
+    if part is None:
+        part = torch.empty(max(g.n, 1), dtype=torch.int32, device=g.vwgt.device)
+    j = ctypes.c_int64(0)
+    calls = ctypes.c_int32(0)
+    gs, hs = g.struct(), hierarchy(a, d)
+    rc = lib().pm_map_hm(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
+                         int(workers), ctypes.c_void_p(part.data_ptr()), ctypes.byref(j),
+                         ctypes.byref(calls), _stream())
+    _check(rc, "pm_map_hm")
+    return rc, part[: g.n], int(j.value), int(calls.value)
 
 
 def make_job(g: DeviceGraph, a, d, eps: float, seed: int, part=None):

@@ -148,9 +148,6 @@ struct Ctx {
 
 }  // namespace
 
-// Structure and overflow validation kernels live in validate.hip.
-void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, hipStream_t s);
-
 // ---------------------------------------------------------------------------
 // Refinement (Algorithm 6)
 // ---------------------------------------------------------------------------
@@ -682,6 +679,63 @@ int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h, int32_t *part
     codes_to_ids(hh, part_out, part_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;
+  });
+}
+
+int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts, int32_t *vstart,
+                 int64_t *estart, int32_t *order, int64_t *xadj_out, int32_t *adjncy_out,
+                 int32_t *adjwgt_out, int32_t *vwgt_out, int64_t *arcs_out, void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    if (parts < 1 || parts == INT32_MAX) throw Error(PM_EINVAL, "parts out of range");
+    if (!vstart || !estart || !xadj_out) throw Error(PM_EINVAL, "NULL output");
+    if (dg.n > 0 && (!part || !order || !vwgt_out)) throw Error(PM_EINVAL, "NULL array");
+    if (dg.nnz > 0 && (!adjncy_out || !adjwgt_out)) throw Error(PM_EINVAL, "NULL array");
+    ArenaLease lease;
+    hipStream_t s = as_stream(stream);
+    Ctx cx(*lease, s);
+    check_parts(part, dg.n, parts, &cx.dev->count, s);
+    cx.pull();
+    if (cx.host->count) throw Error(PM_EINVAL, "partition holds ids outside [0,parts)");
+    SubgraphOut o{vstart, estart, order, xadj_out, adjncy_out, adjwgt_out, vwgt_out, nullptr};
+    subgraphs(*lease, dg, part, parts, o, s);
+    int64_t arcs = 0;
+    PM_HIP(hipMemcpyAsync(&arcs, estart + parts, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (arcs_out) *arcs_out = arcs;
+    return PM_OK;
+  });
+}
+
+int pm_map_hm(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+              int32_t workers, int32_t *part_out, int64_t *j_out, int32_t *calls_out,
+              void *stream) {
+  return guarded([&] {
+    check_device();
+    const DGraph dg = view(g);
+    const Hier hh = make_hier(h);
+    hipStream_t s = as_stream(stream);
+    PM_HIP(hipStreamSynchronize(s));
+    const int rc = hm_impl(dg, h->a, h->levels, eps, seed, part_out, workers, calls_out, s);
+    if (j_out) {
+      *j_out = 0;
+      if (dg.n > 0) {
+        ArenaLease lease;
+        Ctx cx(*lease, s);
+        int32_t *codes = part_out;
+        if (!hh.pow2) {
+          codes = lease->alloc_n<int32_t>(dg.n);
+          ids_to_codes(hh, part_out, codes, dg.n, s);
+        }
+        int32_t *list = lease->alloc_n<int32_t>(dg.n);
+        Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
+        comm_cost(dg, cl, hh, codes, cx.sp.a, cx.dev, s);
+        cx.pull();
+        *j_out = cx.host->j;
+      }
+    }
+    return rc;
   });
 }
 

@@ -177,6 +177,45 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
                      const Variants &var = Variants{});
 
+// ---- induced subgraphs (Section 3.1, Algorithm 1) ----------------------------
+// Layout of all blocks' subgraphs, concatenated in block order (device
+// arrays): vstart[parts+1] first position of each block, estart[parts+1]
+// first arc, order[n] original id per position, xadj[n+parts] block b's
+// relative row offsets at [vstart[b]+b, vstart[b+1]+b], adjncy/adjwgt
+// (local ids, original row order), vwgt[n] by position, wsum[parts] block
+// weights (may be nullptr).
+struct SubgraphOut {
+  int32_t *vstart;
+  int64_t *estart;
+  int32_t *order;
+  int64_t *xadj;
+  int32_t *adjncy;
+  int32_t *adjwgt;
+  int32_t *vwgt;
+  int64_t *wsum;
+};
+// part: device int32[n] in [0, parts) (checked by the caller).
+void subgraphs(Arena &ar, const DGraph &g, const int32_t *part, int32_t parts,
+               const SubgraphOut &o, hipStream_t s);
+// flags into *bad (device int32, cleared here) whether any part[v] is
+// outside [0, parts)
+void check_parts(const int32_t *part, int32_t n, int32_t parts, int32_t *bad, hipStream_t s);
+void compose_ids(int32_t n, const int32_t *orig, const int32_t *order, int32_t *out,
+                 hipStream_t s);
+void scatter_blocks(int32_t n, const int32_t *orig, const int32_t *part, int32_t base,
+                    int32_t *part_out, hipStream_t s);
+
+// Hierarchical multisection (Section 3.1, Algorithm 2) with the multilevel
+// mapper as partitioner; part_out: device ids in [0, k).  Returns PM_OK or
+// PM_WARN_IMBALANCED (some partitioning call ended above its L_max).
+int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint64_t seed,
+            int32_t *part_out, int32_t workers, int32_t *calls_out, hipStream_t s);
+// equation (2) in parts per million, rounded, never negative
+int64_t adaptive_eps_ppm(int64_t eps_ppm, int64_t kp, int64_t k, int64_t cv, int64_t cvp,
+                         int32_t d);
+// Structure and overflow validation (validate.hip); *total_vwgt = c(V).
+void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, hipStream_t s);
+
 // ---- matching and contraction ---------------------------------------------
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, hipStream_t s);
