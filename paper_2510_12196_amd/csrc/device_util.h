@@ -119,6 +119,37 @@ __device__ __forceinline__ void block_scan_lds(uint32_t *a, int m, BlockScratch 
   __syncthreads();
 }
 
+// ---- one wave working alone on its own LDS slice ------------------------------
+// The LDS instructions of one wave are performed in issue order, so a wave
+// needs no barrier between its own LDS phases; this keeps the compiler from
+// moving LDS accesses across the phase boundary.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+// Inclusive prefix sum over a[0..m) in LDS by the 64 lanes of one wave: a
+// contiguous run of ceil(m/64) entries per lane, then a scan of the run
+// totals by shuffles.
+__device__ __forceinline__ void wave_scan_lds(uint32_t *a, int m) {
+  const int lane = threadIdx.x & 63;
+  const int per = (m + 63) / 64;
+  const int lo = lane * per;
+  const int hi = lo + per < m ? lo + per : m;
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) {
+    s += a[i];
+    a[i] = s;
+  }
+  uint32_t incl = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int32_t)incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  const uint32_t off = incl - s;
+  for (int i = lo; i < hi; ++i) a[i] += off;
+}
+
 // ---- striped accumulators ---------------------------------------------------
 // A global sum updated by thousands of workgroups is spread over kStripes
 // counters one cache line apart (atomics on a single address serialise);

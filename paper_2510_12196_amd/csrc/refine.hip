@@ -456,6 +456,7 @@ struct LP1Args {
   int64_t *gain;
   int64_t jet_num;  // > 0: relaxed filter -G < floor(jet_num * conn(v,own) / jet_den)
   int64_t jet_den;
+  int32_t whist;    // G64 vertices use a per-wave LDS histogram (LDS: 4 slices)
 };
 
 // First filter: G >= 0, or with Jet's relaxed filter -G < floor(c conn_own).
@@ -595,6 +596,57 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X
   }
 }
 
+// Degree 33..64, one vertex per wave: instead of pairing every arc with
+// every other one (deg^2 shuffles), the wave adds its arcs into a
+// connectivity histogram in its own LDS slice, scans it, and reads the cost
+// of each candidate from the level group sums (level_cost).
+template <int V>
+__device__ __forceinline__ void lp1_wave(const LP1Args &A, int local, uint32_t *X) {
+  const int32_t ncodes = 1 << A.h.bits;
+  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
+  group_tiles<64, V>(
+      A.g.xadj, A.g.adj, A.cl, CLS_G64, local,
+      [&](int32_t v, bool &act) {
+        act = !A.lock[v];
+        return Lp1V{(uint32_t)A.part[v]};
+      },
+      [&](int32_t u, int64_t e) { return Lp1N{(uint32_t)A.part[u], A.g.w[e]}; },
+      [&](int, bool ok, int32_t v, const Lp1V &vv, bool act, int, bool valid, const Lp1N &nv) {
+        if (!ok) return;
+        const int lane = threadIdx.x & 63;
+        const uint32_t p = vv.p;
+        const uint32_t bu = valid ? nv.bu : p;
+        const bool cand = valid && bu != p;
+        if (!act || !gor<64>(cand ? 1 : 0)) {
+          if (lane == 0) {
+            A.target[v] = (int32_t)p;
+            A.gain[v] = kNotInX;
+          }
+          return;
+        }
+        for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
+        wave_lds_sync();
+        if (valid) atomicAdd(&Xw[bu + 1], (uint32_t)nv.wu);
+        wave_lds_sync();
+        wave_scan_lds(Xw, ncodes + 1);
+        wave_lds_sync();
+        const int64_t costp = level_cost(A.h, Xw, p, ncodes);
+        int64_t g = cand ? costp - level_cost(A.h, Xw, bu, ncodes) : INT64_MIN;
+        uint32_t b = cand ? bu : 0xFFFFFFFFu;
+        gargmax<64>(g, b);
+        if (lane == 0) {
+          if (lp1_pass(A, g, (int64_t)(Xw[p + 1] - Xw[p]))) {
+            A.target[v] = (int32_t)b;
+            A.gain[v] = g;
+          } else {
+            A.target[v] = (int32_t)p;
+            A.gain[v] = kNotInX;
+          }
+        }
+        wave_lds_sync();  // the slice is cleared again for the next vertex
+      });
+}
+
 template <int V>
 __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   extern __shared__ uint32_t X[];
@@ -613,7 +665,10 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
       case CLS_G8: lp1_group<8, V>(A, cls, local); break;
       case CLS_G16: lp1_group<16, V>(A, cls, local); break;
       case CLS_G32: lp1_group<32, V>(A, cls, local); break;
-      case CLS_G64: lp1_group<64, V>(A, cls, local); break;
+      case CLS_G64:
+        if (A.whist) lp1_wave<V>(A, local, X);
+        else lp1_group<64, V>(A, cls, local);
+        break;
       default: lp1_big(A, local, X, sc); break;
     }
   }
@@ -628,15 +683,19 @@ void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1};
+  // four per-wave histogram slices fit in 32 KiB up to 2^10 codes
+  const int whist = h.bits <= 10;
+  LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1,
+            whist};
+  const size_t lds = whist ? 4 * big_lds(h) : big_lds(h);
   auto kern = V == 2 ? k_lp_phase1<2> : k_lp_phase1<1>;
   if (tl_timer) {
     hipEvent_t a, b;
     tl_timer->pair(KT_LP1, a, b);
     tl_timer->bytes[KT_LP1] += 12.0 * (double)g.nnz + 25.0 * (double)g.n;
-    hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, a, b, 0, A);
+    hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
   } else {
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, A);
   }
   PM_LAUNCH_CHECK();
 }
@@ -780,12 +839,18 @@ struct ApplyArgs {
   int64_t *dj;
 };
 
-// block weight deltas go to the workgroup's LDS copy first
-__device__ __forceinline__ void apply_weights(const ApplyArgs &A, int32_t v, uint32_t p,
-                                              uint32_t t, int32_t *dw) {
-  const int32_t c = A.g.c[v];
-  atomicAdd(&dw[t], c);
-  atomicAdd(&dw[p], -c);
+// Block-weight deltas of one mover (+c to its target, -c to its block): added
+// into the weight-delta stripe of the workgroup, one atomic per distinct
+// block per wave.
+struct WMove {
+  bool has = false;
+  uint32_t p = 0, t = 0;
+  int32_t c = 0;
+};
+__device__ __forceinline__ void wmove_flush(const ApplyArgs &A, const WMove &m) {
+  int64_t *w = A.wst + (size_t)(blockIdx.x & (A.nstripes - 1)) * ((size_t)1 << A.h.bits);
+  wave_keyed_add(m.has, m.t, (int64_t)m.c, [=](uint32_t k) { return &w[k]; });
+  wave_keyed_add(m.has, m.p, -(int64_t)m.c, [=](uint32_t k) { return &w[k]; });
 }
 
 struct ApV {
@@ -793,9 +858,9 @@ struct ApV {
 };
 
 template <int G, int V>
-__device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local,
-                                               int32_t *dw) {
+__device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local) {
   int64_t x = 0;
+  WMove mv[V];
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
       [&](int32_t v, bool &act) {
@@ -805,73 +870,93 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
       [&](int32_t u, int64_t e) {
         return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
       },
-      [&](int, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, int4 a) {
+      [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, int4 a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
         if (A.lock && lane == 0) A.lock[v] = act ? 1 : 0;
         if (!act) return;
-        if (lane == 0) apply_weights(A, v, vv.p, vv.t, dw);
+        if (lane == 0) {
+          mv[r].has = true;
+          mv[r].p = vv.p;
+          mv[r].t = vv.t;
+          mv[r].c = A.g.c[v];
+        }
         if (!valid) return;
         const uint32_t old_u = (uint32_t)a.y;
         if (a.w) x += (int64_t)a.x * (dist(A.h, vv.t, (uint32_t)a.z) - dist(A.h, vv.p, old_u));
         else x += 2 * (int64_t)a.x * (dist(A.h, vv.t, old_u) - dist(A.h, vv.p, old_u));
       });
+#pragma unroll
+  for (int r = 0; r < V; ++r) wmove_flush(A, mv[r]);
   return x;
 }
 
+// One class tile per workgroup; no LDS and no workgroup barrier, so that a
+// tile without movers costs only its loads of moved[] and stores of lock[].
 template <int V>
 __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
-  extern __shared__ int32_t dw[];
-  __shared__ BlockScratch sc;
-  const int32_t ncodes = 1 << A.h.bits;
-  for (int c = threadIdx.x; c < ncodes; c += kThreads) dw[c] = 0;
-  __syncthreads();
-  const int total = A.cl.wg[NCLS];
   int64_t x = 0;
-  for (int blk = blockIdx.x; blk < total; blk += gridDim.x) {
-    const int cls = find_class(A.cl, blk);
-    const int local = blk - A.cl.wg[cls];
-    switch (cls) {
-      case CLS_ISO:
-        iso_tiles<V>(A.cl, local, [&](int32_t v) {
+  const int blk = blockIdx.x;
+  const int cls = find_class(A.cl, blk);
+  const int local = blk - A.cl.wg[cls];
+  switch (cls) {
+    case CLS_ISO: {
+      const int cnt = A.cl.off[CLS_ISO + 1] - A.cl.off[CLS_ISO];
+      WMove mv[V];
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int idx = (local * V + r) * kThreads + threadIdx.x;
+        if (idx < cnt) {
+          const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
           const uint8_t m = A.moved[v];
           if (A.lock) A.lock[v] = m;
-          if (m) apply_weights(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v], dw);
-        });
-        break;
-      case CLS_G8: x += apply_group<8, V>(A, cls, local, dw); break;
-      case CLS_G16: x += apply_group<16, V>(A, cls, local, dw); break;
-      case CLS_G32: x += apply_group<32, V>(A, cls, local, dw); break;
-      case CLS_G64: x += apply_group<64, V>(A, cls, local, dw); break;
-      default: {
-        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-        const uint8_t m = A.moved[v];
-        if (A.lock && threadIdx.x == 0) A.lock[v] = m;
-        if (m) {
-          const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-          if (threadIdx.x == 0) apply_weights(A, v, p, t, dw);
-          big_arcs(
-              A.g.xadj[v], A.g.xadj[v + 1],
-              [&](int64_t e) {
-                const int32_t u = A.g.adj[e];
-                return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
-              },
-              [&](int64_t, int4 a) {
-                const uint32_t old_u = (uint32_t)a.y;
-                if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
-                else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
-              });
+          if (m) {
+            mv[r].has = true;
+            mv[r].p = (uint32_t)A.part[v];
+            mv[r].t = (uint32_t)A.target[v];
+            mv[r].c = A.g.c[v];
+          }
         }
-        break;
       }
+#pragma unroll
+      for (int r = 0; r < V; ++r) wmove_flush(A, mv[r]);
+      break;
+    }
+    case CLS_G8: x += apply_group<8, V>(A, cls, local); break;
+    case CLS_G16: x += apply_group<16, V>(A, cls, local); break;
+    case CLS_G32: x += apply_group<32, V>(A, cls, local); break;
+    case CLS_G64: x += apply_group<64, V>(A, cls, local); break;
+    default: {
+      const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const uint8_t m = A.moved[v];
+      if (A.lock && threadIdx.x == 0) A.lock[v] = m;
+      if (m) {
+        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+        WMove mv;
+        if (threadIdx.x == 0) {
+          mv.has = true;
+          mv.p = p;
+          mv.t = t;
+          mv.c = A.g.c[v];
+        }
+        wmove_flush(A, mv);
+        big_arcs(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) {
+              const int32_t u = A.g.adj[e];
+              return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+            },
+            [&](int64_t, int4 a) {
+              const uint32_t old_u = (uint32_t)a.y;
+              if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
+              else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+            });
+      }
+      break;
     }
   }
-  x = block_sum64(x, sc);  // also orders the LDS weight deltas before the flush
-  if (threadIdx.x == 0) stripe_add(A.dj, x);
-  // every workgroup touches the same few blocks: spread the flush over stripes
-  int64_t *wst = A.wst + (size_t)(blockIdx.x & (A.nstripes - 1)) * ncodes;
-  for (int c = threadIdx.x; c < ncodes; c += kThreads)
-    if (dw[c]) atomicAdd((unsigned long long *)&wst[c], (unsigned long long)(int64_t)dw[c]);
+  x = gsum64<64>(x);
+  if ((threadIdx.x & 63) == 0) stripe_add(A.dj, x);
 }
 
 // part <- target for the moved vertices.  Workgroup 0 also folds the
@@ -906,21 +991,19 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
                  int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s) {
-  // capped: every workgroup flushes its LDS block-weight deltas once
   const int V = group_v();
   const Classes tc = tiled(cl, V);
-  const unsigned nwg = capped_grid(tc);
+  const unsigned nwg = classed_grid(tc);
   const int nstripes = weight_stripes(h);
   ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
-  const size_t lds = sizeof(int32_t) * ((size_t)1 << h.bits);
   if (nwg > 0) {
     if (tl_timer) {
       hipEvent_t a, b;
       tl_timer->pair(KT_APPLY, a, b);
-      hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
+      hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
     } else {
-      hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, A);
+      hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
     }
     PM_LAUNCH_CHECK();
   }
