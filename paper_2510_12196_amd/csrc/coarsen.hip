@@ -132,6 +132,33 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
       case CLS_G16: hem_group<16, V>(A, cls, local); break;
       case CLS_G32: hem_group<32, V>(A, cls, local); break;
       case CLS_G64: hem_group<64, V>(A, cls, local); break;
+      case CLS_W: {
+        int32_t v;
+        if (!w_vertex(A.cl, local, v)) break;
+        bool act;
+        const HemV hv = hem_vertex(A, v, act);
+        if (!act) {
+          if ((threadIdx.x & 63) == 0 && hv.matched) A.pref[v] = -1;
+          break;
+        }
+        const int32_t cv = hv.cv;
+        Cand best{-1, 0, 1, 0};
+        wave_arcs<4>(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) {
+              const int32_t u = A.g.adj[e];
+              return make_int4(u, A.match[u], A.g.c[u], A.g.w[e]);
+            },
+            [&](int64_t, int4 a) {
+              if (a.y >= 0 || (int64_t)a.z + cv > A.lmax) return;
+              const uint32_t lo = (uint32_t)(a.x < v ? a.x : v), hi = (uint32_t)(a.x < v ? v : a.x);
+              const Cand c{a.x, a.w, a.z, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+              if (cand_better(c, best, v)) best = c;
+            });
+        cand_reduce<64>(best, v);
+        if ((threadIdx.x & 63) == 0) A.pref[v] = best.u;
+        break;
+      }
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         bool act;
@@ -339,6 +366,22 @@ __global__ __launch_bounds__(kThreads) void k_contract_keys(KeyArgs A) {
       case CLS_G16: self += key_group<16>(A, cls, local); break;
       case CLS_G32: self += key_group<32>(A, cls, local); break;
       case CLS_G64: self += key_group<64>(A, cls, local); break;
+      case CLS_W: {
+        int32_t v;
+        if (!w_vertex(A.cl, local, v)) break;
+        const uint64_t cv = (uint64_t)A.cmap[v];
+        const uint64_t sentinel = (A.bits >= 32) ? ~0ull : ((1ull << (2 * A.bits)) - 1ull);
+        wave_arcs<4>(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) { return make_int2(A.cmap[A.g.adj[e]], A.g.w[e]); },
+            [&](int64_t e, int2 a) {
+              const uint64_t cu = (uint64_t)a.x;
+              A.val[e] = a.y;
+              A.key[e] = cu == cv ? sentinel : ((cv << A.bits) | cu);
+              self += cu == cv ? 1 : 0;
+            });
+        break;
+      }
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint64_t cv = (uint64_t)A.cmap[v];

@@ -222,8 +222,36 @@ __device__ __forceinline__ bool group_vertex(const Classes &cl, int cls, int loc
   return true;
 }
 
-// Sum over the arcs of one vertex weighted by the lane group convention:
-// inside a G-group lane j owns arc xadj[v]+j (deg <= G by construction).
+// W tiles: one vertex per wave, kThreads / 64 vertices per tile.
+__device__ __forceinline__ bool w_vertex(const Classes &cl, int local, int32_t &v) {
+  const int idx = local * (kThreads / 64) + (int)(threadIdx.x >> 6);
+  if (idx >= cl.off[CLS_W + 1] - cl.off[CLS_W]) return false;
+  v = cl.list[cl.off[CLS_W] + idx];
+  return true;
+}
+
+// The arcs [beg, end) of one vertex over the 64 lanes of a wave: lane l takes
+// beg + l, beg + l + 64, ...; B arcs per lane are loaded before any is used
+// (indices past the row are clamped to its last arc, so that no load sits
+// behind a branch, and their uses skipped).  Every lane gets the same number
+// of rounds.
+template <int B, class L, class U>
+__device__ __forceinline__ void wave_arcs(int64_t beg, int64_t end, L load, U use) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t e0 = beg; e0 < end; e0 += 64 * B) {
+    decltype(load(e0)) a[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int64_t e = e0 + lane + 64 * i;
+      a[i] = load(e < end ? e : end - 1);
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const int64_t e = e0 + lane + 64 * i;
+      if (e < end) use(e, a[i]);
+    }
+  }
+}
 
 // ISO tiles: V vertices per thread.
 template <int V, class F>

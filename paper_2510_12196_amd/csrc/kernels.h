@@ -101,7 +101,9 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
 int32_t classes_workgroups(const Classes &cl);
 // The same classes laid out as tiles of V vertices per lane group (ISO: V
 // per thread); BIG keeps one vertex per workgroup.
-Classes tiled(const Classes &cl, int V);
+// w_as_big: W vertices one per tile (the block path), for kernels without
+// the per-wave histogram
+Classes tiled(const Classes &cl, int V, bool w_as_big = false);
 // Vertices per lane group of the staged kernels: 1 (PM_GROUP_V=2 selects
 // 2).
 int group_v();

@@ -120,13 +120,17 @@ struct DGraph {
 };
 
 // Degree classes: vertices are processed by groups of G lanes (one arc per
-// lane) when deg <= G, by a whole workgroup with an LDS histogram otherwise.
-// The enumeration order is the launch order of the class tiles: the longest
-// tiles (high degree) start first, so that they overlap with the rest.
-enum { CLS_BIG = 0, CLS_G64, CLS_G32, CLS_G16, CLS_G8, CLS_ISO, NCLS };
+// lane) when deg <= G (G = 8, 16, 32, 64), by one wave with up to
+// kWaveMaxDeg / 64 arcs per lane when deg <= kWaveMaxDeg (W), by a whole
+// workgroup otherwise (BIG).  The enumeration order is the launch order of
+// the class tiles: the longest tiles (high degree) start first, so that they
+// overlap with the rest.
+enum { CLS_BIG = 0, CLS_W, CLS_G64, CLS_G32, CLS_G16, CLS_G8, CLS_ISO, NCLS };
+constexpr int kWaveMaxDeg = 512;
+constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 __host__ __device__ constexpr int class_group(int cls) {
   return cls == CLS_G8 ? 8 : cls == CLS_G16 ? 16 : cls == CLS_G32 ? 32
-       : cls == CLS_G64 ? 64 : 1;
+       : (cls == CLS_G64 || cls == CLS_W) ? 64 : 1;
 }
 // vertices handled by one workgroup in each class
 __host__ __device__ constexpr int class_per_wg(int cls) {

@@ -62,7 +62,7 @@ void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64
 // ===========================================================================
 // degree classes
 // ===========================================================================
-__global__ void k_classify(DGraph g, uint8_t *cls, int32_t *counts) {
+__global__ void k_classify(DGraph g, int32_t wmax, uint8_t *cls, int32_t *counts) {
   __shared__ int32_t c[NCLS];
   if (threadIdx.x < NCLS) c[threadIdx.x] = 0;
   __syncthreads();
@@ -70,7 +70,7 @@ __global__ void k_classify(DGraph g, uint8_t *cls, int32_t *counts) {
   if (v < g.n) {
     int64_t d = g.xadj[v + 1] - g.xadj[v];
     int k = d == 0 ? CLS_ISO : d <= 8 ? CLS_G8 : d <= 16 ? CLS_G16 : d <= 32 ? CLS_G32
-          : d <= 64 ? CLS_G64 : CLS_BIG;
+          : d <= 64 ? CLS_G64 : d <= wmax ? CLS_W : CLS_BIG;
     cls[v] = (uint8_t)k;
     atomicAdd(&c[k], 1);
   }
@@ -87,14 +87,25 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
   size_t m = ar.mark();
   uint8_t *cls = ar.alloc_n<uint8_t>((size_t)g.n + 1);
   int32_t *counts = ar.alloc_n<int32_t>(2 * NCLS);
-  PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2 * NCLS, s));
-  if (g.n > 0) {
-    hipLaunchKernelGGL(k_classify, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, cls, counts);
-    PM_LAUNCH_CHECK();
-  }
   int32_t *host = static_cast<int32_t *>(ar.host_stage(sizeof(int32_t) * 2 * NCLS));
-  PM_HIP(hipMemcpyAsync(host, counts, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
-  PM_HIP(hipStreamSynchronize(s));
+  // W tiles (a wave per vertex) pay off once they fill the chip; with fewer
+  // such vertices a workgroup per vertex finishes sooner, so degrees above 64
+  // then all go to BIG (the two paths compute the same results).
+  // PM_WAVE_MIN_COUNT overrides the threshold (tests use it to reach the W
+  // paths on small graphs).
+  int64_t wmin = kWaveMinCount;
+  if (const char *e = std::getenv("PM_WAVE_MIN_COUNT")) wmin = std::atoll(e);
+  for (int32_t wmax : {kWaveMaxDeg, 64}) {
+    PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2 * NCLS, s));
+    if (g.n > 0) {
+      hipLaunchKernelGGL(k_classify, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, wmax, cls,
+                         counts);
+      PM_LAUNCH_CHECK();
+    }
+    PM_HIP(hipMemcpyAsync(host, counts, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (host[CLS_W] == 0 || host[CLS_W] >= wmin) break;
+  }
   int32_t cnt[NCLS];
   for (int c = 0; c < NCLS; ++c) cnt[c] = host[c];
   cl.off[0] = 0;
@@ -112,12 +123,12 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
 
 int32_t classes_workgroups(const Classes &cl) { return cl.wg[NCLS]; }
 
-Classes tiled(const Classes &cl, int V) {
+Classes tiled(const Classes &cl, int V, bool w_as_big) {
   Classes t = cl;
   t.wg[0] = 0;
   for (int c = 0; c < NCLS; ++c) {
     const int cnt = cl.off[c + 1] - cl.off[c];
-    const int per = class_per_wg(c) * (c == CLS_BIG ? 1 : V);
+    const int per = c == CLS_W && w_as_big ? 1 : class_per_wg(c) * (c == CLS_BIG || c == CLS_W ? 1 : V);
     t.wg[c + 1] = t.wg[c] + (cnt + per - 1) / per;
   }
   return t;
@@ -257,6 +268,16 @@ __global__ __launch_bounds__(kThreads) void k_comm_cost(CostArgs A) {
       case CLS_G16: x += cost_group<16>(A, cls, local); break;
       case CLS_G32: x += cost_group<32>(A, cls, local); break;
       case CLS_G64: x += cost_group<64>(A, cls, local); break;
+      case CLS_W: {
+        int32_t v;
+        if (!w_vertex(A.cl, local, v)) break;
+        const uint32_t p = (uint32_t)A.part[v];
+        wave_arcs<4>(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
+            [&](int64_t, uint2 a) { x += (int64_t)a.y * dist(A.h, p, a.x); });
+        break;
+      }
       case CLS_BIG: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const uint32_t p = (uint32_t)A.part[v];
@@ -551,9 +572,8 @@ __device__ __forceinline__ void big_histogram(const DGraph &g, const int32_t *pa
   block_scan_lds(X, ncodes + 1, sc);
 }
 
-__device__ __forceinline__ void lp1_big(const LP1Args &A, int local, uint32_t *X,
+__device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X,
                                         BlockScratch &sc) {
-  const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
   const uint32_t p = (uint32_t)A.part[v];
   if (A.lock[v]) {
     if (threadIdx.x == 0) {
@@ -647,6 +667,62 @@ __device__ __forceinline__ void lp1_wave(const LP1Args &A, int local, uint32_t *
       });
 }
 
+// Degree 65..kWaveMaxDeg, one vertex per wave: the block path's histogram
+// in the wave's own LDS slice, without workgroup barriers.
+__device__ __forceinline__ void lp1_w(const LP1Args &A, int local, uint32_t *X) {
+  int32_t v;
+  if (!w_vertex(A.cl, local, v)) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t p = (uint32_t)A.part[v];
+  if (A.lock[v]) {
+    if (lane == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int32_t ncodes = 1 << A.h.bits;
+  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
+  for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
+  wave_lds_sync();
+  wave_arcs<4>(
+      A.g.xadj[v], A.g.xadj[v + 1],
+      [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
+      [&](int64_t, uint2 a) { atomicAdd(&Xw[a.x + 1], a.y); });
+  wave_lds_sync();
+  wave_scan_lds(Xw, ncodes + 1);
+  wave_lds_sync();
+  const uint32_t connp = Xw[p + 1] - Xw[p];
+  if (Xw[ncodes] == connp) {
+    if (lane == 0) {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+    return;
+  }
+  const int64_t costp = level_cost(A.h, Xw, p, ncodes);
+  int64_t g = INT64_MIN;
+  uint32_t b = 0xFFFFFFFFu;
+  for (int c = lane; c < ncodes; c += 64) {
+    if ((uint32_t)c == p || Xw[c + 1] == Xw[c]) continue;
+    const int64_t gc = costp - level_cost(A.h, Xw, (uint32_t)c, ncodes);
+    if (gc > g || (gc == g && (uint32_t)c < b)) {
+      g = gc;
+      b = (uint32_t)c;
+    }
+  }
+  gargmax<64>(g, b);
+  if (lane == 0) {
+    if (lp1_pass(A, g, (int64_t)connp)) {
+      A.target[v] = (int32_t)b;
+      A.gain[v] = g;
+    } else {
+      A.target[v] = (int32_t)p;
+      A.gain[v] = kNotInX;
+    }
+  }
+}
+
 template <int V>
 __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   extern __shared__ uint32_t X[];
@@ -669,7 +745,12 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
         if (A.whist) lp1_wave<V>(A, local, X);
         else lp1_group<64, V>(A, cls, local);
         break;
-      default: lp1_big(A, local, X, sc); break;
+      default:
+        // BIG, and W without the per-wave histogram (then tiled one vertex
+        // per workgroup, like BIG)
+        if (cls == CLS_W && A.whist) lp1_w(A, local, X);
+        else lp1_big(A, A.cl.list[A.cl.off[cls] + local], X, sc);
+        break;
     }
   }
 }
@@ -680,11 +761,11 @@ void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
                const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
                const Variants &var) {
   const int V = group_v();
-  const Classes tc = tiled(cl, V);
-  const unsigned nwg = classed_grid(tc);
-  if (nwg == 0) return;
   // four per-wave histogram slices fit in 32 KiB up to 2^10 codes
   const int whist = h.bits <= 10;
+  const Classes tc = tiled(cl, V, !whist);
+  const unsigned nwg = classed_grid(tc);
+  if (nwg == 0) return;
   LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1,
             whist};
   const size_t lds = whist ? 4 * big_lds(h) : big_lds(h);
@@ -770,6 +851,31 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
       case CLS_G16: lp2_group<16, V>(A, cls, local); break;
       case CLS_G32: lp2_group<32, V>(A, cls, local); break;
       case CLS_G64: lp2_group<64, V>(A, cls, local); break;
+      case CLS_W: {
+        int32_t v;
+        if (!w_vertex(A.cl, local, v)) break;
+        const int64_t gv = A.gain[v];
+        if (gv == kNotInX) {
+          if ((threadIdx.x & 63) == 0) A.moved[v] = 0;
+          break;
+        }
+        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+        int64_t x = 0;
+        wave_arcs<2>(
+            A.g.xadj[v], A.g.xadj[v + 1],
+            [&](int64_t e) {
+              const int32_t u = A.g.adj[e];
+              return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]};
+            },
+            [&](int64_t, const Lp2Arc &a) {
+              uint32_t pu = (uint32_t)a.pu;
+              if (a.gu != kNotInX && (a.gu > gv || (a.gu == gv && a.u < v))) pu = (uint32_t)a.tu;
+              x += (int64_t)a.w * (dist(A.h, p, pu) - dist(A.h, t, pu));
+            });
+        x = gsum64<64>(x);
+        if ((threadIdx.x & 63) == 0) A.moved[v] = x >= 0 ? 1 : 0;
+        break;
+      }
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
         const int64_t gv = A.gain[v];
@@ -926,6 +1032,36 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
     case CLS_G16: x += apply_group<16, V>(A, cls, local); break;
     case CLS_G32: x += apply_group<32, V>(A, cls, local); break;
     case CLS_G64: x += apply_group<64, V>(A, cls, local); break;
+    case CLS_W: {
+      int32_t v;
+      WMove mv;
+      if (w_vertex(A.cl, local, v)) {
+        const uint8_t m = A.moved[v];
+        if (A.lock && (threadIdx.x & 63) == 0) A.lock[v] = m;
+        if (m) {
+          const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+          if ((threadIdx.x & 63) == 0) {
+            mv.has = true;
+            mv.p = p;
+            mv.t = t;
+            mv.c = A.g.c[v];
+          }
+          wave_arcs<4>(
+              A.g.xadj[v], A.g.xadj[v + 1],
+              [&](int64_t e) {
+                const int32_t u = A.g.adj[e];
+                return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+              },
+              [&](int64_t, int4 a) {
+                const uint32_t old_u = (uint32_t)a.y;
+                if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
+                else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+              });
+        }
+      }
+      wmove_flush(A, mv);
+      break;
+    }
     default: {
       const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
       const uint8_t m = A.moved[v];
@@ -1056,6 +1192,7 @@ struct RebArgs {
   int32_t *dest;
   int64_t *bw;   // bucket weight stripes [stripe][code][bucket]
   int32_t jrb;   // loss = J gain of eq. 1 (variant) instead of the edge-cut loss
+  int32_t whist; // W vertices use a per-wave LDS histogram (LDS: 4 slices)
 };
 
 __device__ __forceinline__ int32_t bucket_of(int64_t g) {
@@ -1190,9 +1327,8 @@ __device__ __forceinline__ void reb_group(const RebArgs &A, int cls, int local) 
   for (int r = 0; r < V; ++r) bw_flush(A, add[r]);
 }
 
-__device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X,
+__device__ __forceinline__ void reb_big(const RebArgs &A, int32_t v, uint32_t *X,
                                         BlockScratch &sc) {
-  const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
   const uint32_t p = (uint32_t)A.part[v];
   if (!is_source(A, v, p)) {
     if (threadIdx.x == 0) reb_not_source(A, v);
@@ -1231,6 +1367,56 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int local, uint32_t *X
   }
 }
 
+// Degree 65..kWaveMaxDeg, one vertex per wave, histogram in the wave's LDS
+// slice (the block path without workgroup barriers).
+__device__ __forceinline__ void reb_w(const RebArgs &A, int local, uint32_t *X) {
+  int32_t v;
+  if (!w_vertex(A.cl, local, v)) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t p = (uint32_t)A.part[v];
+  if (!is_source(A, v, p)) {
+    if (lane == 0) reb_not_source(A, v);
+    return;
+  }
+  const int32_t ncodes = 1 << A.h.bits;
+  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
+  for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
+  wave_lds_sync();
+  wave_arcs<4>(
+      A.g.xadj[v], A.g.xadj[v + 1],
+      [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
+      [&](int64_t, uint2 a) { atomicAdd(&Xw[a.x + 1], a.y); });
+  wave_lds_sync();
+  wave_scan_lds(Xw, ncodes + 1);
+  wave_lds_sync();
+  const int64_t costp = A.jrb ? level_cost(A.h, Xw, p, ncodes) : 0;
+  int64_t val = INT64_MIN;
+  uint32_t b = 0xFFFFFFFFu;
+  for (int c = lane; c < ncodes; c += 64) {
+    const uint32_t conn = Xw[c + 1] - Xw[c];
+    if ((uint32_t)c == p || conn == 0 || A.w[c] > A.cap) continue;
+    const int64_t x = A.jrb ? costp - level_cost(A.h, Xw, (uint32_t)c, ncodes) : (int64_t)conn;
+    if (x > val) {
+      val = x;
+      b = (uint32_t)c;
+    }
+  }
+  gargmax<64>(val, b);
+  BwAdd add;
+  if (lane == 0) {
+    if (!A.jrb) {
+      reb_decide(A, v, p, b, val, (int64_t)(Xw[p + 1] - Xw[p]), add);
+    } else if (b != 0xFFFFFFFFu) {
+      reb_finish(A, v, p, b, val, add);
+    } else if (reb_random(A, v, b)) {
+      reb_finish(A, v, p, b, costp - level_cost(A.h, Xw, b, ncodes), add);
+    } else {
+      reb_not_source(A, v);
+    }
+  }
+  bw_flush(A, add);
+}
+
 template <int V>
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
@@ -1259,7 +1445,10 @@ __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
     case CLS_G16: reb_group<16, V>(A, cls, local); break;
     case CLS_G32: reb_group<32, V>(A, cls, local); break;
     case CLS_G64: reb_group<64, V>(A, cls, local); break;
-    default: reb_big(A, local, X, sc); break;
+    default:  // as in k_lp_phase1
+      if (cls == CLS_W && A.whist) reb_w(A, local, X);
+      else reb_big(A, A.cl.list[A.cl.off[cls] + local], X, sc);
+      break;
   }
 }
 
@@ -1671,7 +1860,8 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
                      const Variants &var) {
   const int V = group_v();
-  const Classes tc = tiled(cl, V);
+  const bool whist = h.bits <= 10;  // as in lp_phase1
+  const Classes tc = tiled(cl, V, !whist);
   const unsigned nwg = classed_grid(tc);
   const int64_t n = g.n;
   if (n <= 0) return;
@@ -1693,9 +1883,11 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
               rb.key,
               rb.dest,
               rb.bw,
-              var.j_rebalance ? 1 : 0};
+              var.j_rebalance ? 1 : 0,
+              whist ? 1 : 0};
     auto kern = V == 2 ? k_reb_select<2> : k_reb_select<1>;
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), big_lds(h), s, A);
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), A.whist ? 4 * big_lds(h) : big_lds(h), s,
+                       A);
     PM_LAUNCH_CHECK();
   }
   KPArgs K{};

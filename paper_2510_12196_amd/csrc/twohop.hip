@@ -88,6 +88,35 @@ __global__ __launch_bounds__(kThreads) void k_twohop_keys(TwoHopArgs A) {
     case CLS_G16: th_group<16>(A, cls, local); break;
     case CLS_G32: th_group<32>(A, cls, local); break;
     case CLS_G64: th_group<64>(A, cls, local); break;
+    case CLS_W: {
+      int32_t v;
+      if (!w_vertex(A.cl, local, v)) break;
+      const int lane = threadIdx.x & 63;
+      if (A.match[v] >= 0 || A.mode == TWOHOP_LEAF) {  // degree > 64: never a leaf
+        if (lane == 0) A.flag[v] = 0;
+        break;
+      }
+      const int64_t beg = A.g.xadj[v], end = A.g.xadj[v + 1];
+      if (A.mode == TWOHOP_TWIN) {
+        int64_t h = 0;
+        for (int64_t e = beg + lane; e < end; e += 64)
+          h += (int64_t)mix_hash(A.tseed, (uint64_t)(uint32_t)A.g.adj[e]);
+        h = gsum64<64>(h);
+        if (lane == 0) th_write(A, v, true, mix_hash((uint64_t)h, (uint64_t)(end - beg)));
+      } else {
+        int64_t m = INT64_MAX;
+        for (int64_t e = beg + lane; e < end; e += 64) {
+          const int64_t c = (int64_t)mm_code(A.g, A.g.adj[e]);
+          m = c < m ? c : m;
+        }
+        for (int sh = 32; sh > 0; sh >>= 1) {
+          const int64_t o = gxor64<64>(m, sh);
+          m = o < m ? o : m;
+        }
+        if (lane == 0) th_write(A, v, true, (uint64_t)(uint32_t)(m & 0xffffffffll));
+      }
+      break;
+    }
     default: {
       const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
       if (A.match[v] >= 0 || A.mode == TWOHOP_LEAF) {  // degree > 64: never a leaf

@@ -1,0 +1,192 @@
+"""The one-wave-per-vertex paths (degree 65..512) against the oracle.
+
+The library sends such vertices to these paths only when there are enough of
+them to fill the chip; PM_WAVE_MIN_COUNT=1 forces them on the small graphs
+here.  Hierarchies with at most 2^10 block codes use the per-wave LDS
+histogram; (4, 16, 32) needs 2^11 codes and takes the workgroup fallback."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def force_wave_class():
+    old = os.environ.get("PM_WAVE_MIN_COUNT")
+    os.environ["PM_WAVE_MIN_COUNT"] = "1"
+    yield
+    if old is None:
+        del os.environ["PM_WAVE_MIN_COUNT"]
+    else:
+        os.environ["PM_WAVE_MIN_COUNT"] = old
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_12196_amd as pm
+    pm.lib()
+    return pm
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+def t32(torch_mod, x):
+    return torch_mod.from_numpy(np.ascontiguousarray(np.asarray(x, np.int32))).cuda()
+
+
+def host(x):
+    return x.cpu().numpy()
+
+
+def dense(n=3000, deg=150, seed=4):
+    """Random graph with most degrees in 65..512 (plus a few above)."""
+    rng = np.random.default_rng(seed)
+    m = n * deg // 2
+    u = rng.integers(0, n, m)
+    v = rng.integers(0, n, m)
+    # a few hubs above 512
+    hubs = rng.integers(0, n, 8)
+    u = np.concatenate([u, np.repeat(hubs, 700)])
+    v = np.concatenate([v, rng.integers(0, n, 8 * 700)])
+    keep = u != v
+    lo, hi = np.minimum(u[keep], v[keep]), np.maximum(u[keep], v[keep])
+    uv = np.unique(np.stack([lo, hi], 1), axis=0)
+    w = rng.integers(1, 11, uv.shape[0])
+    return gen.from_edges(n, uv[:, 0], uv[:, 1], w, rng.integers(1, 5, n))
+
+
+def bipartite(a=100, b=200, seed=6):
+    """K_{a,b}: after heavy-edge matching b - a vertices of degree a stay
+    unmatched with one common neighbourhood (two-hop twins)."""
+    rng = np.random.default_rng(seed)
+    uu, vv = np.meshgrid(np.arange(a), a + np.arange(b), indexing="ij")
+    u, v = uu.ravel(), vv.ravel()
+    return gen.from_edges(a + b, u, v, rng.integers(1, 11, u.shape[0]), np.ones(a + b, np.int64))
+
+
+GRAPHS = {}
+
+
+def graph(name):
+    if name not in GRAPHS:
+        GRAPHS[name] = dense() if name == "dense" else bipartite() if name == "kbip" \
+            else gen.get(name).graph()
+    return GRAPHS[name]
+
+
+CASES = [("dense", (4, 16, 8), (1, 10, 100)),
+         ("dense", (3, 5, 7), (2, 7, 50)),
+         ("dense", (4, 16, 32), (1, 10, 100)),
+         ("rmat14", (4, 16, 8), (1, 10, 100)),
+         ("rmat14", (4, 16, 32), (1, 10, 100))]
+
+
+@pytest.mark.parametrize("name,a,d", CASES)
+def test_comm_cost_parity_wave(pm, pmo, torch_mod, name, a, d):
+    g = graph(name)
+    part = gen.random_mapping(g.n, int(np.prod(a)), 3)
+    say("comm_cost wave", name, a)
+    assert pm.pm_comm_cost(pm.DeviceGraph.from_host(g), a, d, t32(torch_mod, part)) == \
+        pmo.comm_cost(g, part, a, d)
+
+
+@pytest.mark.parametrize("name,a,d", CASES)
+def test_lp_rounds_parity_wave(pm, pmo, torch_mod, name, a, d):
+    g = graph(name)
+    k = int(np.prod(a))
+    part_h = gen.random_balanced_mapping(g.n, k, 5)
+    lock_h = np.zeros(g.n, np.uint8)
+    dg = pm.DeviceGraph.from_host(g)
+    part_d = t32(torch_mod, part_h)
+    lock_d = torch_mod.zeros(g.n, dtype=torch_mod.uint8, device="cuda")
+    for rnd in range(3):
+        say("lp_round wave", name, a, rnd)
+        part_h, lock_h, tgt_h, gain_h, mv_h = pmo.lp_round(g, a, d, part_h, lock_h)
+        tgt_d, gain_d, mv_d = pm.pm_lp_round(dg, a, d, part_d, lock_d)
+        assert np.array_equal(host(gain_d), gain_h)
+        assert np.array_equal(host(tgt_d), tgt_h)
+        assert np.array_equal(host(mv_d), mv_h)
+        assert np.array_equal(host(part_d), part_h)
+
+
+@pytest.mark.parametrize("name,a,d", CASES)
+@pytest.mark.parametrize("strong", [False, True])
+@pytest.mark.parametrize("jrb", [False, True])
+def test_rebalance_parity_wave(pm, pmo, torch_mod, name, a, d, strong, jrb):
+    g = graph(name)
+    k = int(np.prod(a))
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    part = gen.random_mapping(g.n, k, 11)
+    part[: g.n // 10] = 1
+    dg = pm.DeviceGraph.from_host(g)
+    opts = pm.options(j_rebalance=True) if jrb else None
+    var = pmo.variants(j_rebalance=True) if jrb else None
+    for it in (1, 2):
+        say("rebalance wave", name, a, strong, jrb, it)
+        exp_part, exp_moved = pmo.rebalance(g, k, part, strong, lm, sg, 77, 2, it,
+                                            a=a, d=d, var=var)
+        part_d = t32(torch_mod, part)
+        mv = pm.pm_rebalance(dg, a, d, part_d, strong, lm, sg, 77, 2, it, opts=opts)
+        assert np.array_equal(host(mv), exp_moved)
+        assert np.array_equal(host(part_d), exp_part)
+        part = exp_part
+
+
+@pytest.mark.parametrize("name,a,d", CASES[:2] + CASES[3:4])
+def test_refine_parity_wave(pm, pmo, torch_mod, name, a, d):
+    g = graph(name)
+    part = gen.random_mapping(g.n, int(np.prod(a)), 21)
+    part[: g.n // 5] = 0
+    say("refine wave", name, a)
+    rc_h, part_h, st_h = pmo.refine(g, a, d, 0.03, 9, part, level=3)
+    part_d = t32(torch_mod, part)
+    rc_d, st_d = pm.pm_refine(pm.DeviceGraph.from_host(g), a, d, 0.03, 9, part_d, level=3)
+    assert rc_d == rc_h and st_d.j_final == st_h.j_final
+    assert np.array_equal(host(part_d), part_h)
+
+
+@pytest.mark.parametrize("name", ["dense", "rmat14", "kbip"])
+def test_hem_two_hop_and_contract_parity_wave(pm, pmo, name):
+    g = graph(name)
+    lm = pmo.lmax(int(g.vwgt.sum()), 16, 0.03)
+    say("hem+contract wave", name)
+    rounds_h, match_h = pmo.hem(g, lm, 5, level=1)
+    dg = pm.DeviceGraph.from_host(g)
+    match_d, rounds_d = pm.pm_hem(dg, lm, 5, level=1)
+    assert rounds_d == rounds_h
+    assert np.array_equal(host(match_d), match_h)
+    nc_h, cmap_h = pmo.coarse_map(match_h)
+    cx_h, ca_h, cw_h, cv_h = pmo.contract(g, cmap_h, nc_h)
+    cmap_d, cg = pm.pm_contract(dg, match_d)
+    assert np.array_equal(host(cmap_d), cmap_h)
+    assert np.array_equal(host(cg.xadj), cx_h)
+    assert np.array_equal(host(cg.adjncy), ca_h)
+    assert np.array_equal(host(cg.adjwgt), cw_h)
+
+
+@pytest.mark.parametrize("name,a,d", CASES[:2] + CASES[3:4])
+def test_map_parity_wave(pm, pmo, name, a, d):
+    g = graph(name)
+    say("map wave", name, a)
+    rc_h, part_h, st_h = pmo.map_graph(g, a, d, 0.03, 1)
+    rc_d, part_d, st_d = pm.pm_map(pm.DeviceGraph.from_host(g), a, d, 0.03, 1)
+    assert rc_d == rc_h and st_d.j_final == st_h.j_final
+    assert np.array_equal(host(part_d), part_h)
