@@ -4,6 +4,7 @@
 
 #include "device_util.h"
 #include "kernels.h"
+#include "prim.h"
 
 namespace pm {
 
@@ -213,6 +214,57 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
   } else {
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
   }
+  PM_LAUNCH_CHECK();
+}
+
+// ---- active-set compaction between matching rounds ---------------------------
+// After the first rounds few vertices must look again (those whose preferred
+// partner was matched), but a launch over all class tiles still visits every
+// vertex.  On large levels the active ones are therefore compacted: a flag
+// per position of the class list, a stable selection of the flagged
+// positions (class order kept), then the new class offsets and the list of
+// vertex ids.
+__global__ void k_hem_active_flags(int32_t n, const int32_t *list, const int32_t *match,
+                                   const int32_t *pref, uint8_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = list[i];
+  const int32_t m = match[v];
+  const int32_t p = pref[v];
+  flag[i] = m < 0 && (p == kPrefUnknown || (p >= 0 && match[p] >= 0)) ? 1 : 0;
+}
+
+// off_out[c] = first compacted position of class c (classes by the offsets
+// off[] of the full list); list_out[j] = list[pos[j]].
+__global__ void k_compact_bounds(int32_t n, Classes cl, const int32_t *pos, const int32_t *count,
+                                 int32_t *list_out, int32_t *off_out) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t m = *count;
+  if (j > m) return;
+  auto cls_of = [&](int32_t p) {
+    int c = 0;
+    while (c < NCLS - 1 && p >= cl.off[c + 1]) ++c;
+    return c;
+  };
+  const int prev = j > 0 ? cls_of(pos[j - 1]) : -1;
+  const int cur = j < m ? cls_of(pos[j]) : NCLS;
+  for (int c = prev + 1; c <= cur; ++c) off_out[c] = (int32_t)j;
+  if (j < m) list_out[j] = cl.list[pos[j]];
+}
+
+void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
+                 const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s) {
+  uint8_t *flag = ar.alloc_n<uint8_t>((size_t)n + 1);
+  int32_t *pos = ar.alloc_n<int32_t>((size_t)n + 1);
+  int32_t *count = ar.alloc_n<int32_t>(1);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_hem_active_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, n, cl.list,
+                       match, pref, flag);
+    PM_LAUNCH_CHECK();
+  }
+  select_indices(ar, flag, pos, count, n, s);
+  hipLaunchKernelGGL(k_compact_bounds, dim3(grid_for((int64_t)n + 1)), dim3(kThreads), 0, s, n,
+                     cl, pos, count, list_out, off_out);
   PM_LAUNCH_CHECK();
 }
 

@@ -1,6 +1,7 @@
 // driver.cpp -- host orchestration and the C ABI of the process-mapping library.
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -110,6 +111,12 @@ struct Ctx {
     sp.b = sp.a + stripe_words();
     PM_HIP(hipMemsetAsync(dev, 0, sizeof(Status), s));
     PM_HIP(hipMemsetAsync(sp.a, 0, sizeof(int64_t) * 2 * (size_t)stripe_words(), s));
+  }
+  // pinned host words after the status copy (the staging buffer holds
+  // sizeof(Status) + 4096 bytes), for small copies that a pull() orders
+  int32_t *aux() {
+    static_assert(sizeof(Status) <= 512, "status block grew");
+    return reinterpret_cast<int32_t *>(reinterpret_cast<char *>(host) + 512);
   }
   // Status read-back: a kernel publishes the status into mapped host memory
   // and the host polls its sequence number, which returns sooner than a copy
@@ -292,15 +299,37 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   const uint64_t hseed = mix_hash(seed ^ kTagMatch, (uint64_t)(int64_t)level);
   int32_t rounds = 0;
   int64_t matched = 0;
+  // large levels: after each round only the vertices that must look again
+  // are tiled for the next one
+  // (PM_HEM_COMPACT_MIN_N overrides the size threshold; tests use it)
+  int64_t cmin = kHemCompactMinN;
+  if (const char *e = std::getenv("PM_HEM_COMPACT_MIN_N")) cmin = std::atoll(e);
+  const bool compact = g.n >= cmin;
+  const size_t mark = cx.ar.mark();
+  int32_t *clist = compact ? cx.ar.alloc_n<int32_t>(g.n) : nullptr;
+  int32_t *coff = compact ? cx.ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
+  int32_t *hoff = cx.aux();
+  Classes cur = L.cl;
   while (rounds < 64) {
     ++rounds;
-    hem_prefer(g, L.cl, lmax, hseed, match, pref, s);
+    hem_prefer(g, cur, lmax, hseed, match, pref, s);
     hem_commit(g.n, pref, match, cx.counter, cx.dev, s);
-    cx.pull();
+    const size_t round_mark = cx.ar.mark();
+    if (compact) {
+      hem_compact(cx.ar, L.cl, g.n, match, pref, clist, coff, s);
+      PM_HIP(hipMemcpyAsync(hoff, coff, sizeof(int32_t) * (NCLS + 1), hipMemcpyDeviceToHost, s));
+    }
+    cx.pull();  // the round's work is done: its scratch can go
+    cx.ar.rewind(round_mark);
     const int32_t added = cx.host->count;
     matched += added;
     if (added == 0) break;
+    if (compact) {
+      cur.list = clist;
+      for (int c = 0; c <= NCLS; ++c) cur.off[c] = hoff[c];
+    }
   }
+  cx.ar.rewind(mark);
   // two-hop matching while 75 % or fewer of the vertices are matched
   const int64_t lim = 3 * (int64_t)g.n;
   const uint64_t tseed = mix_hash(seed ^ kTagTwin, (uint64_t)(int64_t)level);

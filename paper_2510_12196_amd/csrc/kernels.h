@@ -223,6 +223,11 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
                 const int32_t *match, int32_t *pref, hipStream_t s);
 // st->count = new matches.  counter: 65 64-bit completion counters, zero
 // between launches.
+// Compacts the vertices that must recompute their preference: list_out
+// (device int32[n]) gets their ids in class order, off_out (device
+// int32[NCLS + 1]) the class offsets into it.
+void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
+                 const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s);
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
                 hipStream_t s);
 // Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched

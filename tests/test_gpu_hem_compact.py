@@ -1,0 +1,67 @@
+"""Matching rounds that tile only the active vertices (used on large levels)
+against the oracle.  PM_HEM_COMPACT_MIN_N=1 turns the compaction on for the
+small graphs here; the full-size rgg20 map parity covers it at its own
+threshold."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def force_compaction():
+    old = os.environ.get("PM_HEM_COMPACT_MIN_N")
+    os.environ["PM_HEM_COMPACT_MIN_N"] = "1"
+    yield
+    if old is None:
+        del os.environ["PM_HEM_COMPACT_MIN_N"]
+    else:
+        os.environ["PM_HEM_COMPACT_MIN_N"] = old
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2510_12196_amd as pm
+    pm.lib()
+    return pm
+
+
+def host(x):
+    return x.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14", "rmat14", "del16"])
+@pytest.mark.parametrize("seed", [5, 6])
+def test_hem_compacted_parity(pm, pmo, name, seed):
+    w = gen.get(name)
+    g = w.graph()
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    say("hem compacted", name, seed)
+    rounds_h, match_h = pmo.hem(g, lm, seed, level=2)
+    match_d, rounds_d = pm.pm_hem(pm.DeviceGraph.from_host(g), lm, seed, level=2)
+    assert rounds_d == rounds_h
+    assert np.array_equal(host(match_d), match_h)
+
+
+@pytest.mark.parametrize("name", ["rgg14", "rmat14"])
+def test_map_with_compacted_matching_parity(pm, pmo, name):
+    w = gen.get(name)
+    g = w.graph()
+    say("map compacted matching", name)
+    rc_h, part_h, st_h = pmo.map_graph(g, w.a, w.d, w.eps, 1)
+    rc_d, part_d, st_d = pm.pm_map(pm.DeviceGraph.from_host(g), w.a, w.d, w.eps, 1)
+    assert rc_d == rc_h and st_d.j_final == st_h.j_final
+    assert list(st_d.level_hem_rounds[: st_d.levels]) == list(st_h.level_hem_rounds[: st_h.levels])
+    assert np.array_equal(host(part_d), part_h)
