@@ -252,6 +252,13 @@ __global__ void k_compact_bounds(int32_t n, Classes cl, const int32_t *pos, cons
   if (j < m) list_out[j] = cl.list[pos[j]];
 }
 
+void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int32_t *count,
+                    int32_t *list_out, int32_t *off_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_bounds, dim3(grid_for((int64_t)n + 1)), dim3(kThreads), 0, s, n,
+                     cl, pos, count, list_out, off_out);
+  PM_LAUNCH_CHECK();
+}
+
 void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
                  const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s) {
   uint8_t *flag = ar.alloc_n<uint8_t>((size_t)n + 1);
@@ -263,9 +270,7 @@ void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
     PM_LAUNCH_CHECK();
   }
   select_indices(ar, flag, pos, count, n, s);
-  hipLaunchKernelGGL(k_compact_bounds, dim3(grid_for((int64_t)n + 1)), dim3(kThreads), 0, s, n,
-                     cl, pos, count, list_out, off_out);
-  PM_LAUNCH_CHECK();
+  compact_bounds(n, cl, pos, count, list_out, off_out, s);
 }
 
 // v and pref[v] are matched iff they prefer each other.  The count goes up a

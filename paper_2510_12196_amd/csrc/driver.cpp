@@ -179,6 +179,11 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   int64_t *w = ar.alloc_n<int64_t>(ncodes);
   int64_t *wst = alloc_weight_stripes(ar, h, s);
   RebalanceBuffers rb = alloc_rebalance(ar, n, h, s);
+  // PM_REB_COMPACT_MIN_N overrides the size threshold (tests use it)
+  int64_t rmin = kRebCompactMinN;
+  if (const char *e = std::getenv("PM_REB_COMPACT_MIN_N")) rmin = std::atoll(e);
+  int32_t *slist = n >= rmin && n > 0 ? ar.alloc_n<int32_t>(n) : nullptr;
+  int32_t *soff = slist ? ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
 
   hipEvent_t ev0, ev1;
   PM_HIP(hipEventCreate(&ev0));
@@ -220,9 +225,22 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     } else {
       const bool strong = iw >= 2;
       const uint64_t hseed = mix_hash(reb_seed, (uint64_t)bodies);
-      rebalance_round(ar, g, cl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
+      // large levels: only the vertices of overloaded blocks are tiled for
+      // the selection and the moves (movers are sources)
+      Classes rcl = cl;
+      if (slist) {
+        const size_t m2 = ar.mark();
+        reb_sources(ar, cl, (int32_t)n, cur, w, lmax, rb.key, slist, soff, s);
+        PM_HIP(hipMemcpyAsync(cx.aux(), soff, sizeof(int32_t) * (NCLS + 1), hipMemcpyDeviceToHost,
+                              s));
+        cx.pull();
+        ar.rewind(m2);
+        rcl.list = slist;
+        for (int c = 0; c <= NCLS; ++c) rcl.off[c] = cx.aux()[c];
+      }
+      rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
                       cx.dev, s, var);
-      apply_moves(g, cl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, &E, s);
+      apply_moves(g, rcl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, &E, s);
       if (strong) {
         iw = 0;
         ++R.st.strong_iterations;

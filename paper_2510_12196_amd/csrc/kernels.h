@@ -173,6 +173,11 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
 // ready for apply_moves.  The eligible destinations (rb.elig_*, counts in
 // *st_dev) must be those of the current weights (StepEnd / step_status).  No
 // host synchronisation.
+// Rebalancing sources on large levels: the vertices of blocks heavier than
+// lmax, compacted in class order (list_out, off_out as for compact_bounds);
+// every other vertex gets key -1 (not a source) here.
+void reb_sources(Arena &ar, const Classes &cl, int32_t n, const int32_t *part, const int64_t *w,
+                 int64_t lmax, int32_t *key, int32_t *list_out, int32_t *off_out, hipStream_t s);
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
@@ -223,6 +228,11 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
                 const int32_t *match, int32_t *pref, hipStream_t s);
 // st->count = new matches.  counter: 65 64-bit completion counters, zero
 // between launches.
+// Given the positions pos[0..*count) (ascending) of selected entries of the
+// class list, writes their vertex ids (list_out) and the class offsets into
+// that compacted list (off_out, NCLS + 1 entries).
+void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int32_t *count,
+                    int32_t *list_out, int32_t *off_out, hipStream_t s);
 // Compacts the vertices that must recompute their preference: list_out
 // (device int32[n]) gets their ids in class order, off_out (device
 // int32[NCLS + 1]) the class offsets into it.

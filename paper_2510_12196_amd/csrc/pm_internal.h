@@ -129,6 +129,7 @@ enum { CLS_BIG = 0, CLS_W, CLS_G64, CLS_G32, CLS_G16, CLS_G8, CLS_ISO, NCLS };
 constexpr int kWaveMaxDeg = 512;
 constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 constexpr int32_t kHemCompactMinN = 1 << 18;  // matching rounds tile only active vertices
+constexpr int32_t kRebCompactMinN = 1 << 19;  // rebalancing tiles only overloaded blocks
 __host__ __device__ constexpr int class_group(int cls) {
   return cls == CLS_G8 ? 8 : cls == CLS_G16 ? 16 : cls == CLS_G32 ? 32
        : (cls == CLS_G64 || cls == CLS_W) ? 64 : 1;

@@ -1854,6 +1854,30 @@ static void keyed_prefix(KPArgs A, hipStream_t s) {
   PM_LAUNCH_CHECK();
 }
 
+__global__ void k_reb_candidates(int32_t n, const int32_t *list, const int32_t *part,
+                                 const int64_t *w, int64_t lmax, int32_t *key, uint8_t *flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t v = list[i];
+  const bool over = w[part[v]] > lmax;
+  flag[i] = over ? 1 : 0;
+  if (!over) key[v] = -1;
+}
+
+void reb_sources(Arena &ar, const Classes &cl, int32_t n, const int32_t *part, const int64_t *w,
+                 int64_t lmax, int32_t *key, int32_t *list_out, int32_t *off_out, hipStream_t s) {
+  uint8_t *flag = ar.alloc_n<uint8_t>((size_t)n + 1);
+  int32_t *pos = ar.alloc_n<int32_t>((size_t)n + 1);
+  int32_t *count = ar.alloc_n<int32_t>(1);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_reb_candidates, dim3(grid_for(n)), dim3(kThreads), 0, s, n, cl.list, part,
+                       w, lmax, key, flag);
+    PM_LAUNCH_CHECK();
+  }
+  select_indices(ar, flag, pos, count, n, s);
+  compact_bounds(n, cl, pos, count, list_out, off_out, s);
+}
+
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
