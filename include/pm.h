@@ -161,6 +161,31 @@ const char *pm_strerror(int code);
  * other pm_* call is running. */
 void pm_release(void);
 
+/* Launch parameters (process-wide).  They decide how vertices are mapped to
+ * lanes and which vertices a launch tiles, never a result: every mapping,
+ * J and status is the same under any valid setting.  The initial values come
+ * from the environment variables of the same names in upper case with a PM_
+ * prefix (PM_GROUP_V, ...), else the defaults below.
+ *   group_v            vertices per lane group in a tile of the degree
+ *                      classes up to 64 arcs: 1 or 2 (default 1)
+ *   wave_min_count     a level uses the one-wave-per-vertex class (65..512
+ *                      arcs) once it has this many such vertices, else they
+ *                      take a workgroup each (default 8192; >= 1)
+ *   hem_compact_min_n  from this level size on, matching rounds tile only the
+ *                      vertices that must look again (default 2^18; >= 1)
+ *   reb_compact_min_n  from this level size on, rebalancing tiles only the
+ *                      vertices of overloaded blocks (default 2^19; >= 1)
+ * pm_set_tuning returns PM_EINVAL (nothing changed) for values outside these
+ * ranges.  Calls already running may see either setting. */
+typedef struct pm_tuning {
+  int32_t group_v;
+  int32_t wave_min_count;
+  int32_t hem_compact_min_n;
+  int32_t reb_compact_min_n;
+} pm_tuning;
+int pm_get_tuning(pm_tuning *out);
+int pm_set_tuning(const pm_tuning *t);
+
 /* J(Pi) = sum over all arcs (u,v) of w(u,v) * D(Pi(u),Pi(v)) (Section 2,
  * GPMP objective; both directions of each edge count, so J is twice the sum
  * over undirected edges).  part: device int32[n].  j_out: HOST int64. */

@@ -103,6 +103,8 @@ _SIGS = {
     "pm_map_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P, _P]),
     "pm_subgraphs": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pm_map_hm": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P]),
+    "pm_get_tuning": (ctypes.c_int, [_P]),
+    "pm_set_tuning": (ctypes.c_int, [_P]),
     "pm_map_batch": (ctypes.c_int, [_P, _I32, _I32, _P]),
     "pm_job_footprint": (_I64, [_P, _P]),
     "pm_server_create": (_P, [_I64, _I32]),
@@ -173,6 +175,45 @@ def options(jet_c=None, j_rebalance: bool = False) -> PmOptions:
     if j_rebalance:
         o.variants |= PM_VARIANT_J_REBALANCE
     return o
+
+
+class PmTuning(ctypes.Structure):
+    _fields_ = [("group_v", ctypes.c_int32), ("wave_min_count", ctypes.c_int32),
+                ("hem_compact_min_n", ctypes.c_int32), ("reb_compact_min_n", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def get_tuning() -> dict:
+    """The process-wide launch parameters (never change a result)."""
+    t = PmTuning()
+    _check(lib().pm_get_tuning(ctypes.byref(t)), "pm_get_tuning")
+    return t.as_dict()
+
+
+def set_tuning(**kw) -> dict:
+    """Sets some launch parameters; returns the previous ones."""
+    old = get_tuning()
+    t = PmTuning(**{**old, **{k: int(v) for k, v in kw.items()}})
+    _check(lib().pm_set_tuning(ctypes.byref(t)), "pm_set_tuning")
+    return old
+
+
+class tuned:
+    """Context manager: launch parameters for the duration of a block."""
+
+    def __init__(self, **kw):
+        self.kw = kw
+        self.old = None
+
+    def __enter__(self):
+        self.old = set_tuning(**self.kw)
+        return self
+
+    def __exit__(self, *exc):
+        set_tuning(**self.old)
+        return False
 
 
 def _opt(o):

@@ -179,9 +179,8 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   int64_t *w = ar.alloc_n<int64_t>(ncodes);
   int64_t *wst = alloc_weight_stripes(ar, h, s);
   RebalanceBuffers rb = alloc_rebalance(ar, n, h, s);
-  // PM_REB_COMPACT_MIN_N overrides the size threshold (tests use it)
-  int64_t rmin = kRebCompactMinN;
-  if (const char *e = std::getenv("PM_REB_COMPACT_MIN_N")) rmin = std::atoll(e);
+  // (the size threshold is a launch parameter: pm_set_tuning)
+  const int64_t rmin = tuning().reb_compact_min_n;
   int32_t *slist = n >= rmin && n > 0 ? ar.alloc_n<int32_t>(n) : nullptr;
   int32_t *soff = slist ? ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
 
@@ -319,9 +318,8 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   int64_t matched = 0;
   // large levels: after each round only the vertices that must look again
   // are tiled for the next one
-  // (PM_HEM_COMPACT_MIN_N overrides the size threshold; tests use it)
-  int64_t cmin = kHemCompactMinN;
-  if (const char *e = std::getenv("PM_HEM_COMPACT_MIN_N")) cmin = std::atoll(e);
+  // (the size threshold is a launch parameter: pm_set_tuning)
+  const int64_t cmin = tuning().hem_compact_min_n;
   const bool compact = g.n >= cmin;
   const size_t mark = cx.ar.mark();
   int32_t *clist = compact ? cx.ar.alloc_n<int32_t>(g.n) : nullptr;

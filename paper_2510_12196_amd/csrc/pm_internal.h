@@ -130,6 +130,13 @@ constexpr int kWaveMaxDeg = 512;
 constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 constexpr int32_t kHemCompactMinN = 1 << 18;  // matching rounds tile only active vertices
 constexpr int32_t kRebCompactMinN = 1 << 19;  // rebalancing tiles only overloaded blocks
+
+// Process-wide launch parameters (pm_set_tuning); read at each call.
+struct TuningValues {
+  int32_t group_v, wave_min_count, hem_compact_min_n, reb_compact_min_n;
+};
+TuningValues tuning();
+void set_tuning(const TuningValues &t);
 __host__ __device__ constexpr int class_group(int cls) {
   return cls == CLS_G8 ? 8 : cls == CLS_G16 ? 16 : cls == CLS_G32 ? 32
        : (cls == CLS_G64 || cls == CLS_W) ? 64 : 1;

@@ -91,10 +91,8 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
   // W tiles (a wave per vertex) pay off once they fill the chip; with fewer
   // such vertices a workgroup per vertex finishes sooner, so degrees above 64
   // then all go to BIG (the two paths compute the same results).
-  // PM_WAVE_MIN_COUNT overrides the threshold (tests use it to reach the W
-  // paths on small graphs).
-  int64_t wmin = kWaveMinCount;
-  if (const char *e = std::getenv("PM_WAVE_MIN_COUNT")) wmin = std::atoll(e);
+  // (the threshold is a launch parameter: pm_set_tuning)
+  const int64_t wmin = tuning().wave_min_count;
   for (int32_t wmax : {kWaveMaxDeg, 64}) {
     PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2 * NCLS, s));
     if (g.n > 0) {
@@ -134,14 +132,7 @@ Classes tiled(const Classes &cl, int V, bool w_as_big) {
   return t;
 }
 
-int group_v() {
-  static const int v = [] {
-    const char *e = std::getenv("PM_GROUP_V");
-    const int x = e ? std::atoi(e) : 1;
-    return x == 2 ? 2 : 1;
-  }();
-  return v;
-}
+int group_v() { return tuning().group_v; }
 
 // ===========================================================================
 // id <-> code conversion

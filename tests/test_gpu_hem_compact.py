@@ -1,8 +1,7 @@
 """Matching rounds that tile only the active vertices (used on large levels)
-against the oracle.  PM_HEM_COMPACT_MIN_N=1 turns the compaction on for the
-small graphs here; the full-size rgg20 map parity covers it at its own
-threshold."""
-import os
+against the oracle.  The launch parameter hem_compact_min_n=1 turns the
+compaction on for the small graphs here; the full-size rgg20 map parity
+covers it at its own threshold."""
 import sys
 
 import numpy as np
@@ -18,17 +17,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", autouse=True)
-def force_compaction():
-    old = os.environ.get("PM_HEM_COMPACT_MIN_N")
-    os.environ["PM_HEM_COMPACT_MIN_N"] = "1"
-    yield
-    if old is None:
-        del os.environ["PM_HEM_COMPACT_MIN_N"]
-    else:
-        os.environ["PM_HEM_COMPACT_MIN_N"] = old
-
-
 @pytest.fixture(scope="module")
 def pm():
     import torch
@@ -36,6 +24,12 @@ def pm():
     import paper_2510_12196_amd as pm
     pm.lib()
     return pm
+
+
+@pytest.fixture(scope="module", autouse=True)
+def force_path(pm):
+    with pm.tuned(hem_compact_min_n=1):
+        yield
 
 
 def host(x):

@@ -1,8 +1,8 @@
 """Rebalancing rounds that tile only the vertices of overloaded blocks (used
 on large levels) against the oracle, through refinement and the whole map.
-PM_REB_COMPACT_MIN_N=1 turns the compaction on for the small graphs here;
-the full-size rgg20 parity tests cover it at its own threshold."""
-import os
+The launch parameter reb_compact_min_n=1 turns the compaction on for the
+small graphs here; the full-size rgg20 parity tests cover it at its own
+threshold."""
 import sys
 
 import numpy as np
@@ -18,17 +18,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", autouse=True)
-def force_compaction():
-    old = os.environ.get("PM_REB_COMPACT_MIN_N")
-    os.environ["PM_REB_COMPACT_MIN_N"] = "1"
-    yield
-    if old is None:
-        del os.environ["PM_REB_COMPACT_MIN_N"]
-    else:
-        os.environ["PM_REB_COMPACT_MIN_N"] = old
-
-
 @pytest.fixture(scope="module")
 def pm():
     import torch
@@ -36,6 +25,12 @@ def pm():
     import paper_2510_12196_amd as pm
     pm.lib()
     return pm
+
+
+@pytest.fixture(scope="module", autouse=True)
+def force_path(pm):
+    with pm.tuned(reb_compact_min_n=1):
+        yield
 
 
 def t32(torch_mod, x):

@@ -1,10 +1,9 @@
 """The one-wave-per-vertex paths (degree 65..512) against the oracle.
 
 The library sends such vertices to these paths only when there are enough of
-them to fill the chip; PM_WAVE_MIN_COUNT=1 forces them on the small graphs
-here.  Hierarchies with at most 2^10 block codes use the per-wave LDS
+them to fill the chip; the launch parameter wave_min_count=1 forces them on
+the small graphs here.  Hierarchies with at most 2^10 block codes use the per-wave LDS
 histogram; (4, 16, 32) needs 2^11 codes and takes the workgroup fallback."""
-import os
 import sys
 
 import numpy as np
@@ -20,17 +19,6 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module", autouse=True)
-def force_wave_class():
-    old = os.environ.get("PM_WAVE_MIN_COUNT")
-    os.environ["PM_WAVE_MIN_COUNT"] = "1"
-    yield
-    if old is None:
-        del os.environ["PM_WAVE_MIN_COUNT"]
-    else:
-        os.environ["PM_WAVE_MIN_COUNT"] = old
-
-
 @pytest.fixture(scope="module")
 def pm():
     import torch
@@ -38,6 +26,12 @@ def pm():
     import paper_2510_12196_amd as pm
     pm.lib()
     return pm
+
+
+@pytest.fixture(scope="module", autouse=True)
+def force_path(pm):
+    with pm.tuned(wave_min_count=1):
+        yield
 
 
 @pytest.fixture(scope="module")

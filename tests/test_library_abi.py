@@ -69,3 +69,8 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pm, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         pm.lib()
+
+
+def test_tuning_struct_layout():
+    import paper_2510_12196_amd as pm
+    assert ctypes.sizeof(pm.PmTuning) == 16
