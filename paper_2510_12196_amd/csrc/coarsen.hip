@@ -283,7 +283,7 @@ void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
 constexpr int kHemLeaves = 64;
 __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
                                                          int32_t *match, uint64_t *counter,
-                                                         Status *st) {
+                                                         Status *st, int32_t *count_out) {
   __shared__ BlockScratch sc;
   int64_t hits = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -312,13 +312,15 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
   if ((r >> 32) != leaves) return;
   atomicExch(rp, 0ull);
   st->count = (int32_t)(r & 0xFFFFFFFFull);
+  if (count_out) *count_out = (int32_t)(r & 0xFFFFFFFFull);
 }
 
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
-                hipStream_t s) {
+                int32_t *count_out, hipStream_t s) {
   unsigned g = grid_for(n > 0 ? n : 1);
   if (g > kMaxGrid) g = kMaxGrid;
-  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st);
+  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st,
+                     count_out);
   PM_LAUNCH_CHECK();
 }
 
@@ -471,14 +473,21 @@ void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int 
   fold_stripes(stripes, nullptr, &st->count, s);
 }
 
-__global__ void k_contract_heads(int64_t m, const uint64_t *key, int32_t *head) {
+// The sorted keys end with the self-loop sentinels: m = nnz - *self arcs are
+// real (the count is read on the device, so no host read-back is needed
+// between the sort and the emission).
+__global__ void k_contract_heads(int64_t nnz, const int32_t *self, const uint64_t *key,
+                                 int32_t *head) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) head[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+  const int64_t m = nnz - *self;
+  if (i < nnz) head[i] = i < m && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
 }
 
-void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL(k_contract_heads, dim3(grid_for(m)), dim3(kThreads), 0, s, m, key, head);
+void contract_heads(int64_t nnz, const int32_t *self, const uint64_t *key, int32_t *head,
+                    hipStream_t s) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(k_contract_heads, dim3(grid_for(nnz)), dim3(kThreads), 0, s, nnz, self, key,
+                     head);
   PM_LAUNCH_CHECK();
 }
 
@@ -487,10 +496,11 @@ void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s
 // (position of its last run + 1) - (position of its first run); only the
 // threads of those two runs touch the row's counter (a hub row would
 // otherwise take one atomic per run on a single address).
-__global__ void k_contract_emit(int64_t m, const uint64_t *key, const int32_t *val,
-                                const int32_t *head, const int32_t *pos, int bits,
-                                int32_t *cadj, int32_t *cw, int32_t *rowcnt) {
+__global__ void k_contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key,
+                                const int32_t *val, const int32_t *head, const int32_t *pos,
+                                int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = nnz - *self;
   if (i >= m || !head[i]) return;
   const uint64_t k = key[i];
   int64_t sum = 0;
@@ -507,12 +517,12 @@ __global__ void k_contract_emit(int64_t m, const uint64_t *key, const int32_t *v
   else if (last) atomicAdd(&rowcnt[row], o + 1);
 }
 
-void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,
-                   const int32_t *pos, int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt,
-                   hipStream_t s) {
-  if (m <= 0) return;
-  hipLaunchKernelGGL(k_contract_emit, dim3(grid_for(m)), dim3(kThreads), 0, s, m, key, val, head,
-                     pos, bits, cadj, cw, rowcnt);
+void contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key, const int32_t *val,
+                   const int32_t *head, const int32_t *pos, int bits, int32_t *cadj, int32_t *cw,
+                   int32_t *rowcnt, hipStream_t s) {
+  if (nnz <= 0) return;
+  hipLaunchKernelGGL(k_contract_emit, dim3(grid_for(nnz)), dim3(kThreads), 0, s, nnz, self, key,
+                     val, head, pos, bits, cadj, cw, rowcnt);
   PM_LAUNCH_CHECK();
 }
 

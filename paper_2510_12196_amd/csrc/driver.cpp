@@ -326,23 +326,42 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   int32_t *coff = compact ? cx.ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
   int32_t *hoff = cx.aux();
   Classes cur = L.cl;
-  while (rounds < 64) {
-    ++rounds;
-    hem_prefer(g, cur, lmax, hseed, match, pref, s);
-    hem_commit(g.n, pref, match, cx.counter, cx.dev, s);
-    const size_t round_mark = cx.ar.mark();
-    if (compact) {
+  if (compact) {
+    while (rounds < 64) {
+      ++rounds;
+      hem_prefer(g, cur, lmax, hseed, match, pref, s);
+      hem_commit(g.n, pref, match, cx.counter, cx.dev, nullptr, s);
+      const size_t round_mark = cx.ar.mark();
       hem_compact(cx.ar, L.cl, g.n, match, pref, clist, coff, s);
       PM_HIP(hipMemcpyAsync(hoff, coff, sizeof(int32_t) * (NCLS + 1), hipMemcpyDeviceToHost, s));
-    }
-    cx.pull();  // the round's work is done: its scratch can go
-    cx.ar.rewind(round_mark);
-    const int32_t added = cx.host->count;
-    matched += added;
-    if (added == 0) break;
-    if (compact) {
+      cx.pull();  // the round's work is done: its scratch can go
+      cx.ar.rewind(round_mark);
+      const int32_t added = cx.host->count;
+      matched += added;
+      if (added == 0) break;
       cur.list = clist;
       for (int c = 0; c <= NCLS; ++c) cur.off[c] = hoff[c];
+    }
+  } else {
+    // Rounds go in groups of kHemRoundsPerRead between status read-backs:
+    // once a round adds no pair, every later round is a no-op (no vertex is
+    // active and no mutual preference exists), so running a few past the
+    // last one changes nothing; the per-round counts say where it stopped.
+    int32_t *counts = cx.ar.alloc_n<int32_t>(64);
+    bool done = false;
+    while (!done && rounds < 64) {
+      const int k = 64 - rounds < kHemRoundsPerRead ? 64 - rounds : kHemRoundsPerRead;
+      for (int j = 0; j < k; ++j) {
+        hem_prefer(g, cur, lmax, hseed, match, pref, s);
+        hem_commit(g.n, pref, match, cx.counter, cx.dev, counts + rounds + j, s);
+      }
+      PM_HIP(hipMemcpyAsync(hoff, counts + rounds, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+      cx.pull();
+      for (int j = 0; j < k && !done; ++j) {
+        ++rounds;
+        matched += hoff[j];
+        done = hoff[j] == 0;
+      }
     }
   }
   cx.ar.rewind(mark);
@@ -371,17 +390,15 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
   uint64_t *key2 = ar.alloc_n<uint64_t>(nnz);
   int32_t *val = ar.alloc_n<int32_t>(nnz);
   int32_t *val2 = ar.alloc_n<int32_t>(nnz);
-  contract_keys(g, L.cl, cmap, bits, key, val, cx.sp.b, cx.dev, s);
+  contract_keys(g, L.cl, cmap, bits, key, val, cx.sp.b, cx.dev, s);  // cx.dev->count: self loops
   sort_pairs(ar, key, key2, val, val2, nnz, 2 * bits, s);
-  cx.pull();
-  const int64_t mvalid = nnz - cx.host->count;
-  int32_t *head = ar.alloc_n<int32_t>(mvalid + 1);
-  int32_t *pos = ar.alloc_n<int32_t>(mvalid + 1);
+  int32_t *head = ar.alloc_n<int32_t>(nnz + 1);
+  int32_t *pos = ar.alloc_n<int32_t>(nnz + 1);
   int32_t *rowcnt = ar.alloc_n<int32_t>((size_t)nc + 1);
   fill_i32(rowcnt, 0, (int64_t)nc + 1, s);
-  contract_heads(mvalid, key2, head, s);
-  scan_excl(ar, head, pos, mvalid, s);
-  contract_emit(mvalid, key2, val2, head, pos, bits, cadj, cw, rowcnt, s);
+  contract_heads(nnz, &cx.dev->count, key2, head, s);
+  scan_excl(ar, head, pos, nnz, s);
+  contract_emit(nnz, &cx.dev->count, key2, val2, head, pos, bits, cadj, cw, rowcnt, s);
   scan_excl_widen(ar, rowcnt, cxadj, (int64_t)nc + 1, s);
   PM_HIP(hipMemcpyAsync(&cx.host->j, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));

@@ -238,8 +238,10 @@ void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int3
 // int32[NCLS + 1]) the class offsets into it.
 void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
                  const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s);
+// One matching commit; the number of new pairs goes to st->count and, if
+// count_out is not null, to *count_out (device).
 void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
-                hipStream_t s);
+                int32_t *count_out, hipStream_t s);
 // Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched
 // vertices and pairs each group in id order.  Returns the vertices matched.
 // Synchronises the stream.
@@ -255,10 +257,13 @@ void coarse_vwgt(int32_t n, const int32_t *match, const int32_t *cmap, const int
 void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int bits,
                    uint64_t *key, int32_t *val, int64_t *stripes, Status *st,
                    hipStream_t s);   // st->count = arcs inside coarse vertices
-void contract_heads(int64_t m, const uint64_t *key, int32_t *head, hipStream_t s);
-void contract_emit(int64_t m, const uint64_t *key, const int32_t *val, const int32_t *head,
-                   const int32_t *pos, int bits, int32_t *cadj, int32_t *cw, int32_t *rowcnt,
-                   hipStream_t s);
+// Over the nnz sorted keys, of which the last *self (device) are the
+// self-loop sentinels.
+void contract_heads(int64_t nnz, const int32_t *self, const uint64_t *key, int32_t *head,
+                    hipStream_t s);
+void contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key, const int32_t *val,
+                   const int32_t *head, const int32_t *pos, int bits, int32_t *cadj, int32_t *cw,
+                   int32_t *rowcnt, hipStream_t s);
 void project(int32_t n, const int32_t *cmap, const int32_t *coarse, int32_t *fine,
              hipStream_t s);
 

@@ -130,6 +130,7 @@ constexpr int kWaveMaxDeg = 512;
 constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 constexpr int32_t kHemCompactMinN = 1 << 18;  // matching rounds tile only active vertices
 constexpr int32_t kRebCompactMinN = 1 << 19;  // rebalancing tiles only overloaded blocks
+constexpr int kHemRoundsPerRead = 4;  // matching rounds between status read-backs (small levels)
 
 // Process-wide launch parameters (pm_set_tuning); read at each call.
 struct TuningValues {
