@@ -172,3 +172,30 @@ def test_weight_overflow_rejected(pm):
     with pytest.raises(pm.PmError) as e:
         pm.pm_map(pm.DeviceGraph.from_host(g), (2,), (1,), 0.03, 1)
     assert e.value.code == pm.PM_EOVERFLOW
+
+
+@pytest.mark.parametrize("a,d", [((8, 32, 32), (1, 10, 100)),      # 2^13 codes, k = 8192
+                                 ((5, 30, 25), (1, 3, 9))])         # 13 code bits, k = 3750
+def test_largest_hierarchy(pm, pmo, a, d):
+    """The largest hierarchy the block codes allow (13 bits): histograms of
+    8192 entries, no per-wave slices; J, one label-propagation round and the
+    whole map against the oracle."""
+    import torch
+    g = gen.get("rgg14").graph()
+    k = int(np.prod(a))
+    dg = pm.DeviceGraph.from_host(g)
+    part = gen.random_mapping(g.n, k, 4)
+    pd = torch.from_numpy(part.astype(np.int32)).cuda()
+    say("largest hierarchy J", a)
+    assert pm.pm_comm_cost(dg, a, d, pd) == pmo.comm_cost(g, part, a, d)
+    say("largest hierarchy lp round", a)
+    lock = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+    p_h, l_h, t_h, g_h, m_h = pmo.lp_round(g, a, d, part, np.zeros(g.n, np.uint8))
+    t_d, g_d, m_d = pm.pm_lp_round(dg, a, d, pd, lock)
+    assert np.array_equal(host(g_d), g_h) and np.array_equal(host(m_d), m_h)
+    assert np.array_equal(host(pd), p_h)
+    say("largest hierarchy map", a)
+    rc_h, part_h, st_h = pmo.map_graph(g, a, d, 0.03, 1)
+    rc_d, part_d, st_d = pm.pm_map(dg, a, d, 0.03, 1)
+    assert rc_d == rc_h and st_d.j_final == st_h.j_final
+    assert np.array_equal(host(part_d), part_h)
