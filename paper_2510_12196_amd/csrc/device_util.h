@@ -186,13 +186,18 @@ __device__ __forceinline__ void atomic_add_any(int32_t *p, int64_t x) { atomicAd
 __device__ __forceinline__ void atomic_add_any(int64_t *p, int64_t x) {
   atomicAdd((unsigned long long *)p, (unsigned long long)x);
 }
-// For every lane with `has`, adds val to *addr(key); one atomic per distinct
-// key in the wave.  Every lane of the wave must call it (no lane may have
-// left the kernel).
+// For every lane with `has`, adds val to *addr(key).  The keys of the first
+// two leaders are summed over the wave (one atomic each: the common case of
+// neighbouring vertices in one block); lanes with any other key add on their
+// own, since a wave of many distinct keys would otherwise pay a wave-wide
+// sum per key.  Integer adds: the totals do not depend on the grouping.
+// Every lane of the wave must call it (no lane may have left the kernel).
 template <class AddrF>
 __device__ __forceinline__ void wave_keyed_add(bool has, uint32_t key, int64_t val, AddrF addr) {
   unsigned long long left = __ballot(has);
-  while (left) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    if (!left) return;
     const int leader = __ffsll((long long)left) - 1;
     const uint32_t lk = (uint32_t)__shfl((int32_t)key, leader, 64);
     const bool in = has && key == lk;
@@ -200,6 +205,7 @@ __device__ __forceinline__ void wave_keyed_add(bool has, uint32_t key, int64_t v
     if ((int)(threadIdx.x & 63) == leader && sum != 0) atomic_add_any(addr(lk), sum);
     left &= ~__ballot(in);
   }
+  if (((left >> (threadIdx.x & 63)) & 1ull) && val != 0) atomic_add_any(addr(key), val);
 }
 
 // ---- classed launches --------------------------------------------------------

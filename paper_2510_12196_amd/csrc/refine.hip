@@ -1360,26 +1360,12 @@ __device__ __forceinline__ void reb_big(const RebArgs &A, int32_t v, uint32_t *X
 
 // Degree 65..kWaveMaxDeg, one vertex per wave, histogram in the wave's LDS
 // slice (the block path without workgroup barriers).
-__device__ __forceinline__ void reb_w(const RebArgs &A, int local, uint32_t *X) {
-  int32_t v;
-  if (!w_vertex(A.cl, local, v)) return;
+// Selection from the scanned connectivity histogram Xw of source v (block
+// p) in this wave's LDS slice; lane 0 gets the bucket addition.
+__device__ __forceinline__ BwAdd reb_from_hist(const RebArgs &A, int32_t v, uint32_t p,
+                                               const uint32_t *Xw) {
   const int lane = threadIdx.x & 63;
-  const uint32_t p = (uint32_t)A.part[v];
-  if (!is_source(A, v, p)) {
-    if (lane == 0) reb_not_source(A, v);
-    return;
-  }
   const int32_t ncodes = 1 << A.h.bits;
-  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
-  for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
-  wave_lds_sync();
-  wave_arcs<4>(
-      A.g.xadj[v], A.g.xadj[v + 1],
-      [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
-      [&](int64_t, uint2 a) { atomicAdd(&Xw[a.x + 1], a.y); });
-  wave_lds_sync();
-  wave_scan_lds(Xw, ncodes + 1);
-  wave_lds_sync();
   const int64_t costp = A.jrb ? level_cost(A.h, Xw, p, ncodes) : 0;
   int64_t val = INT64_MIN;
   uint32_t b = 0xFFFFFFFFu;
@@ -1405,7 +1391,68 @@ __device__ __forceinline__ void reb_w(const RebArgs &A, int local, uint32_t *X) 
       reb_not_source(A, v);
     }
   }
+  return add;
+}
+
+// Degree 65..kWaveMaxDeg, one vertex per wave, histogram in the wave's LDS
+// slice (the block path without workgroup barriers).
+__device__ __forceinline__ void reb_w(const RebArgs &A, int local, uint32_t *X) {
+  int32_t v;
+  if (!w_vertex(A.cl, local, v)) return;
+  const int lane = threadIdx.x & 63;
+  const uint32_t p = (uint32_t)A.part[v];
+  if (!is_source(A, v, p)) {
+    if (lane == 0) reb_not_source(A, v);
+    return;
+  }
+  const int32_t ncodes = 1 << A.h.bits;
+  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
+  for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
+  wave_lds_sync();
+  wave_arcs<4>(
+      A.g.xadj[v], A.g.xadj[v + 1],
+      [&](int64_t e) { return make_uint2((uint32_t)A.part[A.g.adj[e]], (uint32_t)A.g.w[e]); },
+      [&](int64_t, uint2 a) { atomicAdd(&Xw[a.x + 1], a.y); });
+  wave_lds_sync();
+  wave_scan_lds(Xw, ncodes + 1);
+  wave_lds_sync();
+  const BwAdd add = reb_from_hist(A, v, p, Xw);
   bw_flush(A, add);
+}
+
+// Degree 33..64, one vertex per wave: the histogram instead of pairing every
+// arc with every other one (as lp1_wave).
+template <int V>
+__device__ __forceinline__ void reb_wave(const RebArgs &A, int local, uint32_t *X) {
+  const int32_t ncodes = 1 << A.h.bits;
+  uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
+  BwAdd add[V];
+  group_tiles<64, V>(
+      A.g.xadj, A.g.adj, A.cl, CLS_G64, local,
+      [&](int32_t v, bool &act) {
+        const uint32_t p = (uint32_t)A.part[v];
+        act = is_source(A, v, p);
+        return p;
+      },
+      [&](int32_t u, int64_t e) { return make_uint2((uint32_t)A.part[u], (uint32_t)A.g.w[e]); },
+      [&](int r, bool ok, int32_t v, uint32_t p, bool act, int, bool valid, uint2 a) {
+        if (!ok) return;
+        const int lane = threadIdx.x & 63;
+        if (!act) {
+          if (lane == 0) reb_not_source(A, v);
+          return;
+        }
+        for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
+        wave_lds_sync();
+        if (valid) atomicAdd(&Xw[a.x + 1], a.y);
+        wave_lds_sync();
+        wave_scan_lds(Xw, ncodes + 1);
+        wave_lds_sync();
+        add[r] = reb_from_hist(A, v, p, Xw);
+        wave_lds_sync();  // the slice is cleared again for the next vertex
+      });
+#pragma unroll
+  for (int r = 0; r < V; ++r) bw_flush(A, add[r]);
 }
 
 template <int V>
@@ -1435,7 +1482,10 @@ __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
     case CLS_G8: reb_group<8, V>(A, cls, local); break;
     case CLS_G16: reb_group<16, V>(A, cls, local); break;
     case CLS_G32: reb_group<32, V>(A, cls, local); break;
-    case CLS_G64: reb_group<64, V>(A, cls, local); break;
+    case CLS_G64:
+      if (A.whist) reb_wave<V>(A, local, X);
+      else reb_group<64, V>(A, cls, local);
+      break;
     default:  // as in k_lp_phase1
       if (cls == CLS_W && A.whist) reb_w(A, local, X);
       else reb_big(A, A.cl.list[A.cl.off[cls] + local], X, sc);
