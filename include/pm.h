@@ -328,7 +328,7 @@ typedef struct pm_map_job {
   double ms;               /* out: wall time of the instance                */
 } pm_map_job;
 
-/* Batched mapping (the batched workload of the survey's C4): the jobs are
+/* Batched mapping (many uneven task graphs at once): the jobs are
  * spread over `workers` host threads (0: 8), each with its own HIP stream and
  * scratch, so that the small kernels and host round trips of many instances
  * overlap on the device.  Jobs are started largest first.  `stream` is
