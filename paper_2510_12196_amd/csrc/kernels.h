@@ -142,7 +142,7 @@ void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 // With end != nullptr the commit's last workgroup runs the StepEnd epilogue
 // (end->w must be w, end->dj_stripes dj_stripes).
 constexpr int kWeightStripes = 32;
-int weight_stripes(const Hier &h);   // stripes in use for h (power of two)
+int weight_stripes(const Hier &h, int64_t n);   // stripes in use (power of two)
 int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,

@@ -1102,9 +1102,12 @@ __global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part,
 
 // Weight-delta stripes: at most kWeightStripes, and at most 8192 words in all
 // so that one workgroup folds them quickly.
-int weight_stripes(const Hier &h) {
+int weight_stripes(const Hier &h, int64_t n) {
+  // one stripe per 2048 vertices (the adds of a small graph's few
+  // workgroups hardly collide, and the step epilogue folds every stripe)
   int sc = kWeightStripes;
   while (sc > 1 && ((int64_t)sc << h.bits) > 8192) sc >>= 1;
+  while (sc > 1 && (int64_t)sc * 2048 > n) sc >>= 1;
   return sc;
 }
 
@@ -1121,7 +1124,7 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
-  const int nstripes = weight_stripes(h);
+  const int nstripes = weight_stripes(h, g.n);
   ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
   if (nwg > 0) {
