@@ -74,3 +74,23 @@ def test_autotune_batch_keeps_results(pm):
             assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n))
     finally:
         pm.set_tuning(**before)
+
+
+def test_batch_with_every_path_forced_equals_plain(pm):
+    """Concurrent jobs with the W class and both compactions forced on: every
+    batched result equals the plain run under the same launch parameters."""
+    members = gen.batch_members(32, log2_lo=10.0, log2_hi=13.0)
+    inst = [(pm.DeviceGraph.from_host(m.graph), m.a, m.d, m.eps, m.seed) for m in members]
+    say("batch with forced paths")
+    with pm.tuned(wave_min_count=1, hem_compact_min_n=1, reb_compact_min_n=1, group_v=2):
+        plain = [pm.pm_map(*x) for x in inst]
+        for rep in range(2):
+            res = pm.pm_map_batch(inst, workers=8)
+            for m, (rc, part, job), (rc_p, part_p, st_p) in zip(members, res, plain):
+                assert rc == rc_p and job.j_final == st_p.j_final, rep
+                assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n)), rep
+    # and the same mappings as with the defaults
+    for m, x, (rc_p, part_p, st_p) in zip(members, inst, plain):
+        rc, part, st = pm.pm_map(*x)
+        assert rc == rc_p and st.j_final == st_p.j_final
+        assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n))
