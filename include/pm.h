@@ -175,6 +175,14 @@ void pm_release(void);
  *                      vertices that must look again (default 2^18; >= 1)
  *   reb_compact_min_n  from this level size on, rebalancing tiles only the
  *                      vertices of overloaded blocks (default 2^19; >= 1)
+ *   contract_rows_min_nnz  from this many arcs on, a level may be contracted
+ *                      row by row (rows of at most 64 arcs merged in
+ *                      registers, of at most 4096 in LDS, one radix sort over
+ *                      the longer rows' arcs only) instead of by one radix
+ *                      sort over all arcs (default 2^20; >= 1)
+ *   contract_rows_long_pct  ... provided that coarse rows above 64 arcs hold
+ *                      at most this percentage of the level's arcs
+ *                      (default 12; 0..100)
  * pm_set_tuning returns PM_EINVAL (nothing changed) for values outside these
  * ranges.  Calls already running may see either setting. */
 typedef struct pm_tuning {
@@ -182,6 +190,8 @@ typedef struct pm_tuning {
   int32_t wave_min_count;
   int32_t hem_compact_min_n;
   int32_t reb_compact_min_n;
+  int32_t contract_rows_min_nnz;
+  int32_t contract_rows_long_pct;
 } pm_tuning;
 int pm_get_tuning(pm_tuning *out);
 int pm_set_tuning(const pm_tuning *t);
@@ -252,7 +262,9 @@ int pm_hem(const pm_graph *g, int64_t lmax, uint64_t seed, int32_t level,
  * loops dropped, parallel arcs fused with summed weights.  Outputs (device,
  * caller-allocated at the fine sizes): cmap int32[n], cxadj int64[n+1],
  * cadjncy int32[nnz], cadjwgt int32[nnz], cvwgt int32[n]; nc_out and
- * nnz_out are host.  Coarse rows come out sorted by neighbour id. */
+ * nnz_out are host.  Coarse rows come out sorted by neighbour id.
+ * match: device int32[n], the partner of every vertex, the vertex itself or
+ * -1 when unmatched; PM_EINVAL unless every partner points back. */
 int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap,
                 int64_t *cxadj, int32_t *cadjncy, int32_t *cadjwgt,
                 int32_t *cvwgt, int32_t *nc_out, int64_t *nnz_out,

@@ -179,7 +179,8 @@ def options(jet_c=None, j_rebalance: bool = False) -> PmOptions:
 
 class PmTuning(ctypes.Structure):
     _fields_ = [("group_v", ctypes.c_int32), ("wave_min_count", ctypes.c_int32),
-                ("hem_compact_min_n", ctypes.c_int32), ("reb_compact_min_n", ctypes.c_int32)]
+                ("hem_compact_min_n", ctypes.c_int32), ("reb_compact_min_n", ctypes.c_int32),
+                ("contract_rows_min_nnz", ctypes.c_int32), ("contract_rows_long_pct", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

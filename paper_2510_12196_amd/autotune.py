@@ -35,7 +35,8 @@ def sample_of(instances, count):
 def autotune_batch(instances, sample=64, workers=(4, 8, 16), cands=None, sync=None):
     """instances: list of (DeviceGraph, a, d, eps, seed).  Times pm_map_batch
     on a sample for every (tuning, workers) pair, sets the fastest tuning and
-    returns (tuning, workers, table) where table lists every timing."""
+    returns (tuning, workers, table): every launch parameter now in effect,
+    the worker count, and every timing."""
     cands = cands or candidates()
     sub = sample_of(instances, sample)
     old = get_tuning()
@@ -59,4 +60,4 @@ def autotune_batch(instances, sample=64, workers=(4, 8, 16), cands=None, sync=No
     finally:
         set_tuning(**old)
     set_tuning(**best[1])
-    return best[1], best[2], table
+    return get_tuning(), best[2], table

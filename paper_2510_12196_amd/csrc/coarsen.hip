@@ -341,6 +341,22 @@ void hem_finish(int32_t n, int32_t *match, int32_t *leader, hipStream_t s) {
   PM_LAUNCH_CHECK();
 }
 
+// A matching as the contraction takes it: every entry is -1 (unmatched), the
+// vertex itself, or a partner that points back.
+__global__ void k_check_match(int32_t n, const int32_t *match, int32_t *bad) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t m = match[v];
+  const bool ok = m == -1 || m == v || (m >= 0 && m < n && match[m] == v);
+  if (!ok) atomicOr(bad, 1);
+}
+void check_match(int32_t n, const int32_t *match, int32_t *bad, hipStream_t s) {
+  PM_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_check_match, dim3(grid_for(n)), dim3(kThreads), 0, s, n, match, bad);
+  PM_LAUNCH_CHECK();
+}
+
 // ===========================================================================
 // Coarse numbering: coarse id = rank of the pair's smaller member.
 // `rank` holds, for every leader, the number of leaders before it.
@@ -523,6 +539,423 @@ void contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key, const 
   if (nnz <= 0) return;
   hipLaunchKernelGGL(k_contract_emit, dim3(grid_for(nnz)), dim3(kThreads), 0, s, nnz, self, key,
                      val, head, pos, bits, cadj, cw, rowcnt);
+  PM_LAUNCH_CHECK();
+}
+
+// ===========================================================================
+// Row-local contraction (large levels).  Coarse row c = {v, M(v)} has at most
+// ub(c) = deg(v) + deg(M(v)) arcs before merging.  The arcs of every row are
+// first staged at that upper-bound offset, as (coarse neighbour, weight), with
+// self loops marked.  A row with ub <= 64 is then sorted, merged and
+// compacted in place by G lanes in registers (bitonic network, segmented sum
+// of equal neighbours), a row with ub <= 4096 the same way by a workgroup in
+// LDS; longer rows go through one global radix sort keyed by (row,
+// neighbour) over their arcs only.  The merged lengths give the
+// coarse offsets, and a last pass copies every row to its place.  The result
+// is the same CSR as the global sort over all arcs: per row the distinct
+// coarse neighbours other than itself, ascending, with summed weights.
+// ===========================================================================
+constexpr uint32_t kStageSelf = 0xFFFFFFFFu;
+constexpr int kRowMaxG = 64;      // rows up to this bound: lane groups
+constexpr int kRowMaxLds = 4096;  // rows up to this bound: a workgroup in LDS
+
+__global__ __launch_bounds__(kThreads) void k_contract_rowub(int32_t n, const int64_t *xadj,
+                                                             const int32_t *match,
+                                                             const int32_t *cmap, int32_t *ub,
+                                                             int32_t *ubig, int64_t *above64) {
+  __shared__ BlockScratch sc;
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t a = 0;
+  if (v < n) {
+    const int32_t m = match[v];
+    if (m >= v) {  // the row is written by its leader, the smaller member
+      const int64_t d = (xadj[v + 1] - xadj[v]) + (m != v ? xadj[m + 1] - xadj[m] : 0);
+      const int32_t c = cmap[v];
+      ub[c] = (int32_t)d;
+      ubig[c] = d > kRowMaxLds ? (int32_t)d : 0;
+      a = d > kRowMaxG ? d : 0;
+    }
+  }
+  a = block_sum64(a, sc);
+  if (threadIdx.x == 0 && a) atomicAdd((unsigned long long *)above64, (unsigned long long)a);
+}
+
+void contract_rowub(const DGraph &g, const int32_t *match, const int32_t *cmap, int32_t *ub,
+                    int32_t *ubig, int64_t *above64, hipStream_t s) {
+  fill_i64(above64, 0, 1, s);
+  if (g.n <= 0) return;
+  hipLaunchKernelGGL(k_contract_rowub, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, g.xadj,
+                     match, cmap, ub, ubig, above64);
+  PM_LAUNCH_CHECK();
+}
+
+struct StageArgs {
+  DGraph g;
+  Classes cl;
+  const int32_t *match;
+  const int32_t *cmap;
+  const int64_t *uxadj;
+  uint32_t *scu;
+  int32_t *sw;
+};
+
+// first staged slot of fine vertex v: the leader's arcs come first
+__device__ __forceinline__ int64_t stage_base(const StageArgs &A, int32_t v) {
+  const int32_t m = A.match[v];
+  const int64_t b = A.uxadj[A.cmap[v]];
+  return m < v ? b + (A.g.xadj[m + 1] - A.g.xadj[m]) : b;
+}
+
+__device__ __forceinline__ void stage_arc(const StageArgs &A, uint32_t cv, int64_t dst, int32_t cu,
+                                          int32_t w) {
+  A.scu[dst] = (uint32_t)cu == cv ? kStageSelf : (uint32_t)cu;
+  A.sw[dst] = w;
+}
+
+__global__ __launch_bounds__(kThreads) void k_contract_stage(StageArgs A) {
+  const int blk = blockIdx.x;
+  const int cls = find_class(A.cl, blk);
+  const int local = blk - A.cl.wg[cls];
+  int32_t v;
+  switch (cls) {
+    case CLS_ISO: break;
+    case CLS_G8:
+    case CLS_G16:
+    case CLS_G32:
+    case CLS_G64: {
+      const int G = class_group(cls);
+      const int idx = local * (kThreads / G) + (int)threadIdx.x / G;
+      if (idx >= A.cl.off[cls + 1] - A.cl.off[cls]) break;
+      v = A.cl.list[A.cl.off[cls] + idx];
+      const int lane = threadIdx.x % G;
+      const int64_t beg = A.g.xadj[v];
+      if (beg + lane >= A.g.xadj[v + 1]) break;
+      const int64_t e = beg + lane;
+      stage_arc(A, (uint32_t)A.cmap[v], stage_base(A, v) + lane, A.cmap[A.g.adj[e]], A.g.w[e]);
+      break;
+    }
+    case CLS_W: {
+      if (!w_vertex(A.cl, local, v)) break;
+      const uint32_t cv = (uint32_t)A.cmap[v];
+      const int64_t beg = A.g.xadj[v];
+      const int64_t base = stage_base(A, v) - beg;
+      wave_arcs<4>(
+          beg, A.g.xadj[v + 1],
+          [&](int64_t e) { return make_int2(A.cmap[A.g.adj[e]], A.g.w[e]); },
+          [&](int64_t e, int2 a) { stage_arc(A, cv, base + e, a.x, a.y); });
+      break;
+    }
+    default: {
+      v = A.cl.list[A.cl.off[CLS_BIG] + local];
+      const uint32_t cv = (uint32_t)A.cmap[v];
+      const int64_t beg = A.g.xadj[v];
+      const int64_t base = stage_base(A, v) - beg;
+      big_arcs(
+          beg, A.g.xadj[v + 1],
+          [&](int64_t e) { return make_int2(A.cmap[A.g.adj[e]], A.g.w[e]); },
+          [&](int64_t e, int2 a) { stage_arc(A, cv, base + e, a.x, a.y); });
+      break;
+    }
+  }
+}
+
+void contract_stage(const DGraph &g, const Classes &cl, const int32_t *match, const int32_t *cmap,
+                    const int64_t *uxadj, uint32_t *scu, int32_t *sw, hipStream_t s) {
+  const unsigned nwg = classed_grid(cl);
+  if (nwg == 0 || g.nnz <= 0) return;
+  StageArgs A{g, cl, match, cmap, uxadj, scu, sw};
+  hipLaunchKernelGGL(k_contract_stage, dim3(nwg), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+}
+
+struct RowArgs {
+  Classes rc;           // coarse rows classed by ub
+  const int64_t *uxadj;
+  uint32_t *scu;
+  int32_t *sw;
+  int32_t *rowcnt;
+};
+
+// One row of at most G staged arcs on G lanes: sort by neighbour, add the
+// weights of equal neighbours, write the distinct ones back from the row's
+// first slot, and its length to rowcnt.
+template <int G>
+__device__ __forceinline__ void merge_row(const RowArgs &A, int cls, int local) {
+  int32_t c;
+  if (!group_vertex<G>(A.rc, cls, local, c)) return;
+  const int lane = threadIdx.x % G;
+  const int64_t beg = A.uxadj[c];
+  const int ub = (int)(A.uxadj[c + 1] - beg);
+  uint32_t key = kStageSelf;
+  int32_t w = 0;
+  if (lane < ub) {
+    key = A.scu[beg + lane];
+    w = A.sw[beg + lane];
+  }
+#pragma unroll
+  for (int k = 2; k <= G; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t pk = (uint32_t)__shfl_xor((int32_t)key, j, G);
+      const int32_t pw = __shfl_xor(w, j, G);
+      const bool up = (lane & k) == 0, low = (lane & j) == 0;
+      if (low == up ? pk < key : pk > key) {
+        key = pk;
+        w = pw;
+      }
+    }
+  }
+  // suffix sums within runs of equal keys: the run's first lane gets its total
+  int32_t sum = w;
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    const uint32_t nk = (uint32_t)__shfl_down((int32_t)key, d, G);
+    const int32_t ns = __shfl_down(sum, d, G);
+    if (lane + d < G && nk == key) sum += ns;
+  }
+  const uint32_t pk = (uint32_t)__shfl_up((int32_t)key, 1, G);
+  const bool head = key != kStageSelf && (lane == 0 || pk != key);
+  const int wl = threadIdx.x & 63;
+  const uint64_t gmask = G == 64 ? ~0ull : (((1ull << G) - 1ull) << (wl & ~(G - 1)));
+  const uint64_t heads = __ballot(head) & gmask;
+  if (head) {
+    const int r = __popcll(heads & ((1ull << wl) - 1ull));
+    A.scu[beg + r] = key;
+    A.sw[beg + r] = sum;
+  }
+  if (lane == 0) A.rowcnt[c] = __popcll(heads);
+}
+
+__global__ __launch_bounds__(kThreads) void k_contract_rows(RowArgs A) {
+  const int blk = blockIdx.x;
+  const int cls = find_class(A.rc, blk);
+  const int local = blk - A.rc.wg[cls];
+  switch (cls) {
+    case CLS_ISO:
+      iso_tiles<1>(A.rc, local, [&](int32_t c) { A.rowcnt[c] = 0; });
+      break;
+    case CLS_G8: merge_row<8>(A, cls, local); break;
+    case CLS_G16: merge_row<16>(A, cls, local); break;
+    case CLS_G32: merge_row<32>(A, cls, local); break;
+    case CLS_G64: merge_row<64>(A, cls, local); break;
+    default: break;  // W and BIG rows: the sorted path
+  }
+}
+
+void contract_rows(const Classes &rc, const int64_t *uxadj, uint32_t *scu, int32_t *sw,
+                   int32_t *rowcnt, hipStream_t s) {
+  const unsigned nwg = classed_grid(rc);
+  if (nwg == 0) return;
+  RowArgs A{rc, uxadj, scu, sw, rowcnt};
+  hipLaunchKernelGGL(k_contract_rows, dim3(nwg), dim3(kThreads), 0, s, A);
+  PM_LAUNCH_CHECK();
+}
+
+// Rows with 64 < ub <= 4096: one workgroup per row sorts (neighbour, weight)
+// in LDS with a bitonic network over the next power of two, then writes the
+// distinct neighbours in order with their summed weights from the row's
+// first slot.  Longer rows are left to the radix-sort path.
+struct LdsRow {
+  uint32_t key[kRowMaxLds];
+  int32_t w[kRowMaxLds];
+};
+
+__global__ __launch_bounds__(kThreads) void k_contract_lds_rows(const int32_t *list,
+                                                                const int64_t *uxadj,
+                                                                uint32_t *scu, int32_t *sw,
+                                                                int32_t *rowcnt) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  LdsRow &R = *reinterpret_cast<LdsRow *>(lds_raw);
+  __shared__ BlockScratch sc;
+  const int32_t c = list[blockIdx.x];
+  const int64_t beg = uxadj[c];
+  const int ub = (int)(uxadj[c + 1] - beg);
+  if (ub > kRowMaxLds) return;  // workgroup-uniform
+  int N = 1;
+  while (N < ub) N <<= 1;
+  for (int i = threadIdx.x; i < N; i += kThreads) {
+    R.key[i] = i < ub ? scu[beg + i] : kStageSelf;
+    R.w[i] = i < ub ? sw[beg + i] : 0;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = threadIdx.x; t < (N >> 1); t += kThreads) {
+        const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int p = i + j;
+        const uint32_t a = R.key[i], b = R.key[p];
+        if ((a > b) == ((i & k) == 0)) {
+          R.key[i] = b;
+          R.key[p] = a;
+          const int32_t x = R.w[i];
+          R.w[i] = R.w[p];
+          R.w[p] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // each thread takes a contiguous chunk: count its run heads, scan, write
+  const int per = (N + kThreads - 1) / kThreads;
+  const int lo = threadIdx.x * per < N ? threadIdx.x * per : N;
+  const int hi = lo + per < N ? lo + per : N;
+  uint32_t cnt = 0;
+  for (int i = lo; i < hi; ++i)
+    cnt += R.key[i] != kStageSelf && (i == 0 || R.key[i] != R.key[i - 1]) ? 1u : 0u;
+  uint32_t r = block_excl_scan(cnt, sc);
+  const uint32_t total = sc.u[0] + sc.u[1] + sc.u[2] + sc.u[3];
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t k = R.key[i];
+    if (k == kStageSelf || (i > 0 && R.key[i - 1] == k)) continue;
+    int64_t sum = 0;
+    for (int j = i; j < N && R.key[j] == k; ++j) sum += R.w[j];
+    scu[beg + r] = k;
+    sw[beg + r] = (int32_t)sum;
+    ++r;
+  }
+  if (threadIdx.x == 0) rowcnt[c] = (int32_t)total;
+}
+
+void contract_lds_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, uint32_t *scu,
+                       int32_t *sw, int32_t *rowcnt, hipStream_t s) {
+  if (nl <= 0) return;
+  hipLaunchKernelGGL(k_contract_lds_rows, dim3((unsigned)nl), dim3(kThreads), sizeof(LdsRow), s,
+                     list, uxadj, scu, sw, rowcnt);
+  PM_LAUNCH_CHECK();
+}
+
+// Rows above 4096: keys (row << bits | neighbour) at the row's place among
+// those rows (rstart: exclusive prefix of their ub in row order; rows of the
+// list with no place are skipped), self loops keyed with the all-ones
+// neighbour so that they sort last in their row.
+__global__ __launch_bounds__(kThreads) void k_long_keys(const int32_t *list,
+                                                        const int64_t *uxadj,
+                                                        const int64_t *rstart,
+                                                        const uint32_t *scu, const int32_t *sw,
+                                                        int bits, uint64_t *key, int32_t *val) {
+  const int32_t c = list[blockIdx.x];
+  const int64_t beg = uxadj[c], dst = rstart[c], ub = rstart[c + 1] - dst;  // 0: LDS row
+  const uint64_t mask = (1ull << bits) - 1ull, row = (uint64_t)c << bits;
+  for (int64_t j = threadIdx.x; j < ub; j += kThreads) {
+    const uint32_t x = scu[beg + j];
+    key[dst + j] = row | (x == kStageSelf ? mask : (uint64_t)x);
+    val[dst + j] = sw[beg + j];
+  }
+}
+
+__global__ void k_long_heads(int64_t m, const uint64_t *key, int bits, int32_t *head) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > m) return;
+  const uint64_t mask = (1ull << bits) - 1ull;
+  head[i] = i < m && (key[i] & mask) != mask && (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+// Every run head writes its merged arc at its rank within the row, from the
+// row's first staged slot.
+__global__ void k_long_emit(int64_t m, const uint64_t *key, const int32_t *val,
+                            const int32_t *head, const int32_t *pos, const int64_t *rstart,
+                            const int64_t *uxadj, int bits, uint32_t *scu, int32_t *sw) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m || !head[i]) return;
+  const uint64_t k = key[i];
+  int64_t sum = 0;
+  for (int64_t j = i; j < m && key[j] == k; ++j) sum += val[j];
+  const int32_t c = (int32_t)(k >> bits);
+  const int64_t o = uxadj[c] + (pos[i] - pos[rstart[c]]);
+  scu[o] = (uint32_t)(k & ((1ull << bits) - 1ull));
+  sw[o] = (int32_t)sum;
+}
+
+__global__ void k_long_count(int32_t nl, const int32_t *list, const int64_t *rstart,
+                             const int32_t *pos, int32_t *rowcnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl) return;
+  const int32_t c = list[i];
+  if (rstart[c + 1] > rstart[c]) rowcnt[c] = pos[rstart[c + 1]] - pos[rstart[c]];
+}
+
+void contract_long_rows(Arena &ar, const int32_t *list, int32_t nl, int64_t m, int32_t nc,
+                        const int64_t *uxadj, const int64_t *rstart, uint32_t *scu, int32_t *sw,
+                        int32_t *rowcnt, hipStream_t s) {
+  if (nl <= 0 || m <= 0) return;
+  int bits = 1;
+  while (bits < 31 && (int64_t(1) << bits) <= (int64_t)nc) ++bits;  // 2^bits - 1 >= nc
+  const size_t mk = ar.mark();
+  uint64_t *key = ar.alloc_n<uint64_t>(m);
+  uint64_t *key2 = ar.alloc_n<uint64_t>(m);
+  int32_t *val = ar.alloc_n<int32_t>(m);
+  int32_t *val2 = ar.alloc_n<int32_t>(m);
+  int32_t *head = ar.alloc_n<int32_t>(m + 1);
+  int32_t *pos = ar.alloc_n<int32_t>(m + 1);
+  hipLaunchKernelGGL(k_long_keys, dim3((unsigned)nl), dim3(kThreads), 0, s, list, uxadj, rstart,
+                     scu, sw, bits, key, val);
+  PM_LAUNCH_CHECK();
+  sort_pairs(ar, key, key2, val, val2, m, 2 * bits, s);
+  hipLaunchKernelGGL(k_long_heads, dim3(grid_for(m + 1)), dim3(kThreads), 0, s, m, key2, bits,
+                     head);
+  PM_LAUNCH_CHECK();
+  scan_excl(ar, head, pos, m + 1, s);
+  hipLaunchKernelGGL(k_long_emit, dim3(grid_for(m)), dim3(kThreads), 0, s, m, key2, val2, head,
+                     pos, rstart, uxadj, bits, scu, sw);
+  PM_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_long_count, dim3(grid_for(nl)), dim3(kThreads), 0, s, nl, list, rstart,
+                     pos, rowcnt);
+  PM_LAUNCH_CHECK();
+  ar.rewind(mk);
+}
+
+struct CopyArgs {
+  Classes rc;
+  const int64_t *uxadj;
+  const int64_t *cxadj;
+  const uint32_t *scu;
+  const int32_t *sw;
+  int32_t *cadj;
+  int32_t *cw;
+};
+
+__device__ __forceinline__ void copy_row(const CopyArgs &A, int32_t c, int first, int step) {
+  const int64_t src = A.uxadj[c], dst = A.cxadj[c];
+  const int64_t len = A.cxadj[c + 1] - dst;
+  for (int64_t j = first; j < len; j += step) {
+    A.cadj[dst + j] = (int32_t)A.scu[src + j];
+    A.cw[dst + j] = A.sw[src + j];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_contract_copy(CopyArgs A) {
+  const int blk = blockIdx.x;
+  const int cls = find_class(A.rc, blk);
+  const int local = blk - A.rc.wg[cls];
+  int32_t c;
+  switch (cls) {
+    case CLS_ISO: break;
+    case CLS_G8:
+    case CLS_G16:
+    case CLS_G32:
+    case CLS_G64: {
+      const int G = class_group(cls);
+      const int idx = local * (kThreads / G) + (int)threadIdx.x / G;
+      if (idx >= A.rc.off[cls + 1] - A.rc.off[cls]) break;
+      copy_row(A, A.rc.list[A.rc.off[cls] + idx], threadIdx.x % G, G);
+      break;
+    }
+    case CLS_W:
+      if (w_vertex(A.rc, local, c)) copy_row(A, c, threadIdx.x & 63, 64);
+      break;
+    default:
+      copy_row(A, A.rc.list[A.rc.off[CLS_BIG] + local], threadIdx.x, kThreads);
+      break;
+  }
+}
+
+void contract_copy(const Classes &rc, const int64_t *uxadj, const int64_t *cxadj,
+                   const uint32_t *scu, const int32_t *sw, int32_t *cadj, int32_t *cw,
+                   hipStream_t s) {
+  const unsigned nwg = classed_grid(rc);
+  if (nwg == 0) return;
+  CopyArgs A{rc, uxadj, cxadj, scu, sw, cadj, cw};
+  hipLaunchKernelGGL(k_contract_copy, dim3(nwg), dim3(kThreads), 0, s, A);
   PM_LAUNCH_CHECK();
 }
 

@@ -375,14 +375,13 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
 }
 
 // Coarse numbering + contraction into pre-allocated coarse arrays.
-static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap, int32_t nc,
-                         int64_t *cxadj, int32_t *cadj, int32_t *cw, int32_t *cvwgt,
-                         int64_t *nnz_out) {
+// Contraction by one radix sort of all arcs keyed by (coarse row, coarse
+// neighbour): runs of equal keys merge, self loops (keyed all-ones) drop out.
+static void run_contract_sorted(Ctx &cx, const Level &L, int32_t *cmap, int32_t nc,
+                                int64_t *cxadj, int32_t *cadj, int32_t *cw, int64_t *nnz_out) {
   const DGraph &g = L.g;
   hipStream_t s = cx.s;
   Arena &ar = cx.ar;
-  (void)match;
-  coarse_vwgt(g.n, match, cmap, g.c, cvwgt, s);
   const size_t m = ar.mark();
   const int64_t nnz = g.nnz;
   const int bits = bitlen((uint64_t)(nc > 1 ? nc - 1 : 1));
@@ -403,6 +402,69 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
   PM_HIP(hipMemcpyAsync(&cx.host->j, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PM_HIP(hipStreamSynchronize(s));
   *nnz_out = cx.host->j;
+  ar.rewind(m);
+}
+
+static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap, int32_t nc,
+                         int64_t *cxadj, int32_t *cadj, int32_t *cw, int32_t *cvwgt,
+                         int64_t *nnz_out) {
+  const DGraph &g = L.g;
+  hipStream_t s = cx.s;
+  Arena &ar = cx.ar;
+  coarse_vwgt(g.n, match, cmap, g.c, cvwgt, s);
+  const size_t m = ar.mark();
+  const int64_t nnz = g.nnz;
+  if (nnz > 0 && nnz >= tuning().contract_rows_min_nnz) {
+    // row-local path: stage every coarse row at its upper-bound offset, merge
+    // rows of up to 64 arcs in registers and up to 4096 in LDS, and sort only
+    // the arcs of longer rows.  It pays off while rows above 64 hold a small
+    // share of the arcs (the LDS merge of many such rows is slower than one
+    // radix sort over all arcs); above that share the level takes the sort.
+    int32_t *ub = ar.alloc_n<int32_t>((size_t)nc + 1);
+    int32_t *ubig = ar.alloc_n<int32_t>((size_t)nc + 1);
+    int64_t *uxadj = ar.alloc_n<int64_t>((size_t)nc + 1);
+    int64_t *rstart = ar.alloc_n<int64_t>((size_t)nc + 1);
+    int64_t *above64 = ar.alloc_n<int64_t>(1);
+    fill_i32(ub + nc, 0, 1, s);
+    fill_i32(ubig + nc, 0, 1, s);
+    contract_rowub(g, match, cmap, ub, ubig, above64, s);
+    int64_t *hb = reinterpret_cast<int64_t *>(cx.aux());
+    PM_HIP(hipMemcpyAsync(hb, above64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    if (hb[0] * 100 > nnz * (int64_t)tuning().contract_rows_long_pct) {
+      ar.rewind(m);
+      run_contract_sorted(cx, L, cmap, nc, cxadj, cadj, cw, nnz_out);
+      return;
+    }
+    scan_excl_widen(ar, ub, uxadj, (int64_t)nc + 1, s);
+    scan_excl_widen(ar, ubig, rstart, (int64_t)nc + 1, s);
+    int64_t *long_arcs = hb + 1;
+    PM_HIP(hipMemcpyAsync(long_arcs, rstart + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    uint32_t *scu = ar.alloc_n<uint32_t>(nnz);
+    int32_t *sw = ar.alloc_n<int32_t>(nnz);
+    contract_stage(g, L.cl, match, cmap, uxadj, scu, sw, s);
+    int32_t *rlist = ar.alloc_n<int32_t>((size_t)nc);
+    DGraph rg{};
+    rg.n = nc;
+    rg.xadj = uxadj;
+    const Classes rc = build_classes(ar, rg, rlist, cx.dev, cx.host, s);  // synchronises
+    const int64_t lm = *long_arcs;
+    int32_t *rowcnt = ar.alloc_n<int32_t>((size_t)nc + 1);
+    fill_i32(rowcnt + nc, 0, 1, s);
+    contract_rows(rc, uxadj, scu, sw, rowcnt, s);
+    const int32_t *llist = rc.list + rc.off[CLS_BIG];  // rows above 64 (BIG, then W)
+    const int32_t nl = rc.off[CLS_W + 1] - rc.off[CLS_BIG];
+    contract_lds_rows(llist, nl, uxadj, scu, sw, rowcnt, s);
+    contract_long_rows(ar, llist, nl, lm, nc, uxadj, rstart, scu, sw, rowcnt, s);
+    scan_excl_widen(ar, rowcnt, cxadj, (int64_t)nc + 1, s);
+    contract_copy(rc, uxadj, cxadj, scu, sw, cadj, cw, s);
+    PM_HIP(hipMemcpyAsync(&cx.host->j, cxadj + nc, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PM_HIP(hipStreamSynchronize(s));
+    *nnz_out = cx.host->j;
+    ar.rewind(m);
+    return;
+  }
+  run_contract_sorted(cx, L, cmap, nc, cxadj, cadj, cw, nnz_out);
   ar.rewind(m);
 }
 
@@ -716,6 +778,9 @@ int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap, int64_t 
     L.g = dg;
     L.list = ar.alloc_n<int32_t>(dg.n);
     L.cl = build_classes(ar, dg, L.list, cx.dev, cx.host, s);
+    check_match(dg.n, match, &cx.dev->count, s);
+    cx.pull();
+    if (cx.host->count) throw Error(PM_EINVAL, "match is not a matching of the vertices");
     int32_t *m = ar.alloc_n<int32_t>(dg.n);
     if (dg.n) PM_HIP(hipMemcpyAsync(m, match, sizeof(int32_t) * dg.n, hipMemcpyDeviceToDevice, s));
     const int32_t nc = run_coarse_ids(cx, dg.n, m, cmap);

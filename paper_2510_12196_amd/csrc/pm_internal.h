@@ -130,11 +130,14 @@ constexpr int kWaveMaxDeg = 512;
 constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 constexpr int32_t kHemCompactMinN = 1 << 18;  // matching rounds tile only active vertices
 constexpr int32_t kRebCompactMinN = 1 << 19;  // rebalancing tiles only overloaded blocks
+constexpr int32_t kContractRowsMinNnz = 1 << 20;  // row-local contraction from this many arcs
+constexpr int32_t kContractRowsLongPct = 12;      // ... while rows above 64 hold <= 12 % of them
 constexpr int kHemRoundsPerRead = 4;  // matching rounds between status read-backs (small levels)
 
 // Process-wide launch parameters (pm_set_tuning); read at each call.
 struct TuningValues {
-  int32_t group_v, wave_min_count, hem_compact_min_n, reb_compact_min_n;
+  int32_t group_v, wave_min_count, hem_compact_min_n, reb_compact_min_n, contract_rows_min_nnz,
+      contract_rows_long_pct;
 };
 TuningValues tuning();
 void set_tuning(const TuningValues &t);

@@ -7,7 +7,8 @@ draws): the oracle cannot finish the whole map in test time, so the test
 checks J and the block weights of the GPU mapping with the oracle's plain
 definitions, the matching and contraction invariants at full size, and the
 first-filter results of a label-propagation round on a sample of vertices,
-each computed one by one with the oracle's equation-(1) gain.
+each computed one by one with the oracle's equation-(1) gain; its two
+contraction paths must also give the same coarse graph.
 """
 import sys
 
@@ -130,6 +131,25 @@ def test_rmat22_matching_and_contraction_invariants(pm, pmo, rmat22):
     # coarse vertex weights are the member sums
     assert np.array_equal(np.bincount(cmap, weights=g.vwgt, minlength=nc).astype(np.int64),
                           cv.astype(np.int64))
+
+
+def test_rmat22_contraction_paths_agree(pm, pmo, rmat22):
+    """Row-local contraction forced on (rows up to 4096 arcs merged in
+    registers or LDS, longer ones sorted) equals the contraction by one
+    radix sort over all arcs, at full size."""
+    w, g = rmat22
+    dg = pm.DeviceGraph.from_host(g)
+    lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
+    match_d, _ = pm.pm_hem(dg, lm, 1, level=0)
+    say("rmat22 contraction, row-local path")
+    with pm.tuned(contract_rows_min_nnz=1, contract_rows_long_pct=100):
+        cmap_a, ga = pm.pm_contract(dg, match_d)
+    say("rmat22 contraction, sorted path")
+    with pm.tuned(contract_rows_min_nnz=2**31 - 1):
+        cmap_b, gb = pm.pm_contract(dg, match_d)
+    for x, y in ((cmap_a, cmap_b), (ga.xadj, gb.xadj), (ga.adjncy, gb.adjncy),
+                 (ga.adjwgt, gb.adjwgt), (ga.vwgt, gb.vwgt)):
+        assert bool((x == y).all())
 
 
 def test_rmat22_lp_round_sampled(pm, pmo, rmat22):

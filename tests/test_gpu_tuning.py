@@ -31,7 +31,8 @@ def host(x, n):
 def test_invalid_tuning_is_refused(pm):
     before = pm.get_tuning()
     for bad in ({"group_v": 3}, {"wave_min_count": 0}, {"hem_compact_min_n": -1},
-                {"reb_compact_min_n": 0}):
+                {"reb_compact_min_n": 0}, {"contract_rows_min_nnz": 0},
+                {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101}):
         with pytest.raises(pm.PmError) as e:
             pm.set_tuning(**bad)
         assert e.value.code == pm.PM_EINVAL
@@ -46,7 +47,8 @@ def test_results_do_not_depend_on_tuning(pm, name):
     rc0, part0, st0 = pm.pm_map(dg, w.a, w.d, w.eps, 3)
     ref = host(part0, dg.n).copy()
     for c in candidates() + [{"wave_min_count": 1, "hem_compact_min_n": 1,
-                              "reb_compact_min_n": 1}]:
+                              "reb_compact_min_n": 1, "contract_rows_min_nnz": 1,
+                              "contract_rows_long_pct": 100}]:
         say("tuning", name, c)
         with pm.tuned(**c):
             rc, part, st = pm.pm_map(dg, w.a, w.d, w.eps, 3)
@@ -77,12 +79,14 @@ def test_autotune_batch_keeps_results(pm):
 
 
 def test_batch_with_every_path_forced_equals_plain(pm):
-    """Concurrent jobs with the W class and both compactions forced on: every
+    """Concurrent jobs with the W class, both compactions and the row-local
+    contraction forced on: every
     batched result equals the plain run under the same launch parameters."""
     members = gen.batch_members(32, log2_lo=10.0, log2_hi=13.0)
     inst = [(pm.DeviceGraph.from_host(m.graph), m.a, m.d, m.eps, m.seed) for m in members]
     say("batch with forced paths")
-    with pm.tuned(wave_min_count=1, hem_compact_min_n=1, reb_compact_min_n=1, group_v=2):
+    with pm.tuned(wave_min_count=1, hem_compact_min_n=1, reb_compact_min_n=1, group_v=2,
+                  contract_rows_min_nnz=1, contract_rows_long_pct=100):
         plain = [pm.pm_map(*x) for x in inst]
         for rep in range(2):
             res = pm.pm_map_batch(inst, workers=8)

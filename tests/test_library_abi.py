@@ -73,4 +73,4 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 def test_tuning_struct_layout():
     import paper_2510_12196_amd as pm
-    assert ctypes.sizeof(pm.PmTuning) == 16
+    assert ctypes.sizeof(pm.PmTuning) == 24
