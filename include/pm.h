@@ -176,13 +176,13 @@ void pm_release(void);
  *   reb_compact_min_n  from this level size on, rebalancing tiles only the
  *                      vertices of overloaded blocks (default 2^19; >= 1)
  *   contract_rows_min_nnz  from this many arcs on, a level may be contracted
- *                      row by row (rows of at most 64 arcs merged in
- *                      registers, of at most 4096 in LDS, one radix sort over
+ *                      row by row (rows of at most 512 arcs merged in
+ *                      registers, of at most 2048 in LDS, one radix sort over
  *                      the longer rows' arcs only) instead of by one radix
  *                      sort over all arcs (default 2^20; >= 1)
  *   contract_rows_long_pct  ... provided that coarse rows above 64 arcs hold
  *                      at most this percentage of the level's arcs
- *                      (default 12; 0..100)
+ *                      (default 100; 0..100)
  * pm_set_tuning returns PM_EINVAL (nothing changed) for values outside these
  * ranges.  Calls already running may see either setting. */
 typedef struct pm_tuning {

@@ -548,16 +548,18 @@ void contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key, const 
 // first staged at that upper-bound offset, as (coarse neighbour, weight), with
 // self loops marked.  A row with ub <= 64 is then sorted, merged and
 // compacted in place by G lanes in registers (bitonic network, segmented sum
-// of equal neighbours), a row with ub <= 4096 the same way by a workgroup in
-// LDS; longer rows go through one global radix sort keyed by (row,
-// neighbour) over their arcs only.  The merged lengths give the
+// of equal neighbours), a row with ub <= 512 by one wave holding up to eight
+// arcs per lane, a row with ub <= 2048 by a workgroup in LDS; longer rows go
+// through one global radix sort keyed by (row, neighbour) over their arcs
+// only.  The merged lengths give the
 // coarse offsets, and a last pass copies every row to its place.  The result
 // is the same CSR as the global sort over all arcs: per row the distinct
 // coarse neighbours other than itself, ascending, with summed weights.
 // ===========================================================================
 constexpr uint32_t kStageSelf = 0xFFFFFFFFu;
 constexpr int kRowMaxG = 64;      // rows up to this bound: lane groups
-constexpr int kRowMaxLds = 4096;  // rows up to this bound: a workgroup in LDS
+constexpr int kRowMaxWave = 512;  // ... one wave, eight arcs per lane in registers
+constexpr int kRowMaxLds = 2048;  // ... a workgroup in LDS
 
 __global__ __launch_bounds__(kThreads) void k_contract_rowub(int32_t n, const int64_t *xadj,
                                                              const int32_t *match,
@@ -751,28 +753,129 @@ void contract_rows(const Classes &rc, const int64_t *uxadj, uint32_t *scu, int32
   PM_LAUNCH_CHECK();
 }
 
-// Rows with 64 < ub <= 4096: one workgroup per row sorts (neighbour, weight)
+// Rows with 64 < ub <= 512: one wave, element i = lane * E + slot (E = 2, 4
+// or 8 per lane, N = 64 E).  Bitonic network: partners within a lane are
+// swapped in registers, partners in other lanes exchanged by shuffles.
+// After the sort a run of equal neighbours may span lanes: each lane's
+// leading run is summed, and a backward segmented scan over the lanes adds
+// the continuation from the following lanes.
+template <int E>
+__device__ __forceinline__ void wave_merge_row(int32_t c, int64_t beg, int ub, uint32_t *scu,
+                                               int32_t *sw, int32_t *rowcnt) {
+  const int lane = threadIdx.x & 63;
+  uint32_t k[E];
+  int32_t w[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const int i = lane * E + q;
+    k[q] = i < ub ? scu[beg + i] : kStageSelf;
+    w[q] = i < ub ? sw[beg + i] : 0;
+  }
+#pragma unroll
+  for (int kk = 2; kk <= 64 * E; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= E) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+          const int i = lane * E + q;
+          const uint32_t pk = (uint32_t)__shfl_xor((int32_t)k[q], j / E, 64);
+          const int32_t pw = __shfl_xor(w[q], j / E, 64);
+          const bool up = (i & kk) == 0, low = (i & j) == 0;
+          if (low == up ? pk < k[q] : pk > k[q]) {
+            k[q] = pk;
+            w[q] = pw;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+          if (q & j) continue;
+          const int p = q | j;
+          const bool up = ((lane * E + q) & kk) == 0;
+          if ((k[q] > k[p]) == up) {
+            const uint32_t tk = k[q];
+            k[q] = k[p];
+            k[p] = tk;
+            const int32_t tw = w[q];
+            w[q] = w[p];
+            w[p] = tw;
+          }
+        }
+      }
+    }
+  }
+  const uint32_t prev_last = (uint32_t)__shfl_up((int32_t)k[E - 1], 1, 64);
+  const uint32_t next_first = (uint32_t)__shfl_down((int32_t)k[0], 1, 64);
+  bool head[E];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    const uint32_t pv = q ? k[q - 1] : prev_last;
+    head[q] = k[q] != kStageSelf && ((lane == 0 && q == 0) || pv != k[q]);
+    cnt += head[q] ? 1u : 0u;
+  }
+  // the lane's leading run, and whether it fills the lane
+  int64_t S = w[0];
+  bool full = true;
+#pragma unroll
+  for (int q = 1; q < E; ++q) {
+    full = full && k[q] == k[0];
+    if (full) S += w[q];
+  }
+  // S(L) = lead(L) + S(L + 1) while lane L is one run continued by lane L + 1
+  bool F = !(full && lane < 63 && next_first == k[0]);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t Sn = gshfl64<64>(S, lane + d < 64 ? lane + d : lane);
+    const bool Fn = __shfl_down((int)F, d, 64) != 0;
+    if (!F && lane + d < 64) {
+      S += Sn;
+      F = Fn;
+    }
+  }
+  const int64_t s_next = gshfl64<64>(S, lane < 63 ? lane + 1 : lane);
+  uint32_t r = cnt;  // exclusive scan of the head counts over the lanes
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int32_t)r, o, 64);
+    if (lane >= o) r += y;
+  }
+  const uint32_t total = (uint32_t)__shfl((int32_t)r, 63, 64);
+  r -= cnt;
+#pragma unroll
+  for (int q = 0; q < E; ++q) {
+    if (!head[q]) continue;
+    int64_t sum = 0;
+    bool open = true;
+#pragma unroll
+    for (int t = q; t < E; ++t) {
+      open = open && k[t] == k[q];
+      if (open) sum += w[t];
+    }
+    if (open && lane < 63 && next_first == k[q]) sum += s_next;
+    scu[beg + r] = k[q];
+    sw[beg + r] = (int32_t)sum;
+    ++r;
+  }
+  if (lane == 0) rowcnt[c] = (int32_t)total;
+}
+
+// Rows with 512 < ub <= 2048: the whole workgroup sorts (neighbour, weight)
 // in LDS with a bitonic network over the next power of two, then writes the
 // distinct neighbours in order with their summed weights from the row's
-// first slot.  Longer rows are left to the radix-sort path.
+// first slot.
 struct LdsRow {
   uint32_t key[kRowMaxLds];
   int32_t w[kRowMaxLds];
 };
 
-__global__ __launch_bounds__(kThreads) void k_contract_lds_rows(const int32_t *list,
-                                                                const int64_t *uxadj,
-                                                                uint32_t *scu, int32_t *sw,
-                                                                int32_t *rowcnt) {
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  LdsRow &R = *reinterpret_cast<LdsRow *>(lds_raw);
-  __shared__ BlockScratch sc;
-  const int32_t c = list[blockIdx.x];
-  const int64_t beg = uxadj[c];
-  const int ub = (int)(uxadj[c + 1] - beg);
-  if (ub > kRowMaxLds) return;  // workgroup-uniform
+__device__ __forceinline__ void lds_merge_row(LdsRow &R, BlockScratch &sc, int32_t c, int64_t beg,
+                                              int ub, uint32_t *scu, int32_t *sw,
+                                              int32_t *rowcnt) {
   int N = 1;
   while (N < ub) N <<= 1;
+  __syncthreads();  // the previous row's readers are done
   for (int i = threadIdx.x; i < N; i += kThreads) {
     R.key[i] = i < ub ? scu[beg + i] : kStageSelf;
     R.w[i] = i < ub ? sw[beg + i] : 0;
@@ -816,30 +919,83 @@ __global__ __launch_bounds__(kThreads) void k_contract_lds_rows(const int32_t *l
   if (threadIdx.x == 0) rowcnt[c] = (int32_t)total;
 }
 
-void contract_lds_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, uint32_t *scu,
+// Rows above 64 (the list of BIG and W rows), four per workgroup: first every
+// wave merges its own row if it is at most 512, then the workgroup merges
+// those of 513..2048 one after another.  Longer rows are left to the sort.
+__global__ __launch_bounds__(kThreads) void k_contract_mid_rows(const int32_t *list, int32_t nl,
+                                                                const int64_t *uxadj,
+                                                                uint32_t *scu, int32_t *sw,
+                                                                int32_t *rowcnt) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  LdsRow &R = *reinterpret_cast<LdsRow *>(lds_raw);
+  __shared__ BlockScratch sc;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads / 64);
+  {
+    const int64_t idx = base + (threadIdx.x >> 6);
+    if (idx < nl) {
+      const int32_t c = list[idx];
+      const int64_t beg = uxadj[c];
+      const int ub = (int)(uxadj[c + 1] - beg);
+      if (ub <= 128) wave_merge_row<2>(c, beg, ub, scu, sw, rowcnt);
+      else if (ub <= 256) wave_merge_row<4>(c, beg, ub, scu, sw, rowcnt);
+      else if (ub <= kRowMaxWave) wave_merge_row<8>(c, beg, ub, scu, sw, rowcnt);
+    }
+  }
+  for (int q = 0; q < kThreads / 64 && base + q < nl; ++q) {
+    const int32_t c = list[base + q];
+    const int64_t beg = uxadj[c];
+    const int ub = (int)(uxadj[c + 1] - beg);
+    if (ub > kRowMaxWave && ub <= kRowMaxLds) lds_merge_row(R, sc, c, beg, ub, scu, sw, rowcnt);
+  }
+}
+
+void contract_mid_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, uint32_t *scu,
                        int32_t *sw, int32_t *rowcnt, hipStream_t s) {
   if (nl <= 0) return;
-  hipLaunchKernelGGL(k_contract_lds_rows, dim3((unsigned)nl), dim3(kThreads), sizeof(LdsRow), s,
-                     list, uxadj, scu, sw, rowcnt);
+  const unsigned nwg = (unsigned)((nl + kThreads / 64 - 1) / (kThreads / 64));
+  hipLaunchKernelGGL(k_contract_mid_rows, dim3(nwg), dim3(kThreads), sizeof(LdsRow), s, list, nl,
+                     uxadj, scu, sw, rowcnt);
   PM_LAUNCH_CHECK();
 }
 
-// Rows above 4096: keys (row << bits | neighbour) at the row's place among
+// Rows above 2048: keys (row << bits | neighbour) at the row's place among
 // those rows (rstart: exclusive prefix of their ub in row order; rows of the
 // list with no place are skipped), self loops keyed with the all-ones
 // neighbour so that they sort last in their row.
-__global__ __launch_bounds__(kThreads) void k_long_keys(const int32_t *list,
+// Four list entries per workgroup; a row with a place (above 2048) is copied
+// by the whole workgroup, four elements per thread loaded before any store.
+__global__ __launch_bounds__(kThreads) void k_long_keys(const int32_t *list, int32_t nl,
                                                         const int64_t *uxadj,
                                                         const int64_t *rstart,
                                                         const uint32_t *scu, const int32_t *sw,
                                                         int bits, uint64_t *key, int32_t *val) {
-  const int32_t c = list[blockIdx.x];
-  const int64_t beg = uxadj[c], dst = rstart[c], ub = rstart[c + 1] - dst;  // 0: LDS row
-  const uint64_t mask = (1ull << bits) - 1ull, row = (uint64_t)c << bits;
-  for (int64_t j = threadIdx.x; j < ub; j += kThreads) {
-    const uint32_t x = scu[beg + j];
-    key[dst + j] = row | (x == kStageSelf ? mask : (uint64_t)x);
-    val[dst + j] = sw[beg + j];
+  const uint64_t mask = (1ull << bits) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * (kThreads / 64);
+  for (int q = 0; q < kThreads / 64 && base + q < nl; ++q) {
+    const int32_t c = list[base + q];
+    const int64_t dst = rstart[c], ub = rstart[c + 1] - dst;  // 0: merged in place
+    if (ub == 0) continue;
+    const int64_t beg = uxadj[c];
+    const uint64_t row = (uint64_t)c << bits;
+    for (int64_t j0 = 0; j0 < ub; j0 += 4 * kThreads) {
+      uint32_t x[4];
+      int32_t y[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + r * kThreads + threadIdx.x;
+        const int64_t jj = j < ub ? j : ub - 1;
+        x[r] = scu[beg + jj];
+        y[r] = sw[beg + jj];
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + r * kThreads + threadIdx.x;
+        if (j < ub) {
+          key[dst + j] = row | (x[r] == kStageSelf ? mask : (uint64_t)x[r]);
+          val[dst + j] = y[r];
+        }
+      }
+    }
   }
 }
 
@@ -887,8 +1043,8 @@ void contract_long_rows(Arena &ar, const int32_t *list, int32_t nl, int64_t m, i
   int32_t *val2 = ar.alloc_n<int32_t>(m);
   int32_t *head = ar.alloc_n<int32_t>(m + 1);
   int32_t *pos = ar.alloc_n<int32_t>(m + 1);
-  hipLaunchKernelGGL(k_long_keys, dim3((unsigned)nl), dim3(kThreads), 0, s, list, uxadj, rstart,
-                     scu, sw, bits, key, val);
+  hipLaunchKernelGGL(k_long_keys, dim3((unsigned)((nl + kThreads / 64 - 1) / (kThreads / 64))),
+                     dim3(kThreads), 0, s, list, nl, uxadj, rstart, scu, sw, bits, key, val);
   PM_LAUNCH_CHECK();
   sort_pairs(ar, key, key2, val, val2, m, 2 * bits, s);
   hipLaunchKernelGGL(k_long_heads, dim3(grid_for(m + 1)), dim3(kThreads), 0, s, m, key2, bits,
@@ -914,12 +1070,28 @@ struct CopyArgs {
   int32_t *cw;
 };
 
+// Four elements per thread are loaded before any is stored (long rows).
 __device__ __forceinline__ void copy_row(const CopyArgs &A, int32_t c, int first, int step) {
   const int64_t src = A.uxadj[c], dst = A.cxadj[c];
   const int64_t len = A.cxadj[c + 1] - dst;
-  for (int64_t j = first; j < len; j += step) {
-    A.cadj[dst + j] = (int32_t)A.scu[src + j];
-    A.cw[dst + j] = A.sw[src + j];
+  for (int64_t j0 = first; j0 < len; j0 += 4 * (int64_t)step) {
+    uint32_t x[4];
+    int32_t y[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = j0 + r * step;
+      const int64_t jj = j < len ? j : len - 1;
+      x[r] = A.scu[src + jj];
+      y[r] = A.sw[src + jj];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t j = j0 + r * step;
+      if (j < len) {
+        A.cadj[dst + j] = (int32_t)x[r];
+        A.cw[dst + j] = y[r];
+      }
+    }
   }
 }
 

@@ -414,12 +414,18 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
   coarse_vwgt(g.n, match, cmap, g.c, cvwgt, s);
   const size_t m = ar.mark();
   const int64_t nnz = g.nnz;
-  if (nnz > 0 && nnz >= tuning().contract_rows_min_nnz) {
+  // A fine vertex above 64 arcs puts its coarse row above 64: with W formed
+  // BIG means above 512, else above 64.  When these alone exceed the share,
+  // the level takes the sort without the row pre-pass.
+  const int64_t cnt_w = L.cl.off[CLS_W + 1] - L.cl.off[CLS_W];
+  const int64_t cnt_big = L.cl.off[CLS_BIG + 1] - L.cl.off[CLS_BIG];
+  const int64_t long_lb = 65 * cnt_w + (cnt_w > 0 ? kWaveMaxDeg + 1 : 65) * cnt_big;
+  const int64_t pct = tuning().contract_rows_long_pct;
+  if (nnz > 0 && nnz >= tuning().contract_rows_min_nnz && long_lb * 100 <= nnz * pct) {
     // row-local path: stage every coarse row at its upper-bound offset, merge
-    // rows of up to 64 arcs in registers and up to 4096 in LDS, and sort only
-    // the arcs of longer rows.  It pays off while rows above 64 hold a small
-    // share of the arcs (the LDS merge of many such rows is slower than one
-    // radix sort over all arcs); above that share the level takes the sort.
+    // rows of up to 512 arcs in registers and up to 2048 in LDS, and sort
+    // only the arcs of longer rows.  A share limit below 100 % sends levels
+    // whose rows above 64 hold more of the arcs to the sort.
     int32_t *ub = ar.alloc_n<int32_t>((size_t)nc + 1);
     int32_t *ubig = ar.alloc_n<int32_t>((size_t)nc + 1);
     int64_t *uxadj = ar.alloc_n<int64_t>((size_t)nc + 1);
@@ -429,9 +435,11 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
     fill_i32(ubig + nc, 0, 1, s);
     contract_rowub(g, match, cmap, ub, ubig, above64, s);
     int64_t *hb = reinterpret_cast<int64_t *>(cx.aux());
-    PM_HIP(hipMemcpyAsync(hb, above64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    PM_HIP(hipStreamSynchronize(s));
-    if (hb[0] * 100 > nnz * (int64_t)tuning().contract_rows_long_pct) {
+    if (pct < 100) {
+      PM_HIP(hipMemcpyAsync(hb, above64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      PM_HIP(hipStreamSynchronize(s));
+    }
+    if (pct < 100 && hb[0] * 100 > nnz * pct) {
       ar.rewind(m);
       run_contract_sorted(cx, L, cmap, nc, cxadj, cadj, cw, nnz_out);
       return;
@@ -454,7 +462,7 @@ static void run_contract(Ctx &cx, const Level &L, int32_t *match, int32_t *cmap,
     contract_rows(rc, uxadj, scu, sw, rowcnt, s);
     const int32_t *llist = rc.list + rc.off[CLS_BIG];  // rows above 64 (BIG, then W)
     const int32_t nl = rc.off[CLS_W + 1] - rc.off[CLS_BIG];
-    contract_lds_rows(llist, nl, uxadj, scu, sw, rowcnt, s);
+    contract_mid_rows(llist, nl, uxadj, scu, sw, rowcnt, s);
     contract_long_rows(ar, llist, nl, lm, nc, uxadj, rstart, scu, sw, rowcnt, s);
     scan_excl_widen(ar, rowcnt, cxadj, (int64_t)nc + 1, s);
     contract_copy(rc, uxadj, cxadj, scu, sw, cadj, cw, s);

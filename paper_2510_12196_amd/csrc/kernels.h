@@ -261,7 +261,7 @@ void contract_keys(const DGraph &g, const Classes &cl, const int32_t *cmap, int 
 // self-loop sentinels.
 // *bad = 1 unless match is an involution with -1 for unmatched vertices
 void check_match(int32_t n, const int32_t *match, int32_t *bad, hipStream_t s);
-// Row-local contraction: ub / ubig (ub when above 4096, else 0) per coarse row;
+// Row-local contraction: ub / ubig (ub when above 2048, else 0) per coarse row;
 // *above64 = sum of ub over rows above 64
 void contract_rowub(const DGraph &g, const int32_t *match, const int32_t *cmap, int32_t *ub,
                     int32_t *ubig, int64_t *above64, hipStream_t s);
@@ -269,7 +269,7 @@ void contract_stage(const DGraph &g, const Classes &cl, const int32_t *match, co
                     const int64_t *uxadj, uint32_t *scu, int32_t *sw, hipStream_t s);
 void contract_rows(const Classes &rc, const int64_t *uxadj, uint32_t *scu, int32_t *sw,
                    int32_t *rowcnt, hipStream_t s);
-void contract_lds_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, uint32_t *scu,
+void contract_mid_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, uint32_t *scu,
                        int32_t *sw, int32_t *rowcnt, hipStream_t s);
 void contract_long_rows(Arena &ar, const int32_t *list, int32_t nl, int64_t m, int32_t nc,
                         const int64_t *uxadj, const int64_t *rstart, uint32_t *scu, int32_t *sw,

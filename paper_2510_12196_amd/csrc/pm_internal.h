@@ -131,7 +131,7 @@ constexpr int kWaveMinCount = 8192;  // fewer W vertices: they go to BIG
 constexpr int32_t kHemCompactMinN = 1 << 18;  // matching rounds tile only active vertices
 constexpr int32_t kRebCompactMinN = 1 << 19;  // rebalancing tiles only overloaded blocks
 constexpr int32_t kContractRowsMinNnz = 1 << 20;  // row-local contraction from this many arcs
-constexpr int32_t kContractRowsLongPct = 12;      // ... while rows above 64 hold <= 12 % of them
+constexpr int32_t kContractRowsLongPct = 100;     // ... while rows above 64 hold <= this % of them
 constexpr int kHemRoundsPerRead = 4;  // matching rounds between status read-backs (small levels)
 
 // Process-wide launch parameters (pm_set_tuning); read at each call.

@@ -2,15 +2,17 @@
 
 Levels with at least contract_rows_min_nnz arcs, whose coarse rows above 64
 staged arcs hold at most contract_rows_long_pct percent of them, stage every
-coarse row at the offset of its upper bound deg(v) + deg(M(v)), merge rows of
-at most 64 arcs in registers and of at most 4096 in LDS, and radix-sort only
-the arcs of longer rows.  The launch parameters set to 1 and 100 send every
-level of these small graphs there.  Cases: matchings from the matcher, no
-matching at all, a matching whose pairs hold only each other (every arc a
-self loop), rows of exactly 64 / 65 and 4096 / 4097 staged arcs, two matched
-hubs with common neighbours (every merged arc the sum of two), hubs above 512
-arcs (with and without the one-wave class for 65..512), isolated vertices,
-and malformed matchings (refused)."""
+coarse row at the offset of its upper bound deg(v) + deg(M(v)) and merge
+rows of at most 64 arcs on lane groups, of at most 512 on one wave (up to
+eight per lane), of at most 2048 in LDS, and radix-sort only the arcs of
+longer rows.  The launch parameters set to 1 and 100 send every level of
+these small graphs there.  Cases: matchings from the matcher, no matching
+at all, a matching whose pairs hold only each other (every arc a self
+loop), rows at every size boundary (64 / 65, 128 / 129, 256 / 257,
+512 / 513, 2048 / 2049 staged arcs), two matched hubs with common
+neighbours (every merged arc the sum of two, runs across lanes), hubs above
+512 arcs (with and without the one-wave class for 65..512), isolated
+vertices, and malformed matchings (refused)."""
 import sys
 
 import numpy as np
@@ -106,21 +108,23 @@ def boundary_rows(seed=3):
     return g, match
 
 
-def hub_pairs(seed=9):
-    """Hubs 0, 1 (degrees 2100 and 1996, staged row 4096) and hubs 2, 3
-    (2100 and 1997, staged row 4097) over a pool of 3000 leaves with large
-    overlaps, each pair joined by an edge and matched."""
-    rng = np.random.default_rng(seed)
-    pool = 4 + np.arange(3000)
+def hub_pairs(total, seed=9):
+    """Hubs 0, 1 (staged row of `total` arcs) and hubs 2, 3 (total + 1) over a
+    pool of leaves with large overlaps, each pair joined by an edge and
+    matched."""
+    rng = np.random.default_rng(seed + total)
+    leaves = max(total, 200)
+    pool = 4 + np.arange(leaves)
+    a = total // 2 + 3
     us, vs = [0, 2], [1, 3]
-    for x, d in ((0, 2099), (1, 1995), (2, 2099), (3, 1996)):
+    for x, d in ((0, a - 1), (1, total - a - 1), (2, a - 1), (3, total - a)):
         nb = rng.choice(pool, d, replace=False)
         us += [x] * d
         vs += list(nb)
-    g = simple(3004, np.asarray(us), np.asarray(vs), rng)
+    g = simple(leaves + 4, np.asarray(us), np.asarray(vs), rng)
     deg = np.diff(g.xadj)
-    assert deg[0] + deg[1] == 4096 and deg[2] + deg[3] == 4097
-    match = np.arange(3004, dtype=np.int32)
+    assert deg[0] + deg[1] == total and deg[2] + deg[3] == total + 1
+    match = np.arange(leaves + 4, dtype=np.int32)
     match[[0, 1, 2, 3]] = [1, 0, 3, 2]
     return g, match
 
@@ -194,6 +198,14 @@ def test_contract_rows_matched(pm, pmo, name, wmin):
         check(pm, pmo, g, matched(pm, pmo, g))
 
 
+def test_contract_rows_twin_hubs_wave(pm, pmo):
+    """Twin hubs of 150 leaves: one row of 302 staged arcs on one wave, every
+    merged arc the sum of two, runs crossing lane boundaries."""
+    g, match = twin_hubs(leaves=150, seed=11)
+    say("contract rows, twin hubs on one wave")
+    check(pm, pmo, g, match)
+
+
 @pytest.mark.parametrize("name", ["rmat14", "dense", "star", "isolated"])
 def test_contract_rows_unmatched(pm, pmo, name):
     g = graph(name)
@@ -207,15 +219,19 @@ def test_contract_rows_boundary_64_65(pm, pmo):
     check(pm, pmo, g, match)
 
 
-def test_contract_rows_boundary_4096_4097(pm, pmo):
-    g, match = hub_pairs()
-    say("contract rows, 4096 / 4097 staged arcs")
+@pytest.mark.parametrize("total", [128, 256, 512, 2048])
+def test_contract_rows_size_boundaries(pm, pmo, total):
+    """Rows of exactly 128 / 256 / 512 staged arcs and one more (two, four,
+    eight arcs per lane on one wave, then the workgroup), 2048 and 2049 (the
+    workgroup, then the radix sort)."""
+    g, match = hub_pairs(total)
+    say("contract rows, staged arcs", total, total + 1)
     check(pm, pmo, g, match)
 
 
 def test_contract_rows_sorted_path_sums(pm, pmo):
     g, match = twin_hubs()
-    say("contract rows, matched hubs above 4096")
+    say("contract rows, matched hubs above 2048")
     check(pm, pmo, g, match)
 
 
@@ -243,6 +259,17 @@ def test_contract_rows_equal_sorted_path(pm, pmo):
             assert np.array_equal(host(x), host(y))
         nc_h, cmap_h = pmo.coarse_map(match_h)
         g = gen.Graph(*pmo.contract(g, cmap_h, nc_h))
+
+
+@pytest.mark.parametrize("pct", [0, 12, 30, 50, 70, 90])
+@pytest.mark.parametrize("name", ["rmat14", "dense"])
+def test_contract_long_share_limit(pm, pmo, name, pct):
+    """Share limits below 100 % send a level to the sort either from the fine
+    classes alone or after the row pre-pass; the result is the same."""
+    g = graph(name)
+    say("contract rows, long-row share limit", name, pct)
+    with pm.tuned(contract_rows_long_pct=pct):
+        check(pm, pmo, g, matched(pm, pmo, g))
 
 
 @pytest.mark.parametrize("bad", ["one_way", "out_of_range", "negative"])
