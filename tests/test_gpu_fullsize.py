@@ -134,9 +134,9 @@ def test_rmat22_matching_and_contraction_invariants(pm, pmo, rmat22):
 
 
 def test_rmat22_contraction_paths_agree(pm, pmo, rmat22):
-    """Row-local contraction forced on (rows up to 4096 arcs merged in
-    registers or LDS, longer ones sorted) equals the contraction by one
-    radix sort over all arcs, at full size."""
+    """Row-local contraction forced on (rows up to 512 arcs merged in
+    registers, up to 2048 in LDS, longer ones sorted) equals the contraction
+    by one radix sort over all arcs, at full size."""
     w, g = rmat22
     dg = pm.DeviceGraph.from_host(g)
     lm = pmo.lmax(int(g.vwgt.sum()), w.k, w.eps)
