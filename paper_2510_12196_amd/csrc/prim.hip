@@ -35,11 +35,6 @@ struct MaskedWeight {
   }
 };
 
-struct IsClass {
-  uint8_t c;
-  __host__ __device__ bool operator()(uint8_t x) const { return x == c; }
-};
-
 struct Widen {
   __host__ __device__ int64_t operator()(int32_t x) const { return (int64_t)x; }
 };
@@ -106,19 +101,6 @@ void select_indices(Arena &ar, const uint8_t *flags, int32_t *out, int32_t *coun
     return;
   }
   rocprim::counting_iterator<int32_t> ids(0);
-  run_two_phase(ar, [&](void *t, size_t &b) {
-    return rocprim::select(t, b, ids, flags, out, count_dev, (size_t)n, s);
-  });
-}
-
-void select_class(Arena &ar, const uint8_t *cls, uint8_t c, int32_t *out, int32_t *count_dev,
-                  int64_t n, hipStream_t s) {
-  if (n <= 0) {
-    PM_HIP(hipMemsetAsync(count_dev, 0, sizeof(int32_t), s));
-    return;
-  }
-  rocprim::counting_iterator<int32_t> ids(0);
-  auto flags = rocprim::make_transform_iterator(cls, IsClass{c});
   run_two_phase(ar, [&](void *t, size_t &b) {
     return rocprim::select(t, b, ids, flags, out, count_dev, (size_t)n, s);
   });

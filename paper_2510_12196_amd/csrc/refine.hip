@@ -62,7 +62,11 @@ void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64
 // ===========================================================================
 // degree classes
 // ===========================================================================
-__global__ void k_classify(DGraph g, int32_t wmax, uint8_t *cls, int32_t *counts) {
+// Also writes the workgroup's count of every class to blockcnt[class * nb +
+// workgroup] (class-major: an exclusive scan of it gives each workgroup's
+// first slot per class in the concatenated class lists).
+__global__ void k_classify(DGraph g, int32_t wmax, uint8_t *cls, int32_t *counts,
+                           int32_t *blockcnt, int32_t nb) {
   __shared__ int32_t c[NCLS];
   if (threadIdx.x < NCLS) c[threadIdx.x] = 0;
   __syncthreads();
@@ -75,7 +79,34 @@ __global__ void k_classify(DGraph g, int32_t wmax, uint8_t *cls, int32_t *counts
     atomicAdd(&c[k], 1);
   }
   __syncthreads();
-  if (threadIdx.x < NCLS && c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+  if (threadIdx.x < NCLS) {
+    blockcnt[threadIdx.x * nb + blockIdx.x] = c[threadIdx.x];
+    if (c[threadIdx.x]) atomicAdd(&counts[threadIdx.x], c[threadIdx.x]);
+  }
+}
+
+// Stable scatter of every vertex id into its class list: the workgroup's
+// first slot per class (blockoff) plus the ids of the same class before it
+// in the workgroup (counted per wave by ballots).
+__global__ __launch_bounds__(kThreads) void k_class_scatter(int32_t n, const uint8_t *cls,
+                                                            const int32_t *blockoff, int32_t nb,
+                                                            int32_t *list) {
+  __shared__ int32_t wc[kThreads / 64][NCLS];
+  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = v < n ? (int)cls[v] : -1;
+  uint64_t same = 0;
+  for (int k = 0; k < NCLS; ++k) {
+    const uint64_t m = __ballot(c == k);
+    if (c == k) same = m;
+    if (lane == 0) wc[wave][k] = __popcll(m);
+  }
+  __syncthreads();
+  if (c < 0) return;
+  int32_t off = blockoff[c * nb + blockIdx.x];
+  for (int w = 0; w < wave; ++w) off += wc[w][c];
+  off += __popcll(same & ((1ull << lane) - 1ull));
+  list[off] = (int32_t)v;
 }
 
 Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
@@ -86,18 +117,21 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
   cl.list = list;
   size_t m = ar.mark();
   uint8_t *cls = ar.alloc_n<uint8_t>((size_t)g.n + 1);
-  int32_t *counts = ar.alloc_n<int32_t>(2 * NCLS);
-  int32_t *host = static_cast<int32_t *>(ar.host_stage(sizeof(int32_t) * 2 * NCLS));
+  int32_t *counts = ar.alloc_n<int32_t>(NCLS);
+  const int32_t nb = g.n > 0 ? (int32_t)grid_for(g.n) : 0;
+  int32_t *blockcnt = ar.alloc_n<int32_t>((size_t)NCLS * nb + 1);
+  int32_t *blockoff = ar.alloc_n<int32_t>((size_t)NCLS * nb + 1);
+  int32_t *host = static_cast<int32_t *>(ar.host_stage(sizeof(int32_t) * NCLS));
   // W tiles (a wave per vertex) pay off once they fill the chip; with fewer
   // such vertices a workgroup per vertex finishes sooner, so degrees above 64
   // then all go to BIG (the two paths compute the same results).
   // (the threshold is a launch parameter: pm_set_tuning)
   const int64_t wmin = tuning().wave_min_count;
   for (int32_t wmax : {kWaveMaxDeg, 64}) {
-    PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2 * NCLS, s));
+    PM_HIP(hipMemsetAsync(counts, 0, sizeof(int32_t) * NCLS, s));
     if (g.n > 0) {
-      hipLaunchKernelGGL(k_classify, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g, wmax, cls,
-                         counts);
+      hipLaunchKernelGGL(k_classify, dim3(nb), dim3(kThreads), 0, s, g, wmax, cls, counts,
+                         blockcnt, nb);
       PM_LAUNCH_CHECK();
     }
     PM_HIP(hipMemcpyAsync(host, counts, sizeof(int32_t) * NCLS, hipMemcpyDeviceToHost, s));
@@ -113,8 +147,12 @@ Classes build_classes(Arena &ar, const DGraph &g, int32_t *list, Status *st_dev,
     int per = class_per_wg(c);
     cl.wg[c + 1] = cl.wg[c] + (cnt[c] + per - 1) / per;
   }
-  for (int c = 0; c < NCLS; ++c)
-    if (cnt[c]) select_class(ar, cls, (uint8_t)c, list + cl.off[c], counts + NCLS + c, g.n, s);
+  if (nb > 0) {
+    scan_excl(ar, blockcnt, blockoff, (int64_t)NCLS * nb, s);
+    hipLaunchKernelGGL(k_class_scatter, dim3(nb), dim3(kThreads), 0, s, g.n, cls, blockoff, nb,
+                       list);
+    PM_LAUNCH_CHECK();
+  }
   ar.rewind(m);
   return cl;
 }
