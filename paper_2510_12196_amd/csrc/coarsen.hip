@@ -551,10 +551,10 @@ void contract_emit(int64_t nnz, const int32_t *self, const uint64_t *key, const 
 // of equal neighbours), a row with ub <= 512 by one wave holding up to eight
 // arcs per lane, a row with ub <= 2048 by a workgroup in LDS; longer rows go
 // through one global radix sort keyed by (row, neighbour) over their arcs
-// only.  The merged lengths give the
-// coarse offsets, and a last pass copies every row to its place.  The result
-// is the same CSR as the global sort over all arcs: per row the distinct
-// coarse neighbours other than itself, ascending, with summed weights.
+// only.  The merged lengths give the coarse offsets, and a last pass copies
+// every row to its place.  The result is the same CSR as the global sort over
+// all arcs: per row the distinct coarse neighbours other than itself,
+// ascending, with summed weights.
 // ===========================================================================
 constexpr uint32_t kStageSelf = 0xFFFFFFFFu;
 constexpr int kRowMaxG = 64;      // rows up to this bound: lane groups
@@ -961,9 +961,9 @@ void contract_mid_rows(const int32_t *list, int32_t nl, const int64_t *uxadj, ui
 // Rows above 2048: keys (row << bits | neighbour) at the row's place among
 // those rows (rstart: exclusive prefix of their ub in row order; rows of the
 // list with no place are skipped), self loops keyed with the all-ones
-// neighbour so that they sort last in their row.
-// Four list entries per workgroup; a row with a place (above 2048) is copied
-// by the whole workgroup, four elements per thread loaded before any store.
+// neighbour so that they sort last in their row.  Four list entries per
+// workgroup; a row with a place is copied by the whole workgroup, four
+// elements per thread loaded before any store.
 __global__ __launch_bounds__(kThreads) void k_long_keys(const int32_t *list, int32_t nl,
                                                         const int64_t *uxadj,
                                                         const int64_t *rstart,
