@@ -74,3 +74,43 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 def test_tuning_struct_layout():
     import paper_2510_12196_amd as pm
     assert ctypes.sizeof(pm.PmTuning) == 24
+
+
+def test_tuning_host_logic_without_gpu():
+    """Launch parameters are host state: defaults, refusal of out-of-range
+    values (nothing changed), and a round trip, all without a device."""
+    import paper_2510_12196_amd as pm
+    pm.lib()
+    before = pm.get_tuning()
+    try:
+        for bad in ({"group_v": 0}, {"wave_min_count": 0}, {"contract_rows_min_nnz": 0},
+                    {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101}):
+            with pytest.raises(pm.PmError) as e:
+                pm.set_tuning(**bad)
+            assert e.value.code == pm.PM_EINVAL and pm.get_tuning() == before
+        pm.set_tuning(contract_rows_long_pct=0, contract_rows_min_nnz=5)
+        t = pm.get_tuning()
+        assert t["contract_rows_long_pct"] == 0 and t["contract_rows_min_nnz"] == 5
+    finally:
+        pm.set_tuning(**before)
+
+
+@pytest.mark.parametrize("env,expect", [({}, 100), ({"PM_CONTRACT_ROWS_LONG_PCT": "0"}, 0),
+                                        ({"PM_CONTRACT_ROWS_LONG_PCT": "37"}, 37),
+                                        ({"PM_CONTRACT_ROWS_LONG_PCT": "101"}, 100),
+                                        ({"PM_CONTRACT_ROWS_LONG_PCT": "12x"}, 100)])
+def test_tuning_environment(env, expect):
+    """Initial values come from the environment; malformed or out-of-range
+    values leave the default (a fresh process per case)."""
+    import os
+    import subprocess
+    import sys
+    code = ("import paper_2510_12196_amd as pm; pm.lib(); "
+            "t = pm.get_tuning(); print(t['contract_rows_long_pct'], t['contract_rows_min_nnz'])")
+    e = {k: v for k, v in os.environ.items() if not k.startswith("PM_")}
+    e.update(env)
+    out = subprocess.run([sys.executable, "-c", code], env=e, cwd=ROOT, capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    pct, nnz = map(int, out.stdout.split())
+    assert pct == expect and nnz == 1 << 20
