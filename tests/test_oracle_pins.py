@@ -522,6 +522,76 @@ def test_contraction_properties(pmo, name):
         assert np.array_equal(pmo.block_weights(cg, pc, w.k), pmo.block_weights(g, pf, w.k))
 
 
+def _contract_by_definition(g, cmap, nc):
+    """Coarse graph written out from its definition: per coarse row, the sum
+    of the weights of the fine arcs to every other coarse vertex, rows
+    ascending by neighbour, vertex weights summed."""
+    rows = [dict() for _ in range(nc)]
+    for v in range(g.n):
+        c = int(cmap[v])
+        for e in range(int(g.xadj[v]), int(g.xadj[v + 1])):
+            cu = int(cmap[int(g.adjncy[e])])
+            if cu != c:
+                rows[c][cu] = rows[c].get(cu, 0) + int(g.adjwgt[e])
+    cx = np.zeros(nc + 1, np.int64)
+    ca, cw = [], []
+    for c in range(nc):
+        for cu in sorted(rows[c]):
+            ca.append(cu)
+            cw.append(rows[c][cu])
+        cx[c + 1] = len(ca)
+    cv = np.zeros(nc, np.int64)
+    np.add.at(cv, cmap, g.vwgt.astype(np.int64))
+    return cx, np.array(ca, np.int64), np.array(cw, np.int64), cv
+
+
+def _twin_hubs(leaves, seed):
+    rng = np.random.default_rng(seed)
+    lv = 2 + np.arange(leaves)
+    u = np.concatenate([[0], np.zeros(leaves, np.int64), np.ones(leaves, np.int64)])
+    v = np.concatenate([[1], lv, lv])
+    g = gen.from_edges(leaves + 2, u, v, rng.integers(1, 11, u.shape[0]),
+                       rng.integers(1, 5, leaves + 2))
+    m = np.arange(leaves + 2, dtype=np.int32)
+    m[[0, 1]] = [1, 0]
+    return g, m
+
+
+def _pairs_only(n, seed):
+    rng = np.random.default_rng(seed)
+    u = np.arange(0, n, 2)
+    g = gen.from_edges(n, u, u + 1, rng.integers(1, 11, n // 2), np.ones(n))
+    return g, np.arange(n, dtype=np.int32) ^ 1
+
+
+@pytest.mark.parametrize("case", ["hem_rgg14", "identity_rmat14", "twin_hubs", "pairs_only"])
+def test_contraction_equals_definition(pmo, case):
+    """The oracle's contraction against the coarse graph written out from its
+    definition (brute force), on matchings of the matcher, no matching, two
+    matched hubs sharing every neighbour (each merged arc adds two weights)
+    and a matching that leaves no coarse arc."""
+    if case == "hem_rgg14":
+        w = gen.get("rgg14")
+        g = w.graph()
+        _, match = pmo.hem(g, pmo.lmax(int(g.vwgt.sum()), w.k, w.eps), 3)
+    elif case == "identity_rmat14":
+        g = gen.get("rmat14").graph()
+        match = np.arange(g.n, dtype=np.int32)
+    elif case == "twin_hubs":
+        g, match = _twin_hubs(300, 4)
+    else:
+        g, match = _pairs_only(600, 5)
+    nc, cmap = pmo.coarse_map(match)
+    got = pmo.contract(g, cmap, nc)
+    exp = _contract_by_definition(g, cmap, nc)
+    for x, y in zip(got, exp):
+        assert np.array_equal(np.asarray(x, np.int64), y)
+    if case == "twin_hubs":
+        assert exp[0][1] - exp[0][0] == 300          # the hub pair's row: every leaf once
+    if case == "pairs_only":
+        assert exp[0][-1] == 0 and nc == 300
+
+
 # ----------------------------------------------------------------------------
 # initial partitioning and the multilevel driver
 # ----------------------------------------------------------------------------
