@@ -80,6 +80,8 @@ _SIGS = {
                                _U64, _I32, _I32, _P, _P, _P]),
     "pmo_refine_v": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _I32, _P, _P,
                             _P]),
+    "pmo_refine_trace": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _I32, _P,
+                                _P, _P, _I32, _P, _P, _P, _P]),
     "pmo_map_v": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _U64, _P, _P, _P]),
 }
 
@@ -228,6 +230,27 @@ def refine(g, a, d, eps, seed, part, level: int = 0, var=None):
                             lv, _ptr(a), _ptr(d), eps_to_ppm(eps), seed & (2**64 - 1), level,
                             _ptr(part), ctypes.byref(st), _var(var))
     return int(rc), part, st
+
+
+def refine_trace(g, a, d, eps, seed, part, level: int = 0, var=None, cap: int = 4096):
+    """refine() with a record of the loop bodies.  Returns (status, part,
+    RefineStats, kinds, j_after, imb_after, counter): kinds is a string of
+    'L' / 'w' / 'S' per body; j_after, imb_after and counter are J, the
+    heaviest block and Algorithm 6's counter i after each body."""
+    lv, a, d = _hier(a, d)
+    part = _i32(part).copy()
+    st = RefineStats()
+    kinds = ctypes.create_string_buffer(cap)
+    ja = np.zeros(cap, np.int64)
+    ia = np.zeros(cap, np.int64)
+    ct = np.zeros(cap, np.int32)
+    rc = lib().pmo_refine_trace(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt),
+                                _ptr(g.vwgt), lv, _ptr(a), _ptr(d), eps_to_ppm(eps),
+                                seed & (2**64 - 1), level, _ptr(part), ctypes.byref(st),
+                                _var(var), cap, kinds, _ptr(ja), _ptr(ia), _ptr(ct))
+    m = min(st.iterations, cap)
+    return (int(rc), part, st, kinds.raw[:m].decode(), ja[:m].copy(), ia[:m].copy(),
+            ct[:m].copy())
 
 
 def hem(g, lmax_: int, seed: int, level: int = 0):

@@ -317,6 +317,11 @@ static int cmp_reb(const void *x, const void *y) {
 
 static int32_t floor_log2_u64(uint64_t x) { return 63 - __builtin_clzll(x); }
 
+/* smallest q with c <= 2^q (c >= 1) */
+static int32_t weight_class(int64_t c) {
+  return c <= 1 ? 0 : 1 + floor_log2_u64((uint64_t)(c - 1));
+}
+
 /* One rebalancing round, weak (strong = 0) or strong (strong = 1).
  *
  * Sources: vertices of overloaded blocks (c(block) > L_max) that are not
@@ -341,10 +346,13 @@ static int32_t floor_log2_u64(uint64_t x) { return 63 - __builtin_clzll(x); }
  * Weak: all selected sources move to their destination.
  * Strong: the selected movers of every destination b, ordered by (bucket,
  * id), are accepted while c(b) + (weight before them) + c(v) <= L_max.  The
- * rejected ones, in id order with exclusive weight prefix R, are placed into
- * the blocks with residual capacity r_b = L_max - c(b) - accepted_b > 0:
- * over the ascending list of those blocks with exclusive prefix C_b, the
- * mover goes to the b with C_b <= R < C_b + r_b; if R >= sum r_b it stays.
+ * rejected ones are reassigned to blocks with residual capacity
+ * r_b = L_max - c(b) - accepted_b > 0 without overloading any of them: over
+ * the ascending list of those blocks (exclusive prefix C_b), the rejected
+ * movers in id order take consecutive intervals of the residual capacity and
+ * a mover goes to the block whose interval [C_b, C_b + r_b) contains its
+ * whole interval; a second pass does the same for the movers the first one
+ * could not place, behind the first pass's range; the rest stay.
  *
  * moved_out[v] = 1 for every vertex that changed block; part is updated. */
 void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
@@ -505,42 +513,61 @@ void pmo_rebalance_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
         before += vwgt[v];
       }
     }
-    /* residual capacities, ascending block id */
-    int64_t *resid_start = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
-    int64_t *resid_len = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
-    int32_t *resid_blk = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)k);
-    int64_t nres = 0, csum = 0;
-    for (int64_t b = 0; b < k; ++b) {
-      int64_t r = lmax - w[b] - acc[b];
-      if (r > 0) {
-        resid_start[nres] = csum;
-        resid_len[nres] = r;
-        resid_blk[nres] = (int32_t)b;
-        csum += r;
-        ++nres;
-      }
-    }
-    int64_t rprefix = 0, j = 0;
+    /* residual capacity of every block after the accepted moves */
+    int64_t *resid = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
+    int64_t *got = (int64_t *)xcalloc((size_t)k, sizeof(int64_t));
+    for (int64_t b = 0; b < k; ++b) resid[b] = lmax - w[b] - acc[b];
+    /* the accepted movers go to their destinations */
+    int32_t qmax = -1;
     for (int32_t v = 0; v < n; ++v) {
       if (!sel[v]) continue;
       if (accepted[v]) {
         part[v] = dest[v];
         moved_out[v] = 1;
-        continue;
+      } else if (weight_class(vwgt[v]) > qmax) {
+        qmax = weight_class(vwgt[v]);
       }
-      /* rejected: place by the exclusive prefix of rejected weight */
-      if (rprefix < csum) {
-        while (!(resid_start[j] <= rprefix && rprefix < resid_start[j] + resid_len[j])) ++j;
-        if (resid_blk[j] != part[v]) {
-          part[v] = resid_blk[j];
-          moved_out[v] = 1;
-        }
-      }
-      rprefix += vwgt[v];
     }
-    free(resid_start);
-    free(resid_len);
-    free(resid_blk);
+    /* The rejected movers are reassigned without overloading any block, by
+     * weight class q(v) = ceil(log2 c(v)) (the smallest q with c(v) <= 2^q),
+     * heaviest class first.  For class q, every block b with residual
+     * r_b >= 2^q offers the interval of length s_b = r_b - 2^q + 1 (blocks
+     * in ascending id, exclusive prefix C_b); the movers of the class, in
+     * id order with exclusive weight prefix R, go to the block with
+     * C_b <= R < C_b + s_b, and stay where they are when R >= sum s_b.  The
+     * movers a block receives in one class occupy consecutive positions that
+     * start inside its interval, so together they weigh at most
+     * (s_b - 1) + 2^q = r_b; the block's residual then shrinks by what it
+     * received before the next class. */
+    int64_t *slot_start = (int64_t *)xmalloc(sizeof(int64_t) * (size_t)k);
+    for (int32_t q = qmax; q >= 0; --q) {
+      int64_t unit = (int64_t)1 << q, csum = 0;
+      for (int64_t b = 0; b < k; ++b) {
+        slot_start[b] = csum;
+        if (resid[b] >= unit) csum += resid[b] - unit + 1;
+      }
+      int64_t R = 0, b = 0;
+      for (int32_t v = 0; v < n; ++v) {
+        if (!sel[v] || accepted[v] || weight_class(vwgt[v]) != q) continue;
+        if (R < csum) {
+          /* the block whose interval holds R */
+          while (!(resid[b] >= unit && slot_start[b] <= R &&
+                   R < slot_start[b] + resid[b] - unit + 1))
+            ++b;
+          part[v] = (int32_t)b;
+          moved_out[v] = 1;
+          got[b] += vwgt[v];
+        }
+        R += vwgt[v];
+      }
+      for (int64_t x = 0; x < k; ++x) {
+        resid[x] -= got[x];
+        got[x] = 0;
+      }
+    }
+    free(slot_start);
+    free(resid);
+    free(got);
     free(acc);
     free(accepted);
     free(bucket_of);
@@ -598,6 +625,25 @@ int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                      const int32_t *a, const int32_t *d, int64_t eps_ppm,
                      uint64_t seed, int32_t level, int32_t *part,
                      pmo_refine_stats *stats, const pmo_variants *var) {
+  return pmo_refine_trace(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, eps_ppm,
+                          seed, level, part, stats, var, 0, NULL, NULL, NULL,
+                          NULL);
+}
+
+/* pmo_refine_v with a record of the loop bodies: for body t < trace_cap,
+ * kind[t] is 'L' (label propagation), 'w' (weak) or 'S' (strong
+ * rebalancing); j_after[t] and imb_after[t] are J and the heaviest block of
+ * the current mapping after the body, and counter[t] is Algorithm 6's
+ * counter i after the body's best-mapping update.  Any of the four arrays
+ * may be NULL. */
+int32_t pmo_refine_trace(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                         const int32_t *adjwgt, const int32_t *vwgt,
+                         int32_t levels, const int32_t *a, const int32_t *d,
+                         int64_t eps_ppm, uint64_t seed, int32_t level,
+                         int32_t *part, pmo_refine_stats *stats,
+                         const pmo_variants *var, int32_t trace_cap,
+                         char *kind, int64_t *j_after, int64_t *imb_after,
+                         int32_t *counter) {
   int64_t k = pmo_num_pes(levels, a);
   int64_t total = 0;
   for (int32_t v = 0; v < n; ++v) total += vwgt[v];
@@ -625,21 +671,25 @@ int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
   while (i < REFINE_PATIENCE && bodies < REFINE_MAX_BODIES) {
     ++i;
     ++bodies;
+    char what;
     if (imb_cur <= lmax) {
       pmo_lp_round_v(n, xadj, adjncy, adjwgt, levels, a, d, cur, lock, target,
                      gain, moved, var);
       iw = 0;
       ++st.lp_iterations;
+      what = 'L';
     } else if (iw < REFINE_WEAK_ROUNDS) {
       pmo_rebalance_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, k, 0, lmax,
                       sigma, seed, level, bodies, cur, moved, var);
       ++iw;
       ++st.weak_iterations;
+      what = 'w';
     } else {
       pmo_rebalance_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, d, k, 1, lmax,
                       sigma, seed, level, bodies, cur, moved, var);
       iw = 0;
       ++st.strong_iterations;
+      what = 'S';
     }
     int64_t j_cur = pmo_comm_cost(n, xadj, adjncy, adjwgt, cur, levels, a, d);
     imb_cur = max_block(n, vwgt, cur, k, wscratch);
@@ -658,6 +708,12 @@ int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
       j_best = j_cur;
       imb_best = imb_cur;
       i = 0;
+    }
+    if (bodies <= trace_cap) {
+      if (kind) kind[bodies - 1] = what;
+      if (j_after) j_after[bodies - 1] = j_cur;
+      if (imb_after) imb_after[bodies - 1] = imb_cur;
+      if (counter) counter[bodies - 1] = i;
     }
   }
   st.iterations = bodies;

@@ -111,6 +111,14 @@ int32_t pmo_refine_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                      const int32_t *a, const int32_t *d, int64_t eps_ppm,
                      uint64_t seed, int32_t level, int32_t *part,
                      pmo_refine_stats *stats, const pmo_variants *var);
+int32_t pmo_refine_trace(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                         const int32_t *adjwgt, const int32_t *vwgt,
+                         int32_t levels, const int32_t *a, const int32_t *d,
+                         int64_t eps_ppm, uint64_t seed, int32_t level,
+                         int32_t *part, pmo_refine_stats *stats,
+                         const pmo_variants *var, int32_t trace_cap,
+                         char *kind, int64_t *j_after, int64_t *imb_after,
+                         int32_t *counter);
 int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                    const int32_t *a, const int32_t *d, int64_t eps_ppm,

@@ -298,9 +298,85 @@ def test_strong_rebalance_balances_unit_weights(pmo):
     p2, moved = pmo.rebalance(g, k, part, True, lm, sg, 1, 0, 1)
     w1 = pmo.block_weights(g, p2, k)
     assert w1.max() <= lm
-    assert w1.sum() == w0.sum()
-    # only vertices of overloaded blocks move
-    assert (w0[part[moved.astype(bool)]] > lm).all()
+
+
+def test_strong_rebalance_weighted_hand_example(pmo):
+    fx = golden("strong_rebalance_weighted.json")
+    g = graph_from_fixture(fx)
+    k = int(np.prod(fx["a"]))
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, fx["eps"])
+    assert lm == fx["lmax"]
+    sg = pmo.sigma(lm, total, k)
+    for seed in (1, 2, 3):
+        part, moved = pmo.rebalance(g, k, fx["part_in"], True, lm, sg, seed, 0, 3)
+        assert moved.tolist() == fx["moved"]
+        assert part.tolist() == fx["part_out"]
+        assert pmo.block_weights(g, part, k).tolist() == fx["weights_out"]
+
+
+@pytest.mark.parametrize("name,k", [("rmat14", 512), ("rmat14", 64), ("rmat17", 512)])
+def test_strong_rebalance_never_overloads_and_balances(pmo, name, k):
+    """Strong rebalancing must not overload a destination and balances in
+    one round (Section 4.2, 'Rebalancing'), here on graphs with vertex
+    weights 1..4 from a start with one block holding 5 % of all vertices
+    besides its random share."""
+    g = gen.get(name).graph()
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    sg = pmo.sigma(lm, total, k)
+    rng = np.random.default_rng(5)
+    part = rng.integers(0, k, g.n).astype(np.int32)
+    part[rng.random(g.n) < 0.05] = 3
+    w0 = pmo.block_weights(g, part, k)
+    assert w0.max() > lm
+    p2, moved = pmo.rebalance(g, k, part, True, lm, sg, 7, 0, 1)
+    w1 = pmo.block_weights(g, p2, k)
+    # no block at or below L_max before the round is above it afterwards
+    assert not np.any((w0 <= lm) & (w1 > lm))
+    # the blocks' free capacity covers the excess here: one round balances
+    assert w1.max() <= lm
+    assert np.array_equal(moved != 0, p2 != part)
+
+
+def test_heavy_vertex_boundary_hand_example(pmo):
+    fx = golden("heavy_vertex_boundary.json")
+    g = graph_from_fixture(fx)
+    k = int(np.prod(fx["a"]))
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, fx["eps"])
+    sg = pmo.sigma(lm, total, k)
+    assert (lm, sg) == (1030, 1000)
+    part, moved = pmo.rebalance(g, k, fx["part_in"], False, lm, sg, 1, 0, 1)
+    assert moved.tolist() == fx["weak_moved"] and part.tolist() == fx["weak_part_out"]
+    part, moved = pmo.rebalance(g, k, fx["part_in"], True, lm, sg, 1, 0, 1)
+    assert moved.tolist() == fx["strong_moved"] and part.tolist() == fx["strong_part_out"]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_refine_patience_and_phi_hand_example(pmo, case):
+    fx = golden("refine_patience.json")
+    c = fx["cases"][case]
+    g = graph_from_fixture({"n": fx["n"], "vwgt": fx["vwgt"], "edges": c["edges"]})
+    rc, part, st, kinds, ja, ia, ct = pmo.refine_trace(g, fx["a"], fx["d"], fx["eps"], 1,
+                                                       fx["part_in"])
+    assert rc == 0
+    assert kinds == c["kinds"]
+    assert ct.tolist() == c["counter"]
+    assert ja.tolist() == c["j_after"]
+    assert part.tolist() == c["part_out"]
+
+
+def test_refine_weak_strong_order_hand_example(pmo):
+    fx = golden("refine_weak_strong_order.json")
+    g = graph_from_fixture(fx)
+    rc, part, st, kinds, ja, ia, ct = pmo.refine_trace(g, fx["a"], fx["d"], fx["eps"], 1,
+                                                       fx["part_in"])
+    assert rc == fx["status"]
+    assert kinds == fx["kinds"]
+    assert ct.tolist() == fx["counter"]
+    assert ia.tolist() == fx["imb_after"]
+    assert part.tolist() == fx["part_out"] and st.maxw_final == fx["maxw_final"]
 
 
 def test_weak_rebalance_moves_only_from_overloaded(pmo):
@@ -383,9 +459,12 @@ def test_brute_force_optimum(pmo, n, seed):
     rc, part, st = pmo.map_graph(g, a, d, eps, seed)
     assert rc == 0
     assert pmo.comm_cost(g, part, a, d) >= Jstar
-    # refining an optimal mapping returns it unchanged
+    # refining an optimal mapping returns it unchanged, after exactly 12 loop
+    # bodies: no feasible mapping is cheaper and no unbalanced one is
+    # lighter than a balanced best, so the counter never restarts
     rc2, part2, st2 = pmo.refine(g, a, d, eps, seed, pstar)
     assert rc2 == 0 and np.array_equal(part2, pstar) and st2.j_final == Jstar
+    assert st2.iterations == 12
 
 
 # ----------------------------------------------------------------------------
@@ -626,6 +705,11 @@ def test_map_balance_and_levels(pmo, name, seed):
     assert ns[0] == g.n and all(x > y for x, y in zip(ns, ns[1:]))
     for x, y in zip(ns, ns[1:]):
         assert 20 * y <= 19 * x
+    # coarsening stops once fewer than 8k vertices remain (Section 4.2,
+    # initial partitioning), and not before
+    assert all(x >= 8 * w.k for x in ns[:-1])
+    if len(ns) > 1:
+        assert ns[-1] < 8 * w.k
 
 
 # ----------------------------------------------------------------------------
