@@ -266,7 +266,7 @@ def main():
 
 
 def bench_hm(args, w, g, dg):
-    """Hierarchical multisection (Section 3.1, the GPU-HM variant): every
+    """Hierarchical multisection (Section 4.1, the GPU-HM variant): every
     level's subgraphs partitioned by the multilevel mapper with (a_i), d = 1
     and the adaptive imbalance of equation (2).  Timed beside the multilevel
     mapping of the same graph and seeds; J of both under the full hierarchy."""

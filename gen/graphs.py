@@ -1,7 +1,7 @@
 """Seeded synthetic task graphs and mappings.
 
 This module only *produces inputs*: task graphs in CSR form (both directions of
-every undirected edge stored, as the CSR description of the paper's Section 2
+every undirected edge stored, as the CSR description of the paper's Section 3.4
 requires), vertex/edge weights and initial mappings.  It contains none of the
 mapping method's arithmetic and is shared by the CPU oracle tests and the GPU
 path alike.

@@ -3,7 +3,7 @@
  *
  * The library computes, on one GPU, the data-parallel hot path of the
  * integrated multilevel process-mapping method of "GPU-Accelerated Algorithms
- * for Process Mapping" (arXiv 2510.12196, Section 3.2): refinement of a
+ * for Process Mapping" (arXiv 2510.12196, Section 4.2): refinement of a
  * mapping Pi of a task graph onto the PEs of a hierarchical machine under the
  * communication cost J (Section 2), heavy-edge-matching coarsening, CSR
  * contraction, initial partitioning of the coarsest graph, and projection of
@@ -12,7 +12,7 @@
  * Common conventions
  * ------------------
  * Graph (pm_graph): undirected, both directions of every edge stored (CSR as
- *   in Section 2 "CSR Graph Format").  All arrays live in DEVICE memory owned
+ *   in Section 3.4 "CSR Graph Format").  All arrays live in DEVICE memory owned
  *   by the caller and are only read:
  *     xadj   int64[n+1], xadj[0] = 0, non-decreasing, xadj[n] = nnz
  *     adjncy int32[nnz]  neighbour ids in [0,n), no self-loops, no duplicate
@@ -87,7 +87,7 @@ typedef struct pm_hierarchy {
   int32_t d[PM_MAX_LEVELS];
 } pm_hierarchy;
 
-/* Refinement variants (Section 3.2, the alternatives the paper discusses).
+/* Refinement variants (Section 4.2, the alternatives the paper discusses).
  *   PM_VARIANT_JET_FILTER: Jet's relaxed first filter of label propagation --
  *     a vertex whose best gain G is negative still enters the first-filter
  *     set when -G < floor(c * conn(v, own block)), c = jet_c_num / jet_c_den
@@ -206,7 +206,7 @@ int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part,
 int pm_block_weights(const pm_graph *g, const pm_hierarchy *h,
                      const int32_t *part, int64_t *w_out, void *stream);
 
-/* One round of unconstrained label propagation (Section 3.2, Algorithm 4,
+/* One round of unconstrained label propagation (Section 4.2, Algorithm 4,
  * equation (1), implicit order by (gain desc, id asc), second filter under
  * the approximate future state, moved vertices locked).
  * part: device int32[n], in/out.  lock: device uint8[n], in/out (nonzero =
@@ -235,7 +235,7 @@ int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong,
                     int32_t iter, int32_t *part, uint8_t *moved_out,
                     const pm_options *opts, void *stream);
 
-/* Refinement (Section 3.2, Algorithm 6): label propagation while balanced,
+/* Refinement (Section 4.2, Algorithm 6): label propagation while balanced,
  * otherwise up to two weak then one strong rebalancing; keeps the best
  * mapping; stops after 12 loop bodies without sufficient improvement.
  * part: device int32[n], in/out (input mapping, returned best mapping).
@@ -249,15 +249,18 @@ int pm_refine_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
                  uint64_t seed, int32_t level, int32_t *part,
                  pm_refine_stats *stats, const pm_options *opts, void *stream);
 
-/* Heavy-edge matching rounds (Section 3.2, Matching): rating w^2/(c(u)c(v)),
+/* Heavy-edge matching rounds (Section 4.2, Matching): rating w^2/(c(u)c(v)),
  * exact comparison with a hash tie-break, mutual preference, rounds until no
- * new match; then, if at most 75 % of the vertices are matched, isolated
- * vertices are paired in id order.  match_out: device int32[n] (partner, or
- * the vertex itself).  rounds_out: host int32, may be NULL. */
+ * new match; then two-hop matching, each step only while at most 75 % of the
+ * vertices are matched: leaves (degree 1) sharing their neighbour, twins
+ * (equal neighbourhood key; all isolated vertices form one group), relatives
+ * sharing their matchmaker, paired in id order inside a group when the pair
+ * fits L_max.  match_out: device int32[n] (partner, or the vertex itself).
+ * rounds_out: host int32, may be NULL. */
 int pm_hem(const pm_graph *g, int64_t lmax, uint64_t seed, int32_t level,
            int32_t *match_out, int32_t *rounds_out, void *stream);
 
-/* Coarse numbering and contraction (Section 3.2, Contraction): coarse id =
+/* Coarse numbering and contraction (Section 4.2, Contraction): coarse id =
  * rank of the smaller member; coarse vertex weight = sum; arcs mapped, self
  * loops dropped, parallel arcs fused with summed weights.  Outputs (device,
  * caller-allocated at the fine sizes): cmap int32[n], cxadj int64[n+1],
@@ -270,13 +273,13 @@ int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap,
                 int32_t *cvwgt, int32_t *nc_out, int64_t *nnz_out,
                 void *stream);
 
-/* Initial partitioning (Section 3.2): hierarchical multisection (Section
+/* Initial partitioning (Section 4.2): hierarchical multisection (Section
  * 3.1, Algorithm 2) with a breadth-first split as the simple partitioner,
  * run on the host on a copy of the graph.  part_out: device int32[n]. */
 int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h,
                          int32_t *part_out, void *stream);
 
-/* The whole multilevel mapping (Section 3.2): coarsen while n >= 8k (stop
+/* The whole multilevel mapping (Section 4.2): coarsen while n >= 8k (stop
  * when a level would keep more than 95 % of the vertices, at most 64
  * graphs), initial partitioning, then project and refine level by level.
  * part_out: device int32[n].  stats: host, may be NULL. */
@@ -288,7 +291,7 @@ int pm_map_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
               uint64_t seed, int32_t *part_out, pm_map_stats *stats,
               uint32_t flags, const pm_options *opts, void *stream);
 
-/* Induced subgraphs of a partition (Section 3.1, Algorithm 1), all blocks at
+/* Induced subgraphs of a partition (Section 4.1, Algorithm 1), all blocks at
  * once.  Block b's vertices are numbered in ascending input id order; its
  * subgraph keeps every arc whose two ends lie in b, in the input row order,
  * with the local ids and the arc weights.  part: device int32[n], every id in
@@ -304,7 +307,7 @@ int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts,
                  int64_t *xadj_out, int32_t *adjncy_out, int32_t *adjwgt_out,
                  int32_t *vwgt_out, int64_t *arcs_out, void *stream);
 
-/* Hierarchical multisection (Section 3.1, Algorithm 2, the GPU-HM variant):
+/* Hierarchical multisection (Section 4.1, Algorithm 2, the GPU-HM variant):
  * partition into a_l blocks, then every block's induced subgraph into
  * a_{l-1} blocks, down to a_1; the partitioner is pm_map with the one-level
  * hierarchy (a_i) and d = 1.  A subgraph of weight c(V') that ends up in k'

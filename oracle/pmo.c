@@ -15,9 +15,9 @@
  * each function.
  *
  * Parity unpinned (fixed only by this file; no closed form or printed value
- * reaches them): the strong rebalancing's redistribution of rejected movers,
- * the breadth-first split used as initial partitioner, and the coarsening
- * stop on stalls.
+ * reaches them): the breadth-first split used as initial partitioner (beyond
+ * a closed-form path), and the coarsening stop on stalls (the 8k threshold
+ * itself is pinned).
  */
 #include "pmo.h"
 
@@ -133,7 +133,7 @@ uint64_t pmo_hash(uint64_t seed, uint64_t word) {
 #define TAG_REB 0x5245424CULL
 
 /* ======================================================================
- * Unconstrained label propagation (Section 3.2, Algorithm 4)
+ * Unconstrained label propagation (Section 4.2, Algorithm 4)
  * ====================================================================== */
 
 static int cmp_i32(const void *x, const void *y) {
@@ -216,7 +216,7 @@ void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* Label propagation round (Algorithm 4).  With the relaxed first filter of
- * Jet (variants->jet_c_num > 0, Section 3.2 after Algorithm 4), a vertex also
+ * Jet (variants->jet_c_num > 0, Section 4.2 after Algorithm 4), a vertex also
  * enters X when its best gain is negative but -G < floor(c * conn(v,Pi(v))),
  * c = jet_c_num / jet_c_den; the second filter is unchanged. */
 void pmo_lp_round_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
@@ -290,7 +290,7 @@ void pmo_lp_round_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* ======================================================================
- * Rebalancing (Section 3.2, "Rebalancing", Algorithm 5)
+ * Rebalancing (Section 4.2, "Rebalancing", Algorithm 5)
  * ====================================================================== */
 
 /* sigma = L_max - 100 as in the paper, but never below the average block
@@ -347,12 +347,9 @@ static int32_t weight_class(int64_t c) {
  * Strong: the selected movers of every destination b, ordered by (bucket,
  * id), are accepted while c(b) + (weight before them) + c(v) <= L_max.  The
  * rejected ones are reassigned to blocks with residual capacity
- * r_b = L_max - c(b) - accepted_b > 0 without overloading any of them: over
- * the ascending list of those blocks (exclusive prefix C_b), the rejected
- * movers in id order take consecutive intervals of the residual capacity and
- * a mover goes to the block whose interval [C_b, C_b + r_b) contains its
- * whole interval; a second pass does the same for the movers the first one
- * could not place, behind the first pass's range; the rest stay.
+ * r_b = L_max - c(b) - accepted_b > 0 without overloading any of them, by
+ * weight class, heaviest first (the rule is spelled out where it is done);
+ * the ones that find no room stay.
  *
  * moved_out[v] = 1 for every vertex that changed block; part is updated. */
 void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
@@ -364,7 +361,7 @@ void pmo_rebalance(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                   sigma, seed, level, iter, part, moved_out, NULL);
 }
 
-/* J-objective rebalancing (variants->j_rebalance, the variant of Section 3.2
+/* J-objective rebalancing (variants->j_rebalance, the variant of Section 4.2
  * that the authors tried): the loss of a move to block b is the J gain of
  * eq. 1, G_b(v) = sum_x conn(v,x) (D(Pi(v),x) - D(b,x)); the destination is
  * the neighbour block within the cap with the largest J gain (smaller id on
@@ -581,7 +578,7 @@ void pmo_rebalance_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* ======================================================================
- * Overall refinement (Section 3.2, Algorithm 6)
+ * Overall refinement (Section 4.2, Algorithm 6)
  * ====================================================================== */
 
 #define REFINE_PATIENCE 12
@@ -731,7 +728,7 @@ int32_t pmo_refine_trace(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* ======================================================================
- * Heavy-edge matching (Section 3.2, "Matching")
+ * Heavy-edge matching (Section 4.2, "Matching")
  * ====================================================================== */
 
 /* Is edge (v,u1,w1) rated above edge (v,u2,w2)?  The rating is
@@ -927,7 +924,7 @@ static int cmp_carc(const void *x, const void *y) {
   return (a->cv > b->cv) - (a->cv < b->cv);
 }
 
-/* Contraction (Section 2 "Multilevel Graph Partitioning" and Section 3.2
+/* Contraction (Section 2 "Multilevel Graph Partitioning" and Section 4.2
  * "Contraction"): a coarse vertex weighs the sum of its members; every arc
  * (u,v,w) becomes (M(u),M(v),w); arcs with M(u) == M(v) are dropped and
  * parallel arcs are fused with their weights summed.  Rows come out sorted.
@@ -968,7 +965,7 @@ int64_t pmo_contract(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* ======================================================================
- * Initial partitioning (Section 3.2): hierarchical multisection (Section
+ * Initial partitioning (Section 4.2): hierarchical multisection (Section
  * 3.1, Algorithm 2) run on the host with a simple k-way partitioner.
  * ====================================================================== */
 
@@ -1086,7 +1083,7 @@ void pmo_initial_partition(int32_t n, const int64_t *xadj,
 }
 
 /* ======================================================================
- * Multilevel integrated mapping (Section 3.2)
+ * Multilevel integrated mapping (Section 4.2)
  * ====================================================================== */
 
 typedef struct {
@@ -1205,7 +1202,7 @@ int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
 }
 
 /* ======================================================================
- * Hierarchical multisection (Section 3.1, Algorithms 1 and 2)
+ * Hierarchical multisection (Section 4.1, Algorithms 1 and 2)
  * ====================================================================== */
 
 /* The induced subgraphs of a partition into `parts` blocks (Algorithm 1, all

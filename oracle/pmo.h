@@ -9,7 +9,7 @@
  *
  * Conventions (the same for every function):
  *   graph   : CSR with both directions of every undirected edge stored
- *             (Section 2, "CSR Graph Format"): xadj int64[n+1], adjncy
+ *             (Section 3.4, "CSR Graph Format"): xadj int64[n+1], adjncy
  *             int32[nnz], adjwgt int32[nnz] (> 0, symmetric), vwgt int32[n]
  *             (> 0).  All pointers are host pointers.
  *   hierarchy: levels l in [1,8], a[0] = a_1 (PEs per processor, innermost)
@@ -55,7 +55,7 @@ typedef struct {
   double total_seconds;
 } pmo_map_stats;
 
-/* Refinement variants (Section 3.2): all zero = the method as evaluated.
+/* Refinement variants (Section 4.2): all zero = the method as evaluated.
  *   jet_c_num / jet_c_den: with jet_c_num > 0, Jet's relaxed first filter of
  *     label propagation, c = jet_c_num / jet_c_den (jet_c_den > 0);
  *   j_rebalance: rebalancing by the J gain instead of the edge-cut loss. */
@@ -84,7 +84,7 @@ int64_t pmo_gain(const int64_t *xadj, const int32_t *adjncy,
 /* ---- counter-based hash (splitmix64 output function) ---- */
 uint64_t pmo_hash(uint64_t seed, uint64_t word);
 
-/* ---- refinement (Section 3.2, Algorithms 4, 5 and 6) ---- */
+/* ---- refinement (Section 4.2, Algorithms 4, 5 and 6) ---- */
 void pmo_lp_round(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                   const int32_t *adjwgt, int32_t levels, const int32_t *a,
                   const int32_t *d, int32_t *part, uint8_t *lock,
@@ -125,7 +125,7 @@ int32_t pmo_refine(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                    uint64_t seed, int32_t level, int32_t *part,
                    pmo_refine_stats *stats);
 
-/* ---- coarsening (Section 3.2: matching, contraction) ---- */
+/* ---- coarsening (Section 4.2: matching, contraction) ---- */
 int32_t pmo_hem(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                 const int32_t *adjwgt, const int32_t *vwgt, int64_t lmax,
                 uint64_t seed, int32_t level, int32_t *match_out);
@@ -149,7 +149,7 @@ int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                   uint64_t seed, int32_t *part_out, pmo_map_stats *stats,
                   const pmo_variants *var);
 
-/* ---- hierarchical multisection (Section 3.1, Algorithms 1 and 2) ---- */
+/* ---- hierarchical multisection (Section 4.1, Algorithms 1 and 2) ---- */
 int64_t pmo_subgraphs(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                       const int32_t *adjwgt, const int32_t *vwgt, const int32_t *part,
                       int32_t parts, int32_t *vstart, int64_t *estart, int32_t *order,

@@ -1,5 +1,5 @@
 // coarsen.hip -- heavy-edge matching, coarse numbering, contraction and
-// projection for gfx950 (Section 3.2: Matching, Contraction, Uncontraction).
+// projection for gfx950 (Section 4.2: Matching, Contraction, Uncontraction).
 #include <hip/hip_ext.h>
 
 #include "device_util.h"

@@ -1,4 +1,4 @@
-// hm.hip -- induced subgraphs of a partition on the GPU (Section 3.1,
+// hm.hip -- induced subgraphs of a partition on the GPU (Section 4.1,
 // Algorithm 1), for hierarchical multisection.
 //
 // All blocks are built at once: a stable radix sort of the vertex ids by

@@ -1,8 +1,8 @@
 // ip.cpp -- initial partitioning of the coarsest graph on the host.
 //
-// Section 3.2 runs the initial partitioning on the CPU: the coarsest graph is
+// Section 4.2 runs the initial partitioning on the CPU: the coarsest graph is
 // small, so the device would gain nothing.  The method is hierarchical
-// multisection (Section 3.1, Algorithm 2): split the graph into a_l pieces,
+// multisection (Section 4.1, Algorithm 2): split the graph into a_l pieces,
 // each piece into a_{l-1} pieces, and so on; the piece index at level i is
 // the level-i mixed-radix digit of the PE id.  The "simple k-way graph
 // partitioner" used at every split is a breadth-first split: visit the

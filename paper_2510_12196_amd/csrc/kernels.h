@@ -11,10 +11,8 @@ struct Status {
   int64_t maxw;        // heaviest block (max_block)
   int64_t j;           // full J (comm_cost)
   int32_t count;       // generic counter (matches, sources, ...)
-  int32_t count2;
   int32_t n_elig_weak;   // blocks within the weak rebalancing cap (sigma)
   int32_t n_elig_strong; // blocks within L_max
-  int64_t resid_total; // strong rebalancing: total residual capacity
   int64_t aux;         // generic 64-bit result
 };
 
@@ -121,7 +119,7 @@ void comm_cost(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 void block_weights(const DGraph &g, const Hier &h, const int32_t *part, int64_t *w,
                    hipStream_t s);                     // w[0..2^bits)
 
-// ---- refinement variants (Section 3.2) ----------------------------------------
+// ---- refinement variants (Section 4.2) ----------------------------------------
 // jet_num > 0: Jet's relaxed first filter, c = jet_num / jet_den;
 // j_rebalance: rebalancing by the J gain instead of the edge-cut loss.
 struct Variants {
@@ -153,7 +151,9 @@ struct RebalanceBuffers {
   int32_t *key;        // n: (block << 6 | bucket) for sources, -1 otherwise
   int32_t *dest;       // n: chosen destination
   uint8_t *reject;     // n: strong rounds, movers refused by their destination
-  int64_t *pre;        // n: exclusive weight prefix of the refused movers
+  int32_t *rlist;      // n: strong rounds, the refused movers in id order
+  int32_t *rcount;     // 1: their number
+  int64_t *resid;      // 2^bits: residual capacity per code
   int32_t *elig_weak;  // 2^bits: blocks within sigma, ascending
   int32_t *elig_strong;// 2^bits: blocks within L_max, ascending
   int64_t *bw;         // 8 x 2^bits x 64 bucket weights (kept zero between rounds)
@@ -163,8 +163,8 @@ struct RebalanceBuffers {
   int32_t *tcrit;      // 2^bits
   int64_t *tneed;      // 2^bits
   int32_t *tsum;       // 2^bits x ntiles
-  int64_t *rstart;     // 2^bits: residual prefix
-  int32_t *rblock;     // 2^bits: blocks with residual > 0
+  int64_t *rstart;     // 2^bits: first position of a block in a weight class
+  int32_t *rblock;     // 2^bits: the blocks offering positions in that class
   int32_t tile;        // ids per tile
   int32_t ntiles;
 };
@@ -184,7 +184,7 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
                      const Variants &var = Variants{});
 
-// ---- induced subgraphs (Section 3.1, Algorithm 1) ----------------------------
+// ---- induced subgraphs (Section 4.1, Algorithm 1) ----------------------------
 // Layout of all blocks' subgraphs, concatenated in block order (device
 // arrays): vstart[parts+1] first position of each block, estart[parts+1]
 // first arc, order[n] original id per position, xadj[n+parts] block b's
@@ -212,7 +212,7 @@ void compose_ids(int32_t n, const int32_t *orig, const int32_t *order, int32_t *
 void scatter_blocks(int32_t n, const int32_t *orig, const int32_t *part, int32_t base,
                     int32_t *part_out, hipStream_t s);
 
-// Hierarchical multisection (Section 3.1, Algorithm 2) with the multilevel
+// Hierarchical multisection (Section 4.1, Algorithm 2) with the multilevel
 // mapper as partitioner; part_out: device ids in [0, k).  Returns PM_OK or
 // PM_WARN_IMBALANCED (some partitioning call ended above its L_max).
 int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint64_t seed,

@@ -6,7 +6,7 @@
 // per lane, so a single load instruction of the wave streams the adjacent rows
 // of 64/G vertices; vertices of degree > 64 get a whole workgroup that
 // aggregates the neighbour-block connectivity in an LDS histogram over block
-// codes (the per-vertex connectivity structure of Section 3.2, kept in LDS
+// codes (the per-vertex connectivity structure of Section 4.2, kept in LDS
 // instead of a global hash table).  All arithmetic is integer; sums are
 // order-independent, and every choice has a total-order tie-break, so results
 // do not depend on thread scheduling or on the order of entries in a row.
@@ -1821,77 +1821,148 @@ __global__ __launch_bounds__(kThreads) void k_kp_final(KPArgs A, int flat) {
   else kp_walk(A, (int32_t)blockIdx.x - flat);
 }
 
-// residual capacities r_b = L_max - c(b) - accepted_b > 0, ascending blocks;
-// folds (and clears) the accepted-weight stripes.  One workgroup; thread i
-// owns the codes [i*per, (i+1)*per), per <= 32.
-__global__ __launch_bounds__(kThreads) void k_residual(Hier h, const int64_t *w, int64_t *acc,
-                                                       int64_t lmax, int64_t *rstart,
-                                                       int32_t *rblock, Status *st) {
+// smallest q with c <= 2^q (c >= 1): the weight class of a refused mover
+__device__ __forceinline__ int32_t weight_class(int32_t c) {
+  return c <= 1 ? 0 : 32 - __clz((uint32_t)(c - 1));
+}
+
+// Strong rebalancing, the movers refused by their destination (list[0..
+// *count), ascending ids).  One workgroup.  First the accepted-weight stripes
+// are folded (and cleared) into the residual capacity of every code,
+// resid[c] = L_max - c(b) - accepted_b (0 for codes of no block).  Then the
+// refused movers are placed by weight class q = ceil(log2 c(v)), heaviest
+// class first: in class q a block with residual r >= 2^q offers the
+// r - 2^q + 1 positions [C_b, C_b + r - 2^q + 1) of a prefix over ascending
+// blocks, and a mover of the class whose exclusive weight prefix R (over the
+// class's movers in id order) falls into them goes there; R beyond the last
+// position leaves it where it is.  The movers a block receives in one class
+// start inside its positions, so they weigh at most r: no block ends above
+// L_max.  The residuals shrink by what each block received before the next
+// class.  Positions of a class are kept compacted in sstart / sblock.
+__global__ __launch_bounds__(kThreads) void k_place_rejects(Hier h, const int64_t *w, int64_t *acc,
+                                                            int64_t lmax, const int32_t *list,
+                                                            const int32_t *count,
+                                                            const int32_t *vwgt, int64_t *resid,
+                                                            int64_t *sstart, int32_t *sblock,
+                                                            int32_t *target, uint8_t *moved) {
+  extern __shared__ uint32_t got[];  // weight received per code in the current class
   __shared__ BlockScratch sc;
   __shared__ int64_t wave_tot[kThreads / 64];
+  __shared__ uint32_t cls_mask;
+  __shared__ int32_t nslots;
+  __shared__ int64_t npos;
+  __shared__ uint32_t chunk_total;
   const int32_t ncodes = 1 << h.bits;
   const int per = (ncodes + kThreads - 1) / kThreads;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < ncodes ? lo + per : ncodes;
-  int64_t r[(1 << kMaxCodeBits) / kThreads];
-  uint32_t cnt = 0;
-  int64_t sum = 0;
   for (int c = lo; c < hi; ++c) {
     int64_t a = 0;
     for (int s = 0; s < kBucketStripes; ++s) {
       a += acc[(size_t)s * ncodes + c];
       acc[(size_t)s * ncodes + c] = 0;
     }
-    const int64_t x = code_valid(h, (uint32_t)c) ? lmax - w[c] - a : 0;
-    r[c - lo] = x;
-    if (x > 0) {
-      ++cnt;
-      sum += x;
-    }
+    resid[c] = code_valid(h, (uint32_t)c) ? lmax - w[c] - a : 0;
+    got[c] = 0;
   }
-  uint32_t pos = block_excl_scan(cnt, sc);
+  if (threadIdx.x == 0) cls_mask = 0;
+  __syncthreads();
+  const int32_t L = *count;
+  uint32_t m = 0;
+  for (int32_t i = threadIdx.x; i < L; i += kThreads) m |= 1u << weight_class(vwgt[list[i]]);
+  m = (uint32_t)gor<64>((int32_t)m);
+  if ((threadIdx.x & 63) == 0 && m) atomicOr(&cls_mask, m);
+  __syncthreads();
+  const uint32_t mask = cls_mask;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int64_t incl = sum;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
-    if (lane >= o) incl += y;
-  }
-  __syncthreads();
-  if (lane == 63) wave_tot[wave] = incl;
-  __syncthreads();
-  int64_t off = 0;
-  for (int i = 0; i < wave; ++i) off += wave_tot[i];
-  int64_t runv = off + incl - sum;
-  for (int c = lo; c < hi; ++c) {
-    if (r[c - lo] > 0) {
-      rstart[pos] = runv;
-      rblock[pos] = c;
-      ++pos;
-      runv += r[c - lo];
+  for (int q = 31; q >= 0; --q) {
+    if (!((mask >> q) & 1u)) continue;
+    const int64_t unit = int64_t(1) << q;
+    // positions of the class: blocks with r >= 2^q, ascending
+    uint32_t cnt = 0;
+    int64_t sum = 0;
+    for (int c = lo; c < hi; ++c) {
+      const int64_t r = resid[c];
+      if (r >= unit) {
+        ++cnt;
+        sum += r - unit + 1;
+      }
     }
+    uint32_t pos = block_excl_scan(cnt, sc);
+    int64_t incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    int64_t run = incl - sum;
+    for (int i = 0; i < wave; ++i) run += wave_tot[i];
+    for (int c = lo; c < hi; ++c) {
+      const int64_t r = resid[c];
+      if (r >= unit) {
+        sstart[pos] = run;
+        sblock[pos] = c;
+        ++pos;
+        run += r - unit + 1;
+      }
+    }
+    if (threadIdx.x == kThreads - 1) {
+      nslots = (int32_t)pos;
+      npos = run;
+    }
+    __syncthreads();
+    const int32_t ns = nslots;
+    const int64_t total = npos;
+    // the class's movers in id order, 16 consecutive list entries per thread
+    int64_t base = 0;
+    for (int32_t c0 = 0; c0 < L; c0 += kWalkChunk) {
+      const int32_t i0 = c0 + (int32_t)threadIdx.x * kWalkPer;
+      uint32_t cw[kWalkPer];
+      uint32_t mem = 0, s = 0;
+#pragma unroll
+      for (int i = 0; i < kWalkPer; ++i) {
+        cw[i] = 0;
+        if (i0 + i < L) {
+          const int32_t c = vwgt[list[i0 + i]];
+          if (weight_class(c) == q) {
+            cw[i] = (uint32_t)c;
+            mem |= 1u << i;
+          }
+        }
+        s += cw[i];
+      }
+      const uint32_t excl = block_excl_scan(s, sc);
+      if (threadIdx.x == kThreads - 1) chunk_total = excl + s;
+      int64_t R = base + excl;
+#pragma unroll
+      for (int i = 0; i < kWalkPer; ++i) {
+        if (!(mem & (1u << i))) continue;
+        if (R < total) {
+          int32_t a = 0, b = ns - 1;  // largest j with sstart[j] <= R
+          while (a < b) {
+            const int32_t mid = (a + b + 1) >> 1;
+            if (sstart[mid] <= R) a = mid;
+            else b = mid - 1;
+          }
+          const int32_t blk = sblock[a];
+          const int32_t v = list[i0 + i];
+          target[v] = blk;
+          moved[v] = 1;
+          atomicAdd(&got[blk], cw[i]);
+        }
+        R += cw[i];
+      }
+      __syncthreads();
+      base += chunk_total;
+      __syncthreads();  // chunk_total is rewritten by the next chunk
+    }
+    for (int c = lo; c < hi; ++c) {
+      resid[c] -= got[c];
+      got[c] = 0;
+    }
+    __syncthreads();
   }
-  if (threadIdx.x == kThreads - 1) {
-    st->count2 = (int32_t)pos;
-    st->resid_total = runv;
-  }
-}
-
-// rejected movers (id order, exclusive weight prefix R) -> residual slots
-__global__ void k_assign_rejects(int32_t n, const uint8_t *reject, const int64_t *pre,
-                                 const int64_t *rstart, const int32_t *rblock,
-                                 const Status *st, int32_t *target, uint8_t *moved) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= n || !reject[v]) return;
-  const int64_t R = pre[v];
-  if (R >= st->resid_total) return;
-  int32_t lo = 0, hi = st->count2 - 1;  // largest j with rstart[j] <= R
-  while (lo < hi) {
-    const int32_t mid = (lo + hi + 1) >> 1;
-    if (rstart[mid] <= R) lo = mid;
-    else hi = mid - 1;
-  }
-  target[v] = rblock[lo];
-  moved[v] = 1;
 }
 
 RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_t s) {
@@ -1904,7 +1975,9 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
   rb.key = ar.alloc_n<int32_t>(n);
   rb.dest = ar.alloc_n<int32_t>(n);
   rb.reject = ar.alloc_n<uint8_t>(n);
-  rb.pre = ar.alloc_n<int64_t>(n);
+  rb.rlist = ar.alloc_n<int32_t>(n);
+  rb.rcount = ar.alloc_n<int32_t>(1);
+  rb.resid = ar.alloc_n<int64_t>(ncodes);
   rb.elig_weak = ar.alloc_n<int32_t>(ncodes);
   rb.elig_strong = ar.alloc_n<int32_t>(ncodes);
   rb.bw = ar.alloc_n<int64_t>((size_t)kBucketStripes * ncodes * kBuckets);
@@ -2023,12 +2096,10 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
   K.pass = KP_ACCEPT;
   K.strong = 0;
   keyed_prefix(K, s);
-  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kThreads), 0, s, h, w, rb.acc, lmax, rb.rstart,
-                     rb.rblock, st_dev);
-  PM_LAUNCH_CHECK();
-  scan_excl_masked(ar, rb.reject, g.c, rb.pre, n, s);
-  hipLaunchKernelGGL(k_assign_rejects, dim3(grid_for(n)), dim3(kThreads), 0, s, (int32_t)n,
-                     rb.reject, rb.pre, rb.rstart, rb.rblock, st_dev, target, moved);
+  select_indices(ar, rb.reject, rb.rlist, rb.rcount, n, s);
+  hipLaunchKernelGGL(k_place_rejects, dim3(1), dim3(kThreads), sizeof(uint32_t) * (size_t)ncodes,
+                     s, h, w, rb.acc, lmax, rb.rlist, rb.rcount, g.c, rb.resid, rb.rstart,
+                     rb.rblock, target, moved);
   PM_LAUNCH_CHECK();
 }
 

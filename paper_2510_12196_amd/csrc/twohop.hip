@@ -1,6 +1,6 @@
 // twohop.hip -- two-hop matching (leaf, twin and relative categories) that
 // follows heavy-edge matching while 75 % or fewer of the vertices are matched
-// (Section 3.2, Matching).  Every category forms groups of unmatched vertices
+// (Section 4.2, Matching).  Every category forms groups of unmatched vertices
 // -- leaves by their only neighbour, twins by their neighbourhood, relatives
 // by a common "matchmaker" neighbour of smallest (degree, id) -- and pairs
 // the members of each group in id order.

@@ -1,4 +1,4 @@
-"""Hierarchical multisection on the GPU (Section 3.1, Algorithms 1 and 2):
+"""Hierarchical multisection on the GPU (Section 4.1, Algorithms 1 and 2):
 the induced subgraphs of a partition and the whole recursion, exactly as the
 oracle computes them."""
 import sys

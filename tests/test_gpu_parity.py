@@ -165,6 +165,71 @@ def test_weak_rebalance_hand_example_on_gpu(pm, torch_mod):
     assert host(part).tolist() == fx["part_out"]
 
 
+def test_strong_rebalance_hand_example_on_gpu(pm, torch_mod):
+    say("strong rebalance fixture")
+    fx = golden("strong_rebalance_weighted.json")
+    g = graph_from_fixture(fx)
+    part = t32(torch_mod, fx["part_in"])
+    lm = fx["lmax"]
+    mv = pm.pm_rebalance(dev(pm, g), fx["a"], fx["d"], part, True, lm, lm, 1, 0, 1)
+    assert host(mv).tolist() == fx["moved"]
+    assert host(part).tolist() == fx["part_out"]
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_heavy_vertex_boundary_on_gpu(pm, pmo, torch_mod, strong):
+    say("heavy vertex fixture", "strong" if strong else "weak")
+    fx = golden("heavy_vertex_boundary.json")
+    g = graph_from_fixture(fx)
+    k = k_of(fx["a"])
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, fx["eps"])
+    sg = pmo.sigma(lm, total, k)
+    part = t32(torch_mod, fx["part_in"])
+    mv = pm.pm_rebalance(dev(pm, g), fx["a"], fx["d"], part, strong, lm, sg, 1, 0, 1)
+    tag = "strong" if strong else "weak"
+    assert host(mv).tolist() == fx[tag + "_moved"]
+    assert host(part).tolist() == fx[tag + "_part_out"]
+
+
+def _reweighted(g, seed, wlog):
+    """g with vertex weights floor(2^U(0, wlog)): refused movers of a strong
+    round then fall into many weight classes."""
+    rng = np.random.default_rng(seed)
+    vw = np.floor(2.0 ** rng.uniform(0, wlog, g.n)).astype(np.int32)
+    src = np.repeat(np.arange(g.n), np.diff(g.xadj))
+    m = src < g.adjncy
+    return gen.from_edges(g.n, src[m], g.adjncy[m], g.adjwgt[m], vw)
+
+
+@pytest.mark.parametrize("name,a,frac,wlog", [("rmat14", (4, 16, 8), 0.1, 12),
+                                              ("rmat17", (4, 16, 8), 0.1, 12),
+                                              ("rmat17", (4, 16, 8), 0.2, 4),
+                                              ("rgg17", (4, 8, 8), 0.3, 8),
+                                              ("rgg14", (4, 8, 3), 0.3, 10)])
+def test_strong_rebalance_weight_classes(pm, pmo, torch_mod, name, a, frac, wlog):
+    """Strong rounds whose refused movers span up to 13 weight classes and
+    (rmat17) more than one 4096-entry chunk of the placement walk; the
+    result equals the oracle and no block at or below L_max before the round
+    ends above it."""
+    g = _reweighted(gen.get(name).graph(), 5, wlog)
+    k = k_of(a)
+    d = (1, 10, 100)
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    part = gen.random_mapping(g.n, k, 11)
+    part[: int(g.n * frac)] = 1
+    say("strong classes", name, a, frac, wlog)
+    exp_part, exp_moved = pmo.rebalance(g, k, part, True, lm, lm, 77, 2, 1)
+    part_d = t32(torch_mod, part)
+    mv = pm.pm_rebalance(dev(pm, g), a, d, part_d, True, lm, lm, 77, 2, 1)
+    assert np.array_equal(host(mv), exp_moved)
+    assert np.array_equal(host(part_d), exp_part)
+    w0 = np.bincount(part, weights=g.vwgt, minlength=k)
+    w1 = np.bincount(exp_part, weights=g.vwgt, minlength=k)
+    assert not np.any((w0 <= lm) & (w1 > lm))
+
+
 # ---------------------------------------------------------------------------
 # refinement (Algorithm 6)
 # ---------------------------------------------------------------------------

@@ -1,4 +1,4 @@
-"""Refinement variants (Section 3.2): Jet's relaxed first filter and
+"""Refinement variants (Section 4.2): Jet's relaxed first filter and
 rebalancing by the J gain, on the GPU against the oracle, exactly."""
 import sys
 

@@ -482,7 +482,7 @@ def test_row_order_invariance(pmo, name):
 
 
 # ----------------------------------------------------------------------------
-# matching and contraction (Section 3.2)
+# matching and contraction (Section 4.2)
 # ----------------------------------------------------------------------------
 
 def test_two_hop_matching_properties(pmo):
@@ -713,7 +713,7 @@ def test_map_balance_and_levels(pmo, name, seed):
 
 
 # ----------------------------------------------------------------------------
-# refinement variants (Section 3.2): Jet's relaxed first filter, J-objective
+# refinement variants (Section 4.2): Jet's relaxed first filter, J-objective
 # rebalancing
 # ----------------------------------------------------------------------------
 
@@ -801,7 +801,7 @@ def test_j_rebalance_destinations_maximise_the_gain(pmo):
 
 
 # ----------------------------------------------------------------------------
-# hierarchical multisection (Section 3.1, Algorithms 1 and 2)
+# hierarchical multisection (Section 4.1, Algorithms 1 and 2)
 # ----------------------------------------------------------------------------
 
 def test_subgraphs_hand_example(pmo):
