@@ -118,7 +118,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rgg20")
+    ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise pass over 512 MiB (known traffic: 512 MiB "
@@ -243,26 +243,111 @@ def main():
     }
 
     if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        log("cpu baseline: oracle pm_map, seed 1, single thread")
-        t = time.perf_counter()
-        orc, opart, ost = oracle.map_graph(g, w.a, w.d, w.eps, 1)
-        ocpu = time.perf_counter() - t
-        arcs = sum(ost.level_iterations[i] * ost.level_nnz[i] for i in range(ost.levels))
-        parity = bool(np.array_equal(first_part.cpu().numpy(), opart)) and orc == stats[0][0]
-        line["cpu_baseline"] = {
-            "value": round(arcs / ost.refine_seconds / 1e9, 5) if ost.refine_seconds > 0 else None,
-            "unit": "GTEPS",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"one full map of {w.name} (seed 1); refinement {ost.refine_seconds:.2f}s "
-                      f"of {ocpu:.2f}s total",
-            "map_ms": round(ocpu * 1e3, 1),
-        }
-        line["parity_seed1"] = parity
-        log(f"oracle: {ocpu:.2f}s, parity {parity}")
+        if w.name == "rmat22":
+            line["cpu_baseline"] = cpu_baseline_rounds(w, g, dg)
+        else:
+            import oracle
+            oracle.build(force=False)
+            log("cpu baseline: oracle pm_map, seed 1, one pinned thread")
+            with pinned_to_one_cpu() as cpu:
+                t = time.perf_counter()
+                orc, opart, ost = oracle.map_graph(g, w.a, w.d, w.eps, 1)
+                ocpu = time.perf_counter() - t
+            arcs = sum(ost.level_iterations[i] * ost.level_nnz[i] for i in range(ost.levels))
+            parity = bool(np.array_equal(first_part.cpu().numpy(), opart)) and orc == stats[0][0]
+            line["cpu_baseline"] = {
+                "value": round(arcs / ost.refine_seconds / 1e9, 5) if ost.refine_seconds > 0
+                else None,
+                "unit": "GTEPS",
+                "cores": 1,
+                "kind": "oracle",
+                "sample": f"one full map of {w.name} (seed 1); refinement "
+                          f"{ost.refine_seconds:.2f}s of {ocpu:.2f}s total",
+                "map_ms": round(ocpu * 1e3, 1),
+                "parity_with_gpu": parity,
+                **host_info(cpu),
+            }
+            log(f"oracle: {ocpu:.2f}s, parity {parity}")
     print(json.dumps(line), flush=True)
+
+
+def host_info(cpu):
+    """The host the CPU baseline ran on: the core it was pinned to, the
+    logical CPU count and the CPU model."""
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"pinned_cpu": cpu, "nproc": os.cpu_count(), "cpu_model": model}
+
+
+class pinned_to_one_cpu:
+    """Runs the block with the calling thread bound to one CPU of the
+    process's affinity set (the oracle is single-threaded C called through
+    ctypes, so it runs on this thread); restores the affinity afterwards."""
+
+    def __enter__(self):
+        self.old = os.sched_getaffinity(0)
+        cpu = sorted(self.old)[0]
+        os.sched_setaffinity(0, {cpu})
+        return cpu
+
+    def __exit__(self, *exc):
+        os.sched_setaffinity(0, self.old)
+        return False
+
+
+def cpu_baseline_rounds(w, g, dg, reps=3):
+    """Oracle baseline on a bounded sample of the R-MAT workload: `reps` weak
+    and `reps` strong rebalancing rounds (Algorithm 5) over the whole
+    level-0 graph, each from a mapping where one block holds a tenth of the
+    vertices, on one pinned core.  Every round is also run on the GPU and
+    compared element by element.  (The oracle's label-propagation round
+    evaluates equation (1) for every pair of neighbour blocks of a vertex and
+    takes minutes on this graph from a random mapping, so it is left out.)"""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+    import paper_2510_12196_amd as pm
+    oracle.build(force=False)
+    total = int(g.vwgt.sum())
+    lm = oracle.lmax(total, w.k, w.eps)
+    sg = oracle.sigma(lm, total, w.k)
+    secs = 0.0
+    rounds = 0
+    equal = True
+    with pinned_to_one_cpu() as cpu:
+        for r in range(reps):
+            part = gen.random_mapping(g.n, w.k, 0xB0 + r)
+            part[: g.n // 10] = 1 + r
+            for strong in (False, True):
+                log(f"cpu baseline: oracle {'strong' if strong else 'weak'} round {r}")
+                t = time.perf_counter()
+                exp_part, exp_moved = oracle.rebalance(g, w.k, part, strong, lm, sg, 7, 0, 1 + r)
+                secs += time.perf_counter() - t
+                rounds += 1
+                pd = torch.from_numpy(part.copy()).cuda()
+                mv = pm.pm_rebalance(dg, w.a, w.d, pd, strong, lm, sg, 7, 0, 1 + r)
+                equal &= bool(np.array_equal(mv.cpu().numpy(), exp_moved) and
+                              np.array_equal(pd.cpu().numpy(), exp_part))
+    log(f"oracle: {rounds} rounds in {secs:.2f}s, equal to the GPU: {equal}")
+    return {
+        "value": round(rounds * g.nnz / secs / 1e9, 5),
+        "unit": "GTEPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{reps} weak + {reps} strong rebalancing rounds over the whole level-0 graph "
+                  f"of {w.name} ({g.nnz} arcs each) in {secs:.2f}s; the oracle's "
+                  "label-propagation round is left out (minutes on this graph)",
+        "parity_with_gpu": equal,
+        **host_info(cpu),
+    }
 
 
 def bench_hm(args, w, g, dg):
@@ -316,12 +401,14 @@ def bench_hm(args, w, g, dg):
     if not args.no_cpu_baseline:
         import oracle
         oracle.build(force=False)
-        log("cpu baseline: oracle hm, seed 1, single thread")
-        t = time.perf_counter()
-        orc, opart = oracle.hm(g, w.a, w.eps, 1)
-        ocpu = time.perf_counter() - t
+        log("cpu baseline: oracle hm, seed 1, one pinned thread")
+        with pinned_to_one_cpu() as cpu:
+            t = time.perf_counter()
+            orc, opart = oracle.hm(g, w.a, w.eps, 1)
+            ocpu = time.perf_counter() - t
         line["cpu_baseline"] = {"value": round(ocpu * 1e3, 1), "unit": "ms", "cores": 1,
-                                "kind": "oracle", "sample": f"one hm of {w.name} (seed 1)"}
+                                "kind": "oracle", "sample": f"one hm of {w.name} (seed 1)",
+                                **host_info(cpu)}
         line["parity_seed1"] = bool(orc == first[0] and np.array_equal(first[1], opart))
         log(f"oracle: {ocpu:.2f}s, parity {line['parity_seed1']}")
     print(json.dumps(line), flush=True)

@@ -95,7 +95,7 @@ std::map<int, std::vector<Arena *>> g_free;   // idle arenas per device
 std::vector<Arena *> g_all;                   // every arena ever made
 }  // namespace
 
-ArenaLease::ArenaLease() {
+ArenaLease::ArenaLease(hipStream_t s) : s_(s) {
   int dev = 0;
   PM_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(g_pool_mutex);
@@ -111,6 +111,7 @@ ArenaLease::ArenaLease() {
 }
 
 ArenaLease::~ArenaLease() {
+  if (hipStreamSynchronize(s_) != hipSuccess) (void)hipGetLastError();
   arena_->reset();
   std::lock_guard<std::mutex> lock(g_pool_mutex);
   g_free[arena_->device()].push_back(arena_);

@@ -184,9 +184,8 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   int32_t *slist = n >= rmin && n > 0 ? ar.alloc_n<int32_t>(n) : nullptr;
   int32_t *soff = slist ? ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
 
-  hipEvent_t ev0, ev1;
-  PM_HIP(hipEventCreate(&ev0));
-  PM_HIP(hipEventCreate(&ev1));
+  EventSet evs;
+  hipEvent_t ev0 = evs.make(), ev1 = evs.make();
   PM_HIP(hipEventRecord(ev0, s));
 
   if (n > 0) PM_HIP(hipMemcpyAsync(cur, best, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
@@ -272,8 +271,6 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   PM_HIP(hipEventSynchronize(ev1));
   float ms = 0.f;
   PM_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
 
   R.st.iterations = bodies;
   R.st.j_final = j_best;
@@ -579,7 +576,7 @@ int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part, 
     if (!j_out || (!part && g && g->n > 0)) throw Error(PM_EINVAL, "NULL output or mapping");
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     hipStream_t s = as_stream(stream);
     Ctx cx(*lease, s);
     int64_t total = 0;
@@ -606,7 +603,7 @@ int pm_block_weights(const pm_graph *g, const pm_hierarchy *h, const int32_t *pa
     if (!w_out || (!part && g && g->n > 0)) throw Error(PM_EINVAL, "NULL output or mapping");
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     hipStream_t s = as_stream(stream);
     Ctx cx(*lease, s);
     require_ids(cx, hh, part, dg.n);
@@ -640,7 +637,7 @@ int pm_lp_round_ex(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint
     const Hier hh = make_hier(h);
     if (dg.n > 0 && (!part || !lock || !target_out || !gain_out || !moved_out))
       throw Error(PM_EINVAL, "NULL array");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     hipStream_t s = as_stream(stream);
     Ctx cx(*lease, s);
     int64_t total = 0;
@@ -679,7 +676,7 @@ int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong, in
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     if (dg.n > 0 && (!part || !moved_out)) throw Error(PM_EINVAL, "NULL array");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     Arena &ar = *lease;
     hipStream_t s = as_stream(stream);
     Ctx cx(ar, s);
@@ -723,7 +720,7 @@ int pm_refine_ex(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t 
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     if (dg.n > 0 && !part) throw Error(PM_EINVAL, "NULL mapping");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     Arena &ar = *lease;
     hipStream_t s = as_stream(stream);
     Ctx cx(ar, s);
@@ -750,7 +747,7 @@ int pm_hem(const pm_graph *g, int64_t lmax, uint64_t seed, int32_t level, int32_
     check_device();
     const DGraph dg = view(g);
     if (dg.n > 0 && !match_out) throw Error(PM_EINVAL, "NULL output");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     Arena &ar = *lease;
     hipStream_t s = as_stream(stream);
     Ctx cx(ar, s);
@@ -778,7 +775,7 @@ int pm_contract(const pm_graph *g, const int32_t *match, int32_t *cmap, int64_t 
     const DGraph dg = view(g);
     if (dg.n > 0 && (!match || !cmap || !cxadj || !cvwgt || !nc_out || !nnz_out))
       throw Error(PM_EINVAL, "NULL array");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     Arena &ar = *lease;
     hipStream_t s = as_stream(stream);
     Ctx cx(ar, s);
@@ -807,7 +804,7 @@ int pm_initial_partition(const pm_graph *g, const pm_hierarchy *h, int32_t *part
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     if (dg.n > 0 && !part_out) throw Error(PM_EINVAL, "NULL output");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     hipStream_t s = as_stream(stream);
     Ctx cx(*lease, s);
     run_initial(cx, dg, hh, part_out);
@@ -827,7 +824,7 @@ int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts, int32_t 
     if (!vstart || !estart || !xadj_out) throw Error(PM_EINVAL, "NULL output");
     if (dg.n > 0 && (!part || !order || !vwgt_out)) throw Error(PM_EINVAL, "NULL array");
     if (dg.nnz > 0 && (!adjncy_out || !adjwgt_out)) throw Error(PM_EINVAL, "NULL array");
-    ArenaLease lease;
+    ArenaLease lease(as_stream(stream));
     hipStream_t s = as_stream(stream);
     Ctx cx(*lease, s);
     check_parts(part, dg.n, parts, &cx.dev->count, s);
@@ -856,7 +853,7 @@ int pm_map_hm(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t see
     if (j_out) {
       *j_out = 0;
       if (dg.n > 0) {
-        ArenaLease lease;
+        ArenaLease lease(s);
         Ctx cx(*lease, s);
         int32_t *codes = part_out;
         if (!hh.pow2) {
@@ -901,7 +898,7 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     if (dg.n > 0 && !part_out) throw Error(PM_EINVAL, "NULL output");
-    ArenaLease lease;
+    ArenaLease lease(stream);
     Arena &ar = *lease;
     hipStream_t s = stream;
     Ctx cx(ar, s);
@@ -918,12 +915,10 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
       ~TimerScope() { tl_timer = nullptr; }
     } timer_scope((flags & PM_FLAG_KERNEL_TIMES) ? &timer : nullptr);
 
-    std::vector<hipEvent_t> evs;
+    EventSet evs;
     auto mark_event = [&]() {
-      hipEvent_t e;
-      PM_HIP(hipEventCreate(&e));
+      hipEvent_t e = evs.make();
       PM_HIP(hipEventRecord(e, s));
-      evs.push_back(e);
       return e;
     };
     struct Span { hipEvent_t a, b; double *acc; };
@@ -1015,7 +1010,6 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
     }
-    for (auto e : evs) (void)hipEventDestroy(e);
     if (flags & PM_FLAG_KERNEL_TIMES) timer.finish(st.kernel_launches, st.kernel_ms, st.kernel_bytes);
     st.total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)

@@ -1,4 +1,4 @@
-// multisection.cpp -- hierarchical multisection on the GPU (Section 3.1,
+// multisection.cpp -- hierarchical multisection on the GPU (Section 4.1,
 // Algorithm 2): split the graph into a_l blocks with the adaptive imbalance
 // of equation (2), build the induced subgraphs, split each into a_{l-1}
 // blocks, and so on down to a_1.  The graph partitioner is the multilevel
@@ -80,7 +80,7 @@ int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint
   int dev = 0;
   PM_HIP(hipGetDevice(&dev));
 
-  ArenaLease lease;  // level-wide arrays of every level
+  ArenaLease lease(s);  // level-wide arrays of every level
   Arena &ar = *lease;
   int64_t cv = 0;
   validate_graph(ar, dg, false, &cv, s);
@@ -151,14 +151,14 @@ int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint
             scatter_blocks(tk.n, tk.orig, pt, (int32_t)tk.base, part_out, ws);
             PM_HIP(hipStreamSynchronize(ws));
           } else {
-            ArenaLease tmp;
+            ArenaLease tmp(ws);
             const DGraph g{tk.n, tk.nnz, tk.xadj, tk.adj, tk.w, tk.c};
             SubgraphOut o{vstart + t * (ai + 1), estart + t * (ai + 1), order + tk.voff,
                           xadj + tk.voff + t * ai, adj + tk.eoff, wgt + tk.eoff, vw + tk.voff,
                           wsum + t * ai};
             subgraphs(*tmp, g, pt, ai, o, ws);
             compose_ids(tk.n, tk.orig, order + tk.voff, orig + tk.voff, ws);
-            PM_HIP(hipStreamSynchronize(ws));  // before the lease hands tmp back
+            PM_HIP(hipStreamSynchronize(ws));
           }
         } catch (const Error &e) {
           (void)hipGetLastError();

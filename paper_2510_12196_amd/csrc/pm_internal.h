@@ -190,15 +190,38 @@ class Arena {
   int64_t publish_seq_ = 0;
 };
 
-// Acquire an arena for the current device for the duration of a call.
+// Acquire an arena for the current device for the duration of a call whose
+// work runs on stream s.  On release (also when the call throws) the stream
+// is synchronised first, so no queued kernel still writes into the arena when
+// another call leases it.
 class ArenaLease {
  public:
-  ArenaLease();
+  explicit ArenaLease(hipStream_t s);
   ~ArenaLease();
+  ArenaLease(const ArenaLease &) = delete;
+  ArenaLease &operator=(const ArenaLease &) = delete;
   Arena &operator*() { return *arena_; }
   Arena *operator->() { return arena_; }
  private:
   Arena *arena_;
+  hipStream_t s_;
+};
+
+// Events that are destroyed with their owner (also on an exception).
+struct EventSet {
+  std::vector<hipEvent_t> ev;
+  hipEvent_t make() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(PM_EHIP, "hipEventCreate failed");
+    }
+    ev.push_back(e);
+    return e;
+  }
+  ~EventSet() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
 };
 
 void release_all_arenas();

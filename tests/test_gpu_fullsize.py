@@ -178,3 +178,29 @@ def test_rmat22_lp_round_sampled(pm, pmo, rmat22):
             assert (tgt[v], gain[v]) == (cand[best], gains[best]), v
         else:
             assert gain[v] == NIN and tgt[v] == part0[v], v
+
+
+@pytest.mark.parametrize("strong", [False, True])
+def test_rmat22_rebalance_round_full_parity(pm, pmo, rmat22, strong):
+    """One weak / strong rebalancing round on the whole level-0 graph of
+    rmat22 (one block holding a tenth of the vertices besides a uniform
+    random mapping), element by element against the oracle, and the strong
+    round leaves no block above L_max that was at or below it."""
+    import torch
+    w, g = rmat22
+    dg = pm.DeviceGraph.from_host(g)
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, w.k, w.eps)
+    sg = pmo.sigma(lm, total, w.k)
+    part = gen.random_mapping(g.n, w.k, 0xB2)
+    part[: g.n // 10] = 1
+    say("rmat22 rebalance", "strong" if strong else "weak")
+    exp_part, exp_moved = pmo.rebalance(g, w.k, part, strong, lm, sg, 7, 0, 1)
+    pd = torch.from_numpy(part.copy()).cuda()
+    mv = pm.pm_rebalance(dg, w.a, w.d, pd, strong, lm, sg, 7, 0, 1)
+    assert np.array_equal(host(mv), exp_moved)
+    assert np.array_equal(host(pd), exp_part)
+    if strong:
+        w0 = pmo.block_weights(g, part, w.k)
+        w1 = pmo.block_weights(g, exp_part, w.k)
+        assert not np.any((w0 <= lm) & (w1 > lm))
