@@ -163,8 +163,8 @@ struct RebalanceBuffers {
   int32_t *tcrit;      // 2^bits
   int64_t *tneed;      // 2^bits
   int32_t *tsum;       // 2^bits x ntiles
-  int64_t *rstart;     // 2^bits: first position of a block in a weight class
-  int32_t *rblock;     // 2^bits: the blocks offering positions in that class
+  int64_t *rstart;     // 2^bits: first position of a code in a weight class
+  int32_t *rweight;    // n: weights of the refused movers, in list order
   int32_t tile;        // ids per tile
   int32_t ntiles;
 };

@@ -1827,33 +1827,82 @@ __device__ __forceinline__ int32_t weight_class(int32_t c) {
 }
 
 // Strong rebalancing, the movers refused by their destination (list[0..
-// *count), ascending ids).  One workgroup.  First the accepted-weight stripes
-// are folded (and cleared) into the residual capacity of every code,
-// resid[c] = L_max - c(b) - accepted_b (0 for codes of no block).  Then the
-// refused movers are placed by weight class q = ceil(log2 c(v)), heaviest
-// class first: in class q a block with residual r >= 2^q offers the
-// r - 2^q + 1 positions [C_b, C_b + r - 2^q + 1) of a prefix over ascending
-// blocks, and a mover of the class whose exclusive weight prefix R (over the
-// class's movers in id order) falls into them goes there; R beyond the last
-// position leaves it where it is.  The movers a block receives in one class
-// start inside its positions, so they weigh at most r: no block ends above
-// L_max.  The residuals shrink by what each block received before the next
-// class.  Positions of a class are kept compacted in sstart / sblock.
-__global__ __launch_bounds__(kThreads) void k_place_rejects(Hier h, const int64_t *w, int64_t *acc,
-                                                            int64_t lmax, const int32_t *list,
-                                                            const int32_t *count,
-                                                            const int32_t *vwgt, int64_t *resid,
-                                                            int64_t *sstart, int32_t *sblock,
-                                                            int32_t *target, uint8_t *moved) {
-  extern __shared__ uint32_t got[];  // weight received per code in the current class
-  __shared__ BlockScratch sc;
-  __shared__ int64_t wave_tot[kThreads / 64];
-  __shared__ uint32_t cls_mask;
-  __shared__ int32_t nslots;
-  __shared__ int64_t npos;
+// *count), ascending ids), placed by one workgroup of kPlaceThreads.  First
+// the accepted-weight stripes are folded (and cleared) into the residual
+// capacity of every code, resid[c] = L_max - c(b) - accepted_b (0 for codes
+// of no block), and the movers' weights are gathered once into rw[].  Then
+// the movers are placed by weight class q = ceil(log2 c(v)), heaviest class
+// first: in class q a block with residual r >= 2^q offers the r - 2^q + 1
+// positions [C_b, C_b + r - 2^q + 1) of a prefix over ascending codes, and a
+// mover of the class whose exclusive weight prefix R (over the class's movers
+// in id order) falls into them goes there; R beyond the last position leaves
+// it where it is.  The movers a block receives in one class start inside its
+// positions, so they weigh at most r: no block ends above L_max.  The
+// residuals shrink by what each block received before the next class.
+//
+// The position starts C (one per code, codes without positions repeat the
+// next start) are searched for the last C <= R, which is always a code with
+// positions.  With at most kPlaceLdsCodes codes, residuals and starts live
+// in LDS; beyond, in the global arrays gresid / gstart.  A chunk of
+// kPlaceChunk movers is read per step; a per-chunk mask of the classes it
+// holds lets a class skip the chunks without members.
+constexpr int kPlaceThreads = 1024;
+constexpr int kPlacePer = 16;
+constexpr int kPlaceChunk = kPlaceThreads * kPlacePer;
+constexpr int kPlaceLdsCodes = 2048;
+constexpr int kPlaceMaxChunks = 1024;  // chunks with a class mask; beyond: every class visits
+
+__device__ __forceinline__ uint32_t place_excl_scan(uint32_t x, uint32_t *wsum) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int32_t)incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t off = 0;
+  for (int i = 0; i < wave; ++i) off += wsum[i];
+  return off + incl - x;
+}
+
+__device__ __forceinline__ int64_t place_excl_scan64(int64_t x, int64_t *wsum, int64_t *total) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t incl = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();
+  if (lane == 63) wsum[wave] = incl;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+  for (int i = 0; i < kPlaceThreads / 64; ++i) {
+    if (i < wave) off += wsum[i];
+    tot += wsum[i];
+  }
+  *total = tot;
+  return off + incl - x;
+}
+
+__global__ __launch_bounds__(kPlaceThreads) void k_place_rejects(
+    Hier h, const int64_t *w, int64_t *acc, int64_t lmax, const int32_t *list,
+    const int32_t *count, const int32_t *vwgt, int32_t *rw, int64_t *gresid, int64_t *gstart,
+    int32_t *target, uint8_t *moved) {
+  extern __shared__ int64_t place_lds[];
+  __shared__ uint32_t wsum[kPlaceThreads / 64];
+  __shared__ int64_t wsum64[kPlaceThreads / 64];
+  __shared__ uint32_t cmask[kPlaceMaxChunks];
   __shared__ uint32_t chunk_total;
   const int32_t ncodes = 1 << h.bits;
-  const int per = (ncodes + kThreads - 1) / kThreads;
+  const bool in_lds = ncodes <= kPlaceLdsCodes;
+  int64_t *resid = in_lds ? place_lds : gresid;
+  int64_t *start = in_lds ? place_lds + ncodes : gstart;
+  uint32_t *got = reinterpret_cast<uint32_t *>(in_lds ? place_lds + 2 * ncodes : place_lds);
+  const int per = (ncodes + kPlaceThreads - 1) / kPlaceThreads;
   const int lo = threadIdx.x * per;
   const int hi = lo + per < ncodes ? lo + per : ncodes;
   for (int c = lo; c < hi; ++c) {
@@ -1865,66 +1914,69 @@ __global__ __launch_bounds__(kThreads) void k_place_rejects(Hier h, const int64_
     resid[c] = code_valid(h, (uint32_t)c) ? lmax - w[c] - a : 0;
     got[c] = 0;
   }
-  if (threadIdx.x == 0) cls_mask = 0;
+  for (int i = threadIdx.x; i < kPlaceMaxChunks; i += kPlaceThreads) cmask[i] = 0;
   __syncthreads();
   const int32_t L = *count;
-  uint32_t m = 0;
-  for (int32_t i = threadIdx.x; i < L; i += kThreads) m |= 1u << weight_class(vwgt[list[i]]);
-  m = (uint32_t)gor<64>((int32_t)m);
-  if ((threadIdx.x & 63) == 0 && m) atomicOr(&cls_mask, m);
+  const int32_t nchunks = (L + kPlaceChunk - 1) / kPlaceChunk;
+  // weights of the movers, and the classes of every chunk
+  uint32_t all = 0;
+  for (int32_t c0 = 0; c0 < L; c0 += kPlaceChunk) {
+    uint32_t m = 0;
+#pragma unroll
+    for (int i = 0; i < kPlacePer; ++i) {
+      const int32_t j = c0 + i * kPlaceThreads + (int32_t)threadIdx.x;  // coalesced
+      if (j < L) {
+        const int32_t c = vwgt[list[j]];
+        rw[j] = c;
+        m |= 1u << weight_class(c);
+      }
+    }
+    m = (uint32_t)gor<64>((int32_t)m);
+    all |= m;
+    const int32_t ch = c0 / kPlaceChunk;
+    if ((threadIdx.x & 63) == 0 && m && ch < kPlaceMaxChunks) atomicOr(&cmask[ch], m);
+  }
   __syncthreads();
-  const uint32_t mask = cls_mask;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the union of the classes over all waves
+  uint32_t mask = 0;
+  for (int32_t ch = 0; ch < nchunks && ch < kPlaceMaxChunks; ++ch) mask |= cmask[ch];
+  if (nchunks > kPlaceMaxChunks) {
+    all = (uint32_t)gor<64>((int32_t)all);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = all;
+    __syncthreads();
+    for (int i = 0; i < kPlaceThreads / 64; ++i) mask |= wsum[i];
+    __syncthreads();
+  }
   for (int q = 31; q >= 0; --q) {
     if (!((mask >> q) & 1u)) continue;
     const int64_t unit = int64_t(1) << q;
-    // positions of the class: blocks with r >= 2^q, ascending
-    uint32_t cnt = 0;
+    // position starts of the class over ascending codes
     int64_t sum = 0;
     for (int c = lo; c < hi; ++c) {
       const int64_t r = resid[c];
-      if (r >= unit) {
-        ++cnt;
-        sum += r - unit + 1;
-      }
+      if (r >= unit) sum += r - unit + 1;
     }
-    uint32_t pos = block_excl_scan(cnt, sc);
-    int64_t incl = sum;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int64_t y = gshfl64<64>(incl, lane >= o ? lane - o : lane);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) wave_tot[wave] = incl;
-    __syncthreads();
-    int64_t run = incl - sum;
-    for (int i = 0; i < wave; ++i) run += wave_tot[i];
+    int64_t total = 0;
+    int64_t run = place_excl_scan64(sum, wsum64, &total);
     for (int c = lo; c < hi; ++c) {
+      start[c] = run;
       const int64_t r = resid[c];
-      if (r >= unit) {
-        sstart[pos] = run;
-        sblock[pos] = c;
-        ++pos;
-        run += r - unit + 1;
-      }
-    }
-    if (threadIdx.x == kThreads - 1) {
-      nslots = (int32_t)pos;
-      npos = run;
+      if (r >= unit) run += r - unit + 1;
     }
     __syncthreads();
-    const int32_t ns = nslots;
-    const int64_t total = npos;
-    // the class's movers in id order, 16 consecutive list entries per thread
+    // the class's movers in id order, 16 consecutive entries per thread
     int64_t base = 0;
-    for (int32_t c0 = 0; c0 < L; c0 += kWalkChunk) {
-      const int32_t i0 = c0 + (int32_t)threadIdx.x * kWalkPer;
-      uint32_t cw[kWalkPer];
+    for (int32_t c0 = 0; c0 < L && base < total; c0 += kPlaceChunk) {
+      const int32_t ch = c0 / kPlaceChunk;
+      if (ch < kPlaceMaxChunks && !((cmask[ch] >> q) & 1u)) continue;
+      const int32_t i0 = c0 + (int32_t)threadIdx.x * kPlacePer;
+      uint32_t cw[kPlacePer];
       uint32_t mem = 0, s = 0;
 #pragma unroll
-      for (int i = 0; i < kWalkPer; ++i) {
+      for (int i = 0; i < kPlacePer; ++i) {
         cw[i] = 0;
         if (i0 + i < L) {
-          const int32_t c = vwgt[list[i0 + i]];
+          const int32_t c = rw[i0 + i];
           if (weight_class(c) == q) {
             cw[i] = (uint32_t)c;
             mem |= 1u << i;
@@ -1932,31 +1984,30 @@ __global__ __launch_bounds__(kThreads) void k_place_rejects(Hier h, const int64_
         }
         s += cw[i];
       }
-      const uint32_t excl = block_excl_scan(s, sc);
-      if (threadIdx.x == kThreads - 1) chunk_total = excl + s;
+      const uint32_t excl = place_excl_scan(s, wsum);
+      if (threadIdx.x == kPlaceThreads - 1) chunk_total = excl + s;
       int64_t R = base + excl;
 #pragma unroll
-      for (int i = 0; i < kWalkPer; ++i) {
+      for (int i = 0; i < kPlacePer; ++i) {
         if (!(mem & (1u << i))) continue;
         if (R < total) {
-          int32_t a = 0, b = ns - 1;  // largest j with sstart[j] <= R
+          int32_t a = 0, b = ncodes - 1;  // last code with start <= R
           while (a < b) {
             const int32_t mid = (a + b + 1) >> 1;
-            if (sstart[mid] <= R) a = mid;
+            if (start[mid] <= R) a = mid;
             else b = mid - 1;
           }
-          const int32_t blk = sblock[a];
           const int32_t v = list[i0 + i];
-          target[v] = blk;
+          target[v] = a;
           moved[v] = 1;
-          atomicAdd(&got[blk], cw[i]);
+          atomicAdd(&got[a], cw[i]);
         }
         R += cw[i];
       }
       __syncthreads();
       base += chunk_total;
-      __syncthreads();  // chunk_total is rewritten by the next chunk
     }
+    __syncthreads();
     for (int c = lo; c < hi; ++c) {
       resid[c] -= got[c];
       got[c] = 0;
@@ -1988,7 +2039,7 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
   rb.tneed = ar.alloc_n<int64_t>(ncodes);
   rb.tsum = ar.alloc_n<int32_t>((size_t)ncodes * (rb.ntiles > 0 ? rb.ntiles : 1));
   rb.rstart = ar.alloc_n<int64_t>(ncodes);
-  rb.rblock = ar.alloc_n<int32_t>(ncodes);
+  rb.rweight = ar.alloc_n<int32_t>(n);
   fill_i64(rb.bw, 0, (int64_t)kBucketStripes * ncodes * kBuckets, s);
   fill_i64(rb.acc, 0, (int64_t)kBucketStripes * ncodes, s);
   fill_i32(rb.tsum, 0, (int64_t)ncodes * (rb.ntiles > 0 ? rb.ntiles : 1), s);
@@ -2097,9 +2148,9 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
   K.strong = 0;
   keyed_prefix(K, s);
   select_indices(ar, rb.reject, rb.rlist, rb.rcount, n, s);
-  hipLaunchKernelGGL(k_place_rejects, dim3(1), dim3(kThreads), sizeof(uint32_t) * (size_t)ncodes,
-                     s, h, w, rb.acc, lmax, rb.rlist, rb.rcount, g.c, rb.resid, rb.rstart,
-                     rb.rblock, target, moved);
+  const size_t plds = ncodes <= kPlaceLdsCodes ? (size_t)ncodes * 20 : (size_t)ncodes * 4;
+  hipLaunchKernelGGL(k_place_rejects, dim3(1), dim3(kPlaceThreads), plds, s, h, w, rb.acc, lmax,
+                     rb.rlist, rb.rcount, g.c, rb.rweight, rb.resid, rb.rstart, target, moved);
   PM_LAUNCH_CHECK();
 }
 

@@ -205,13 +205,14 @@ def _reweighted(g, seed, wlog):
 @pytest.mark.parametrize("name,a,frac,wlog", [("rmat14", (4, 16, 8), 0.1, 12),
                                               ("rmat17", (4, 16, 8), 0.1, 12),
                                               ("rmat17", (4, 16, 8), 0.2, 4),
+                                              ("rmat17", (16, 16, 16), 0.1, 12),
                                               ("rgg17", (4, 8, 8), 0.3, 8),
                                               ("rgg14", (4, 8, 3), 0.3, 10)])
 def test_strong_rebalance_weight_classes(pm, pmo, torch_mod, name, a, frac, wlog):
-    """Strong rounds whose refused movers span up to 13 weight classes and
-    (rmat17) more than one 4096-entry chunk of the placement walk; the
-    result equals the oracle and no block at or below L_max before the round
-    ends above it."""
+    """Strong rounds whose refused movers span up to 13 weight classes,
+    with up to 10 000 refused movers and with 4096 codes (residuals and
+    position starts outside LDS); the result equals the oracle and no block
+    at or below L_max before the round ends above it."""
     g = _reweighted(gen.get(name).graph(), 5, wlog)
     k = k_of(a)
     d = (1, 10, 100)
@@ -228,6 +229,29 @@ def test_strong_rebalance_weight_classes(pm, pmo, torch_mod, name, a, frac, wlog
     w0 = np.bincount(part, weights=g.vwgt, minlength=k)
     w1 = np.bincount(exp_part, weights=g.vwgt, minlength=k)
     assert not np.any((w0 <= lm) & (w1 > lm))
+
+
+@pytest.fixture(scope="module")
+def rmat19():
+    return gen.rmat(19, 1 << 22, 0xC3, name="rmat19")
+
+
+@pytest.mark.parametrize("a,frac", [((4, 16, 8), 0.5), ((16, 16, 16), 0.3)])
+def test_strong_rebalance_many_refused(pm, pmo, torch_mod, rmat19, a, frac):
+    """Strong rounds with about 15 000 and 30 000 refused movers (more than
+    one 16 384-entry chunk of the placement), equal to the oracle."""
+    g = rmat19
+    k = k_of(a)
+    total = int(g.vwgt.sum())
+    lm = pmo.lmax(total, k, 0.03)
+    part = gen.random_mapping(g.n, k, 11)
+    part[: int(g.n * frac)] = 1
+    say("strong many refused", a, frac)
+    exp_part, exp_moved = pmo.rebalance(g, k, part, True, lm, lm, 77, 2, 1)
+    part_d = t32(torch_mod, part)
+    mv = pm.pm_rebalance(dev(pm, g), a, (1, 10, 100), part_d, True, lm, lm, 77, 2, 1)
+    assert np.array_equal(host(mv), exp_moved)
+    assert np.array_equal(host(part_d), exp_part)
 
 
 # ---------------------------------------------------------------------------
