@@ -5,11 +5,14 @@ One step = one pm_map call (coarsening, contraction, initial partitioning,
 projection and refinement at every level) on a synthetic task graph that is
 already resident in HBM.  Reported value: refinement GTEPS = logical arcs
 processed by refinement (iterations x arcs, summed over levels) / device
-time of refinement.  The line also carries the end-to-end map time, the
-roofline of the dominant kernel (label propagation phase 1, timed per launch
-with start/stop events) and the CPU oracle timed on this host.
+time of refinement.  The line also carries the end-to-end map time, per
+timed kernel its launches, device time (start/stop events of every launch
+inside the timed region) and algorithmic bytes (counted in a second,
+untimed pass over the same seeds), the roofline of the kernel with the
+largest device time, the refinement kernels' aggregate, and the CPU oracle
+timed on this host.
 
-    python bench.py [--steps K] [--warmup W] [--workload rgg20]
+    python bench.py [--steps K] [--warmup W] [--workload rmat22]
 """
 import argparse
 import json
@@ -24,13 +27,18 @@ sys.path.insert(0, ROOT)
 METRIC = "refinement GTEPS + end-to-end map time; batched/served vs plain at equal J"
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 512 << 20
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_lp_phase1_rgg20_traffic.txt")
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_2510_12196_amd", "csrc", f)
-                   for f in ("refine.hip", "device_util.h", "pm_internal.h")]
+                   for f in ("refine.hip", "coarsen.hip", "device_util.h", "pm_internal.h",
+                             "kernels.h")]
+# timed kernels of the library (pm_map_stats order) and their rocprof names
+KERNEL_NAMES = {"lp_phase1": "k_lp_phase1", "lp_phase2": "k_lp_phase2",
+                "apply_moves": "k_apply", "hem_prefer": "k_hem_prefer",
+                "reb_select": "k_reb_select"}
+REFINEMENT = ("lp_phase1", "lp_phase2", "apply_moves", "reb_select")
 
 
 def source_digest():
-    """Digest of the sources that define the label-propagation phase-1 kernel."""
+    """Digest of the sources that define the timed kernels."""
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
@@ -39,11 +47,16 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload):
-    """Measured HBM bytes per launch of k_lp_phase1 from the committed counter
+def traffic_file(kernel, workload):
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+
+
+def read_traffic(kernel, workload):
+    """Measured HBM bytes per launch of a kernel from the committed counter
     summary, if it was taken on this workload and on the current sources."""
     try:
-        kv = dict(line.split(":", 1) for line in open(TRAFFIC_FILE) if ":" in line)
+        kv = dict(line.split(":", 1) for line in open(traffic_file(kernel, workload))
+                  if ":" in line)
     except OSError:
         return None
     kv = {k.strip(): v.strip() for k, v in kv.items()}
@@ -55,11 +68,12 @@ def read_traffic(workload):
         return None
 
 
-def summarize_pmc(d):
+def summarize_pmc(d, kernel):
     """Reduce rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch)
-    for k_lp_phase1 and the calibration copy kernel to bytes per launch."""
+    for `kernel` and the calibration copy kernel to bytes per launch."""
     import csv
     import glob
+    import re
     sums = {}
     for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         for r in csv.DictReader(open(f)):
@@ -67,7 +81,10 @@ def summarize_pmc(d):
             ctr = r.get("Counter_Name", "")
             val = float(r.get("Counter_Value", "0") or 0)
             disp = r.get("Dispatch_Id", "")
-            kind = "lp1" if "k_lp_phase1" in name else ("copy" if "neg_kernel" in name else None)
+            # (the move accounting is k_apply on small tilings, k_apply_listed
+            # on large ones)
+            kind = ("k" if re.search(r"pm::%s(<|\(|_listed)" % kernel, name) else
+                    ("copy" if "neg_kernel" in name else None))
             if kind is None:
                 continue
             key = (kind, ctr)
@@ -79,18 +96,17 @@ def summarize_pmc(d):
             out[(kind, ctr)] = (max(per.values()), 1)
         else:
             out[(kind, ctr)] = (sum(per.values()), len(per))
-    for k, v in sorted(out.items()):
-        print(k, v)
     copy_mib = COPY_BYTES / 1024.0
     res = {}
     for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-        if ("copy", ctr) in out and ("lp1", ctr) in out:
+        if ("copy", ctr) in out and ("k", ctr) in out:
             ctot, cn = out[("copy", ctr)]
-            ltot, ln = out[("lp1", ctr)]
+            ltot, ln = out[("k", ctr)]
             scale = copy_mib / (ctot / cn) if ctot else float("nan")
             res[ctr] = (ltot / ln) * scale * 1024.0
             print(f"{ctr}: copy reads {ctot / cn:.0f} KiB for {copy_mib:.0f} KiB -> scale "
-                  f"{scale:.4f}; k_lp_phase1 {ltot / ln:.1f} KiB/launch -> {res[ctr]:.0f} B")
+                  f"{scale:.4f}; {kernel} {ltot / ln:.1f} KiB/launch over {ln} launches -> "
+                  f"{res[ctr]:.0f} B")
     if len(res) == 2:
         print(f"hbm_bytes_per_launch: {res['FETCH_SIZE'] + res['WRITE_SIZE']:.0f}")
     print(f"source_digest: {source_digest()}")
@@ -120,6 +136,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-times", choices=("pass", "inline"), default="pass",
+                    help="time the kernels' launches in a pass after the timed steps (pass) or "
+                         "inside them (inline)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise pass over 512 MiB (known traffic: 512 MiB "
                          "read, 512 MiB written) for scaling hardware byte counters")
@@ -128,9 +147,11 @@ def main():
                          "multilevel mapping")
     ap.add_argument("--summarize-pmc", metavar="DIR",
                     help="summarise rocprofv3 --pmc counter CSVs under DIR and exit")
+    ap.add_argument("--pmc-kernel", default="k_lp_phase1",
+                    help="kernel whose counters --summarize-pmc reduces")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(args.summarize_pmc)
+        summarize_pmc(args.summarize_pmc, args.pmc_kernel)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the mapping of one task graph runs on a single "
@@ -158,8 +179,9 @@ def main():
     if args.hm:
         return bench_hm(args, w, g, dg)
 
-    def step(i, kernel_times):
-        return pm.pm_map(dg, w.a, w.d, w.eps, 1 + i % 5, kernel_times=kernel_times)
+    def step(i, kernel_times, kernel_counts=False):
+        return pm.pm_map(dg, w.a, w.d, w.eps, 1 + i % 5, kernel_times=kernel_times,
+                         kernel_counts=kernel_counts)
 
     if args.copy_calibration:
         src = torch.empty(COPY_BYTES // 4, dtype=torch.int32, device="cuda").fill_(1)
@@ -170,8 +192,9 @@ def main():
         log(f"copy calibration: {COPY_BYTES} bytes read, {COPY_BYTES} bytes written")
         del src, dst
 
+    inline = args.kernel_times == "inline"
     for i in range(args.warmup):
-        rc, part, st = step(i, True)
+        rc, part, st = step(i, inline)
         log(f"warmup {i}: rc={rc} J={st.j_final} levels={st.levels} total {st.total_ms:.2f} ms")
     torch.cuda.synchronize()
 
@@ -179,7 +202,7 @@ def main():
     first_part = None
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rc, part, st = step(i, True)
+        rc, part, st = step(i, inline)
         if i == 0:
             first_part = part
         stats.append((rc, st))
@@ -191,14 +214,42 @@ def main():
     refine_ms = sum(s.refine_ms for _, s in stats)
     gteps = refine_arcs / (refine_ms * 1e-3) / 1e9 if refine_ms > 0 else 0.0
     map_ms = [s.total_ms for _, s in stats]
-    kl = [sum(s.kernel_launches[j] for _, s in stats) for j in range(4)]
-    kms = [sum(s.kernel_ms[j] for _, s in stats) for j in range(4)]
-    kbytes = sum(s.kernel_bytes[0] for _, s in stats)
-    achieved = kbytes / (kms[0] * 1e-3) / 1e9 if kms[0] > 0 else 0.0
+    nk = len(pm.TIMED_KERNELS)
+    # Device time of every launch of the timed kernels (start/stop events on
+    # the launch's stream): inside the timed steps (--kernel-times inline), or
+    # in a pass over the same seeds right after them (pass; the default,
+    # since recording events around every launch adds host work that slows
+    # the latency-bound small levels of the map being timed).
+    timed = stats if inline else [(None, step(i, True)[2]) for i in range(args.steps)]
+    assert [s.j_final for _, s in timed] == [s.j_final for _, s in stats]
+    kl = [sum(s.kernel_launches[j] for _, s in timed) for j in range(nk)]
+    kms = [sum(s.kernel_ms[j] for _, s in timed) for j in range(nk)]
+
+    # Units of work of the same launches: the timed steps again (same seeds,
+    # hence the same launches), outside the timed region, with the library's
+    # counting launches beside the timed kernels.
+    counted = [step(i, False, True)[2] for i in range(args.steps)]
+    assert [s.j_final for s in counted] == [s.j_final for _, s in stats]
+    kbytes = [sum(s.kernel_bytes[j] for s in counted) for j in range(nk)]
+    kunits = [[sum(s.kernel_units[j][u] for s in counted) for u in range(3)] for j in range(nk)]
 
     def avg(f):
         return statistics.fmean(getattr(s, f) for _, s in stats)
 
+    kernels = {}
+    for j, name in enumerate(pm.TIMED_KERNELS):
+        if not kl[j]:
+            continue
+        gbs = kbytes[j] / (kms[j] * 1e-3) / 1e9 if kms[j] > 0 else 0.0
+        kernels[name] = {"kernel": KERNEL_NAMES[name], "launches": kl[j],
+                         "total_ms": round(kms[j], 3), "avg_us": round(kms[j] * 1e3 / kl[j], 3),
+                         "bytes_per_launch": round(kbytes[j] / kl[j], 1),
+                         "units_per_launch": [round(x / kl[j], 1) for x in kunits[j]],
+                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    kd = kernels[dom]
+    rb = sum(kbytes[j] for j, n in enumerate(pm.TIMED_KERNELS) if n in REFINEMENT)
+    rt = sum(kms[j] for j, n in enumerate(pm.TIMED_KERNELS) if n in REFINEMENT)
     s0 = stats[0][1]
     line = {
         "metric": METRIC,
@@ -227,18 +278,26 @@ def main():
         "level_iterations": list(s0.level_iterations[: s0.levels]),
         "J_seed1": s0.j_final,
         "status": sorted({rc for rc, _ in stats}),
-        "kernels": {name: {"launches": kl[j], "avg_us": round(kms[j] * 1e3 / kl[j], 3) if kl[j] else None}
-                    for j, name in enumerate(pm.TIMED_KERNELS)},
+        "kernels": kernels,
+        "kernel_times": args.kernel_times,
+        # the timed kernel with the largest device time over the timed steps
         "roofline": {
-            "kernel": "k_lp_phase1",
+            "kernel": kd["kernel"],
             "bound": "hbm",
-            "achieved": round(achieved, 1),
+            "achieved": kd["achieved_gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": read_traffic(w.name),
-            "bytes_per_launch": round(kbytes / kl[0], 1) if kl[0] else None,
-            "avg_launch_us": round(kms[0] * 1e3 / kl[0], 3) if kl[0] else None,
+            "frac": kd["frac"],
+            "traffic": read_traffic(kd["kernel"], w.name),
+            "bytes_per_launch": kd["bytes_per_launch"],
+            "avg_launch_us": kd["avg_us"],
+        },
+        # the refinement kernels together: algorithmic bytes over their time
+        "refinement_roofline": {
+            "kernels": [KERNEL_NAMES[n] for n in REFINEMENT],
+            "achieved": round(rb / (rt * 1e-3) / 1e9, 1) if rt > 0 else None,
+            "frac": round(rb / (rt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if rt > 0 else None,
+            "kernel_ms_per_map": round(rt / args.steps, 3),
         },
     }
 

@@ -67,7 +67,10 @@ extern "C" {
 /* pm_map: time every launch of the kernels listed under pm_map_stats with
  * start/stop events (adds a little host work per launch) */
 #define PM_FLAG_KERNEL_TIMES 2u
-#define PM_TIMED_KERNELS 4
+/* pm_map: count the units of work of every launch of those kernels (extra
+ * counting launches beside them; results unchanged, the map takes longer) */
+#define PM_FLAG_KERNEL_COUNTS 4u
+#define PM_TIMED_KERNELS 5
 
 #define PM_MAX_LEVELS 8
 #define PM_MAX_GRAPH_LEVELS 64
@@ -98,15 +101,21 @@ typedef struct pm_hierarchy {
  *     within the cap with the largest gain (smaller block on ties), and the
  *     bucket of every source comes from that gain (for the pseudo-random
  *     destination too).
- * A NULL pm_options pointer, or variants = 0, is the method as evaluated.
- * Invalid bits or constants: PM_EINVAL.  Host struct. */
+ * refine_repeats: the "ultra" repetition (Section 5: Jet's ultra
+ *   configuration runs the complete refinement 18 times): in pm_map, pm_map_ex
+ *   and the partitioning calls of pm_map_hm_ex, Algorithm 6 runs this many
+ *   times at every level, run r from the result of run r - 1 (empty lock
+ *   set) with seed + r for its pseudo-random choices; 0 or 1: once, at most
+ *   64.  pm_refine_ex ignores it.
+ * A NULL pm_options pointer, or variants = 0 and refine_repeats <= 1, is the
+ * method as evaluated.  Invalid bits or constants: PM_EINVAL.  Host struct. */
 #define PM_VARIANT_JET_FILTER 1u
 #define PM_VARIANT_J_REBALANCE 2u
 typedef struct pm_options {
   uint32_t variants;
   int32_t jet_c_num;
   int32_t jet_c_den;
-  int32_t reserved;        /* 0 */
+  int32_t refine_repeats;  /* 0 or 1: once; "ultra": 18 */
 } pm_options;
 
 /* Statistics of one refinement run (Algorithm 6).  Host struct. */
@@ -142,15 +151,29 @@ typedef struct pm_map_stats {
   double refine_ms;        /* refinement incl. rebalancing, all levels    */
   double total_ms;         /* whole call, host wall clock                 */
   int64_t refine_arcs;     /* sum over levels of iterations x nnz         */
-  /* With PM_FLAG_KERNEL_TIMES: per timed kernel -- [0] label propagation
-   * phase 1, [1] phase 2, [2] move accounting, [3] matching preference --
-   * the launches, their summed device time (start/stop events of each
-   * launch) and, for [0], the algorithmic bytes (12 per arc + 25 per
-   * vertex: neighbour id, edge weight and neighbour block per arc; row
-   * offset, block, lock, target and gain per vertex). */
+  /* Per timed kernel -- [0] label propagation phase 1, [1] phase 2,
+   * [2] move accounting, [3] matching preference, [4] rebalancing
+   * selection: with PM_FLAG_KERNEL_TIMES the launches and their summed
+   * device time (start/stop events of each launch); with
+   * PM_FLAG_KERNEL_COUNTS, summed over the launches, the vertices tiled
+   * ([i][0]), the vertices that did the kernel's work ([i][1]: unlocked,
+   * members of X, movers, vertices looking for a partner, sources) and
+   * their arcs ([i][2]), and the algorithmic bytes those imply:
+   *   [0] 12 per active arc (neighbour id, edge weight, neighbour block)
+   *       + 25 per tiled vertex (row offsets, block, lock, target, gain)
+   *   [1] 24 per active arc (neighbour id, weight, block, target, gain)
+   *       + 16 per active vertex (row offsets, block, target) + 9 per tiled
+   *       vertex (gain, moved flag)
+   *   [2] 17 per active arc (neighbour id, weight, block, target, moved
+   *       flag) + 20 per mover (row offsets, block, target, weight)
+   *   [3] 16 per active arc (neighbour id, weight, its match, its weight)
+   *       + 12 per tiled vertex (match, preference, weight)
+   *   [4] 12 per active arc + 24 per source (row offsets, block, weight,
+   *       key, destination) */
   int64_t kernel_launches[PM_TIMED_KERNELS];
   double kernel_ms[PM_TIMED_KERNELS];
   double kernel_bytes[PM_TIMED_KERNELS];
+  int64_t kernel_units[PM_TIMED_KERNELS][3];
 } pm_map_stats;
 
 /* Library version string. */
@@ -183,6 +206,19 @@ void pm_release(void);
  *   contract_rows_long_pct  ... provided that coarse rows above 64 arcs hold
  *                      at most this percentage of the level's arcs
  *                      (default 100; 0..100)
+ *   lp_cache           1: label propagation keeps the first filter's result
+ *                      of a vertex while neither it nor a neighbour has moved
+ *                      (Section 4.2, "Refinement": results are cached and
+ *                      reused while the neighbourhood is unchanged); 0:
+ *                      every round evaluates every unlocked vertex (default
+ *                      0: the marking of moved neighbourhoods costs more
+ *                      than the skipped evaluations save on the R-MAT
+ *                      workload)
+ *   graph_bodies       1: on levels whose loop bodies read nothing back, the
+ *                      label-propagation and weak-rebalancing bodies of a
+ *                      level are captured in HIP graphs the first time and
+ *                      replayed (calls on a stream other than the null
+ *                      stream); 0: every kernel is launched (default 0)
  * pm_set_tuning returns PM_EINVAL (nothing changed) for values outside these
  * ranges.  Calls already running may see either setting. */
 typedef struct pm_tuning {
@@ -192,6 +228,8 @@ typedef struct pm_tuning {
   int32_t reb_compact_min_n;
   int32_t contract_rows_min_nnz;
   int32_t contract_rows_long_pct;
+  int32_t lp_cache;
+  int32_t graph_bodies;
 } pm_tuning;
 int pm_get_tuning(pm_tuning *out);
 int pm_set_tuning(const pm_tuning *t);
@@ -324,6 +362,12 @@ int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts,
 int pm_map_hm(const pm_graph *g, const pm_hierarchy *h, double eps,
               uint64_t seed, int32_t workers, int32_t *part_out,
               int64_t *j_out, int32_t *calls_out, void *stream);
+/* pm_map_hm with refinement variants for every partitioning call (opts may
+ * be NULL); refine_repeats = 18 is the paper's GPU-HM-ultra. */
+int pm_map_hm_ex(const pm_graph *g, const pm_hierarchy *h, double eps,
+                 uint64_t seed, int32_t workers, int32_t *part_out,
+                 int64_t *j_out, int32_t *calls_out, const pm_options *opts,
+                 void *stream);
 
 /* ---------------------------------------------------------------------------
  * Many instances.  A job is one independent mapping instance: a device graph,

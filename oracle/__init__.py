@@ -75,6 +75,7 @@ _SIGS = {
     "pmo_subgraphs": (_I64, [_I32, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P]),
     "pmo_adaptive_eps_ppm": (_I64, [_I64, _I64, _I64, _I64, _I64, _I32]),
     "pmo_hm": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _I64, _U64, _P]),
+    "pmo_hm_v": (_I32, [_I32, _P, _P, _P, _P, _I32, _P, _I64, _U64, _P, _P]),
     "pmo_lp_round_v": (None, [_I32, _P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pmo_rebalance_v": (None, [_I32, _P, _P, _P, _P, _I32, _P, _P, _I64, _I32, _I64, _I64,
                                _U64, _I32, _I32, _P, _P, _P]),
@@ -90,16 +91,19 @@ class Variants(ctypes.Structure):
     """Refinement variants (pmo_variants): jet_c = (num, den) enables Jet's
     relaxed first filter with c = num/den; j_rebalance rebalances by J."""
     _fields_ = [("jet_c_num", ctypes.c_int32), ("jet_c_den", ctypes.c_int32),
-                ("j_rebalance", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("j_rebalance", ctypes.c_int32), ("refine_repeats", ctypes.c_int32)]
 
 
-def variants(jet_c=None, j_rebalance=False):
+def variants(jet_c=None, j_rebalance=False, repeats=0):
+    """repeats: the "ultra" repetition (Algorithm 6 runs this many times per
+    level of a multilevel map; 0 or 1: once)."""
     v = Variants()
     if jet_c:
         v.jet_c_num, v.jet_c_den = int(jet_c[0]), int(jet_c[1])
     else:
         v.jet_c_num, v.jet_c_den = 0, 1
     v.j_rebalance = 1 if j_rebalance else 0
+    v.refine_repeats = int(repeats)
     return v
 
 
@@ -323,10 +327,12 @@ def adaptive_eps_ppm(eps_ppm: int, kp: int, k: int, cv: int, cvp: int, d: int) -
     return int(lib().pmo_adaptive_eps_ppm(eps_ppm, kp, k, cv, cvp, d))
 
 
-def hm(g, a, eps, seed):
-    """Recursive hierarchical multisection (Algorithm 2).  Returns (status, part)."""
+def hm(g, a, eps, seed, var=None):
+    """Recursive hierarchical multisection (Algorithm 2); var: refinement
+    variants of every partitioning call.  Returns (status, part)."""
     a = _i32(a)
     part = np.empty(max(g.n, 1), np.int32)
-    rc = lib().pmo_hm(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
-                      a.shape[0], _ptr(a), eps_to_ppm(eps), seed & (2**64 - 1), _ptr(part))
+    rc = lib().pmo_hm_v(g.n, _ptr(g.xadj), _ptr(g.adjncy), _ptr(g.adjwgt), _ptr(g.vwgt),
+                        a.shape[0], _ptr(a), eps_to_ppm(eps), seed & (2**64 - 1), _ptr(part),
+                        _var(var))
     return int(rc), part[: g.n]

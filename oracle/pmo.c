@@ -1167,16 +1167,23 @@ int32_t pmo_map_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                         a, part);
   int32_t status = 0;
   double tr = 0.0;
+  /* "ultra": the complete refinement runs `repeats` times at every level,
+   * run r from the result of run r - 1 (empty lock set), with seed + r for
+   * its pseudo-random choices */
+  const int32_t repeats = (var && var->refine_repeats > 1) ? var->refine_repeats : 1;
   for (int32_t s = t;; --s) {
     level_graph *g = &lv[s];
-    pmo_refine_stats rs;
-    double r0 = now_seconds();
-    status = pmo_refine_v(g->n, g->xadj, g->adjncy, g->adjwgt, g->vwgt, levels,
-                          a, d, eps_ppm, seed, s, part, &rs, var);
-    tr += now_seconds() - r0;
-    st.level_iterations[s] = rs.iterations;
-    st.j_final = rs.j_final;
-    st.feasible = rs.feasible;
+    st.level_iterations[s] = 0;
+    for (int32_t r = 0; r < repeats; ++r) {
+      pmo_refine_stats rs;
+      double r0 = now_seconds();
+      status = pmo_refine_v(g->n, g->xadj, g->adjncy, g->adjwgt, g->vwgt, levels,
+                            a, d, eps_ppm, seed + (uint64_t)r, s, part, &rs, var);
+      tr += now_seconds() - r0;
+      st.level_iterations[s] += rs.iterations;
+      st.j_final = rs.j_final;
+      st.feasible = rs.feasible;
+    }
     if (s == 0) break;
     level_graph *f = &lv[s - 1];
     int32_t *fine = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)f->n);
@@ -1280,6 +1287,7 @@ typedef struct {
   uint64_t seed;
   int32_t *part_out;
   int32_t status;
+  const pmo_variants *var;
 } hm_ctx;
 
 static void hm_rec(hm_ctx *c, int32_t n, const int64_t *xadj, const int32_t *adjncy,
@@ -1292,7 +1300,8 @@ static void hm_rec(hm_ctx *c, int32_t n, const int64_t *xadj, const int32_t *adj
   int64_t ppm = pmo_adaptive_eps_ppm(c->eps_ppm, kp, c->k, c->cv, cvp, i);
   int32_t ai = c->a[i - 1], one = 1;
   int32_t *part = (int32_t *)xmalloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-  int32_t st = pmo_map(n, xadj, adjncy, adjwgt, vwgt, 1, &ai, &one, ppm, c->seed, part, NULL);
+  int32_t st = pmo_map_v(n, xadj, adjncy, adjwgt, vwgt, 1, &ai, &one, ppm, c->seed, part, NULL,
+                         c->var);
   if (st > c->status) c->status = st;
   int64_t pstride = kp / ai; /* P_{i-1} */
   if (i == 1) {
@@ -1335,7 +1344,17 @@ static void hm_rec(hm_ctx *c, int32_t n, const int64_t *xadj, const int32_t *adj
 int32_t pmo_hm(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out) {
+  return pmo_hm_v(n, xadj, adjncy, adjwgt, vwgt, levels, a, eps_ppm, seed, part_out, NULL);
+}
+
+/* pmo_hm with refinement variants for every partitioning call (e.g. the
+ * "ultra" repetition, which the paper's GPU-HM-ultra uses). */
+int32_t pmo_hm_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                 const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                 const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out,
+                 const pmo_variants *var) {
   hm_ctx c;
+  c.var = var;
   c.levels = levels;
   c.a = a;
   c.k = pmo_num_pes(levels, a);

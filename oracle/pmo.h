@@ -58,12 +58,15 @@ typedef struct {
 /* Refinement variants (Section 4.2): all zero = the method as evaluated.
  *   jet_c_num / jet_c_den: with jet_c_num > 0, Jet's relaxed first filter of
  *     label propagation, c = jet_c_num / jet_c_den (jet_c_den > 0);
- *   j_rebalance: rebalancing by the J gain instead of the edge-cut loss. */
+ *   j_rebalance: rebalancing by the J gain instead of the edge-cut loss;
+ *   refine_repeats: the "ultra" repetition of Section 5 -- the complete
+ *     refinement (Algorithm 6) runs this many times at every level of a
+ *     multilevel map (0 or 1: once). */
 typedef struct {
   int32_t jet_c_num;
   int32_t jet_c_den;
   int32_t j_rebalance;
-  int32_t pad_;
+  int32_t refine_repeats;
 } pmo_variants;
 
 /* ---- hierarchy and objective (Section 2) ---- */
@@ -160,6 +163,10 @@ int64_t pmo_adaptive_eps_ppm(int64_t eps_ppm, int64_t kp, int64_t k, int64_t cv,
 int32_t pmo_hm(int32_t n, const int64_t *xadj, const int32_t *adjncy,
                const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
                const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out);
+int32_t pmo_hm_v(int32_t n, const int64_t *xadj, const int32_t *adjncy,
+                 const int32_t *adjwgt, const int32_t *vwgt, int32_t levels,
+                 const int32_t *a, int64_t eps_ppm, uint64_t seed, int32_t *part_out,
+                 const pmo_variants *var);
 
 #ifdef __cplusplus
 }

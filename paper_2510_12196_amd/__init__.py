@@ -28,7 +28,8 @@ PM_EHIP = -5
 PM_ENODEVICE = -6
 PM_FLAG_VALIDATE = 1
 PM_FLAG_KERNEL_TIMES = 2
-TIMED_KERNELS = ("lp_phase1", "lp_phase2", "apply_moves", "hem_prefer")
+PM_FLAG_KERNEL_COUNTS = 4
+TIMED_KERNELS = ("lp_phase1", "lp_phase2", "apply_moves", "hem_prefer", "reb_select")
 MAX_LEVELS = 8
 MAX_GRAPH_LEVELS = 64
 
@@ -70,8 +71,8 @@ class PmMapStats(ctypes.Structure):
                 ("initial_ms", ctypes.c_double), ("uncoarsen_ms", ctypes.c_double),
                 ("refine_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("refine_arcs", ctypes.c_int64),
-                ("kernel_launches", ctypes.c_int64 * 4), ("kernel_ms", ctypes.c_double * 4),
-                ("kernel_bytes", ctypes.c_double * 4)]
+                ("kernel_launches", ctypes.c_int64 * 5), ("kernel_ms", ctypes.c_double * 5),
+                ("kernel_bytes", ctypes.c_double * 5), ("kernel_units", (ctypes.c_int64 * 3) * 5)]
 
 
 class PmMapJob(ctypes.Structure):
@@ -103,6 +104,7 @@ _SIGS = {
     "pm_map_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _P, _P, _U32, _P, _P]),
     "pm_subgraphs": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "pm_map_hm": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P]),
+    "pm_map_hm_ex": (ctypes.c_int, [_P, _P, ctypes.c_double, _U64, _I32, _P, _P, _P, _P, _P]),
     "pm_get_tuning": (ctypes.c_int, [_P]),
     "pm_set_tuning": (ctypes.c_int, [_P]),
     "pm_map_batch": (ctypes.c_int, [_P, _I32, _I32, _P]),
@@ -161,14 +163,15 @@ PM_VARIANT_J_REBALANCE = 2
 
 class PmOptions(ctypes.Structure):
     _fields_ = [("variants", ctypes.c_uint32), ("jet_c_num", ctypes.c_int32),
-                ("jet_c_den", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("jet_c_den", ctypes.c_int32), ("refine_repeats", ctypes.c_int32)]
 
 
-def options(jet_c=None, j_rebalance: bool = False) -> PmOptions:
+def options(jet_c=None, j_rebalance: bool = False, repeats: int = 0) -> PmOptions:
     """Refinement variants: jet_c = (num, den) enables Jet's relaxed first
     filter with c = num/den; j_rebalance ranks rebalancing moves by the J
-    gain."""
+    gain; repeats runs Algorithm 6 that many times per level ("ultra": 18)."""
     o = PmOptions()
+    o.refine_repeats = int(repeats)
     if jet_c:
         o.variants |= PM_VARIANT_JET_FILTER
         o.jet_c_num, o.jet_c_den = int(jet_c[0]), int(jet_c[1])
@@ -180,7 +183,8 @@ def options(jet_c=None, j_rebalance: bool = False) -> PmOptions:
 class PmTuning(ctypes.Structure):
     _fields_ = [("group_v", ctypes.c_int32), ("wave_min_count", ctypes.c_int32),
                 ("hem_compact_min_n", ctypes.c_int32), ("reb_compact_min_n", ctypes.c_int32),
-                ("contract_rows_min_nnz", ctypes.c_int32), ("contract_rows_long_pct", ctypes.c_int32)]
+                ("contract_rows_min_nnz", ctypes.c_int32), ("contract_rows_long_pct", ctypes.c_int32),
+                ("lp_cache", ctypes.c_int32), ("graph_bodies", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -390,14 +394,17 @@ def pm_initial_partition(g: DeviceGraph, a, d):
 
 
 def pm_map(g: DeviceGraph, a, d, eps: float, seed: int, part=None, validate: bool = False,
-           kernel_times: bool = False, opts: PmOptions = None):
-    """Full multilevel mapping.  Returns (status, part, PmMapStats)."""
+           kernel_times: bool = False, opts: PmOptions = None, kernel_counts: bool = False):
+    """Full multilevel mapping.  Returns (status, part, PmMapStats).
+    kernel_times / kernel_counts: per-launch device times / unit counts of
+    the timed kernels (TIMED_KERNELS) in the stats."""
     torch = _torch()
     if part is None:
         part = torch.empty(g.n, dtype=torch.int32, device=g.vwgt.device)
     st = PmMapStats()
     gs, hs = g.struct(), hierarchy(a, d)
-    flags = (PM_FLAG_VALIDATE if validate else 0) | (PM_FLAG_KERNEL_TIMES if kernel_times else 0)
+    flags = ((PM_FLAG_VALIDATE if validate else 0) | (PM_FLAG_KERNEL_TIMES if kernel_times else 0)
+             | (PM_FLAG_KERNEL_COUNTS if kernel_counts else 0))
     if opts is None:
         rc = lib().pm_map(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
                           _dev(part, "int32", g.n), ctypes.byref(st), flags, _stream())
@@ -434,8 +441,10 @@ def pm_subgraphs(g: DeviceGraph, part, parts: int):
             "adjncy": adj[:m], "adjwgt": wgt[:m], "vwgt": vw[:n]}
 
 
-def pm_map_hm(g: DeviceGraph, a, d, eps: float, seed: int, workers: int = 8, part=None):
-    """Hierarchical multisection with the multilevel mapper as partitioner.
+def pm_map_hm(g: DeviceGraph, a, d, eps: float, seed: int, workers: int = 8, part=None,
+              opts: PmOptions = None):
+    """Hierarchical multisection with the multilevel mapper as partitioner
+    (opts: refinement variants of every partitioning call).
     Returns (status, part, J under (a, d), number of partitioning calls)."""
     torch = _torch()
     if part is None:
@@ -443,9 +452,9 @@ def pm_map_hm(g: DeviceGraph, a, d, eps: float, seed: int, workers: int = 8, par
     j = ctypes.c_int64(0)
     calls = ctypes.c_int32(0)
     gs, hs = g.struct(), hierarchy(a, d)
-    rc = lib().pm_map_hm(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
-                         int(workers), ctypes.c_void_p(part.data_ptr()), ctypes.byref(j),
-                         ctypes.byref(calls), _stream())
+    rc = lib().pm_map_hm_ex(ctypes.byref(gs), ctypes.byref(hs), float(eps), seed & (2**64 - 1),
+                            int(workers), ctypes.c_void_p(part.data_ptr()), ctypes.byref(j),
+                            ctypes.byref(calls), _opt(opts), _stream())
     _check(rc, "pm_map_hm")
     return rc, part[: g.n], int(j.value), int(calls.value)
 

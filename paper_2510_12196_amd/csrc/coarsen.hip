@@ -207,9 +207,12 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
   if (nwg == 0) return;
   HemArgs A{g, tc, lmax, hseed, match, pref};
   auto kern = V == 2 ? k_hem_prefer<2> : k_hem_prefer<1>;
-  if (tl_timer) {
-    hipEvent_t a, b;
-    tl_timer->pair(KT_HEM, a, b);
+  if (tl_timer) count_units(cl, g.xadj, CU_HEM_ACTIVE, CountArgs{nullptr, nullptr, nullptr, nullptr, match,
+                                                                 pref},
+                            tl_timer->counters(KT_HEM), s);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tl_timer) tl_timer->pair(KT_HEM, a, b);
+  if (a) {
     hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
   } else {
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);

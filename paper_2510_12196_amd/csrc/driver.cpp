@@ -1,6 +1,7 @@
 // driver.cpp -- host orchestration and the C ABI of the process-mapping library.
 #include <chrono>
 #include <cmath>
+#include <functional>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -70,6 +71,9 @@ Variants variants_of(const pm_options *o) {
     v.jet_den = o->jet_c_den;
   }
   v.j_rebalance = (o->variants & PM_VARIANT_J_REBALANCE) != 0;
+  if (o->refine_repeats < 0 || o->refine_repeats > 64)
+    throw Error(PM_EINVAL, "refine_repeats must be in [0, 64]");
+  v.repeats = o->refine_repeats > 1 ? o->refine_repeats : 1;
   return v;
 }
 
@@ -96,8 +100,11 @@ struct Ctx {
   int64_t *seq_dev = nullptr;
   const volatile int64_t *seq_host = nullptr;
   uint64_t *counter = nullptr;  // completion counter of the matching commit
+  int64_t *seq_ctr = nullptr;   // device copy of the publication sequence
   explicit Ctx(Arena &a, hipStream_t st) : ar(a), s(st) {
     dev = ar.alloc_n<Status>(1);
+    seq_ctr = ar.alloc_n<int64_t>(1);
+    fill_i64(seq_ctr, ar.publish_seq(), 1, s);
     counter = ar.alloc_n<uint64_t>(65);
     PM_HIP(hipMemsetAsync(counter, 0, sizeof(uint64_t) * 65, s));
     host = static_cast<Status *>(ar.host_stage(sizeof(Status) + 4096));
@@ -123,12 +130,15 @@ struct Ctx {
   // plus a stream synchronisation.  next_pub() names a publication for a
   // kernel that ends a step; wait() blocks until it has happened.  A stream
   // that fails or goes idle without publishing raises PM_EHIP.
-  Pub next_pub() { return Pub{mirror_dev, seq_dev, ar.next_publish()}; }
-  void pull() {
+  Pub next_pub() { return Pub{mirror_dev, seq_dev, ar.next_publish(), seq_ctr}; }
+  // enqueues a publication (the device counts the sequence) and returns the
+  // number the host then waits for
+  Pub publish() {
     const Pub p = next_pub();
-    publish_status(dev, mirror_dev, seq_dev, p.seq, s);
-    wait(p);
+    publish_status(dev, mirror_dev, seq_dev, p.seq, s, seq_ctr);
+    return p;
   }
+  void pull() { wait(publish()); }
   void wait(const Pub &p) {
     const int64_t seq = p.seq;
     for (uint64_t it = 1;; ++it) {
@@ -172,7 +182,8 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   const int64_t n = g.n;
   const int32_t ncodes = 1 << h.bits;
   int32_t *cur = ar.alloc_n<int32_t>(n);
-  int32_t *target = ar.alloc_n<int32_t>(n);
+  int32_t *target = ar.alloc_n<int32_t>(n);   // label propagation (kept between its rounds)
+  int32_t *rtarget = ar.alloc_n<int32_t>(n);  // rebalancing
   int64_t *gain = ar.alloc_n<int64_t>(n);
   uint8_t *moved = ar.alloc_n<uint8_t>(n);
   uint8_t *lock = ar.alloc_n<uint8_t>(n);
@@ -190,6 +201,12 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
 
   if (n > 0) PM_HIP(hipMemcpyAsync(cur, best, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
   fill_u8(lock, 0, n, s);
+  // result caching of label propagation (a launch parameter: pm_set_tuning)
+  uint8_t *dirty = nullptr;
+  if (tuning().lp_cache && n > 0) {
+    dirty = ar.alloc_n<uint8_t>(n);
+    fill_u8(dirty, 1, n, s);
+  }
   block_weights(g, h, cur, w, s);
   comm_cost(g, cl, h, cur, cx.sp.a, cx.dev, s);
   // step epilogue: heaviest block, J change, eligible destinations, publication
@@ -210,14 +227,67 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   R.st.maxw_initial = imb_cur;
   const uint64_t reb_seed = mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level);
 
+  // Loop bodies replayed from HIP graphs (launch parameter graph_bodies):
+  // the label-propagation body and the weak-rebalancing body of this level
+  // are captured the first time they run and replayed afterwards.  Every
+  // argument of their kernels is the same in every body of the level; the
+  // body number of the pseudo-random destinations and the publication's
+  // sequence number are read from device counters.  Levels that read sizes
+  // back inside a body (compacted rebalancing), strong rounds (a library
+  // selection inside) and calls on the null stream (which cannot be
+  // captured) are launched as usual.
+  struct BodyGraph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~BodyGraph() {
+      if (x) (void)hipGraphExecDestroy(x);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } bgs[2];
+  const bool use_graphs = tuning().graph_bodies && !tl_timer && !slist && n > 0 && s != nullptr;
+  int64_t *body_ctr = nullptr;
+  if (use_graphs) {
+    body_ctr = ar.alloc_n<int64_t>(1);
+    fill_i64(body_ctr, 0, 1, s);
+    E.body_ctr = body_ctr;
+  }
+  auto replay = [&](BodyGraph &bg, const std::function<void()> &body) -> Pub {
+    if (!bg.x) {
+      PM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      try {
+        body();
+        publish_status(cx.dev, cx.mirror_dev, cx.seq_dev, 0, s, cx.seq_ctr);
+      } catch (...) {
+        hipGraph_t dead = nullptr;
+        (void)hipStreamEndCapture(s, &dead);
+        if (dead) (void)hipGraphDestroy(dead);
+        throw;
+      }
+      PM_HIP(hipStreamEndCapture(s, &bg.g));
+      PM_HIP(hipGraphInstantiate(&bg.x, bg.g, nullptr, nullptr, 0));
+    }
+    const Pub p = cx.next_pub();
+    PM_HIP(hipGraphLaunch(bg.x, s));
+    return p;
+  };
+
   int32_t i = 0, iw = 0, bodies = 0;
   while (i < 12 && bodies < 4096) {
     ++i;
     ++bodies;
+    Pub pub{};
     if (imb_cur <= lmax) {
-      lp_phase1(g, cl, h, cur, lock, target, gain, s, var);
-      lp_phase2(g, cl, h, cur, target, gain, moved, s);
-      apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, &E, s);
+      auto body = [&] {
+        lp_phase1(g, cl, h, cur, lock, target, gain, s, var, dirty);
+        lp_phase2(g, cl, h, cur, target, gain, moved, s);
+        apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, &E, s, dirty);
+      };
+      if (use_graphs) {
+        pub = replay(bgs[0], body);
+      } else {
+        body();
+        pub = cx.publish();
+      }
       iw = 0;
       ++R.st.lp_iterations;
     } else {
@@ -236,9 +306,18 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         rcl.list = slist;
         for (int c = 0; c <= NCLS; ++c) rcl.off[c] = cx.aux()[c];
       }
-      rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, target, moved, rb,
-                      cx.dev, s, var);
-      apply_moves(g, rcl, h, cur, target, moved, nullptr, w, wst, cx.sp.a, &E, s);
+      if (use_graphs && !strong) {
+        pub = replay(bgs[1], [&] {
+          rebalance_round(ar, g, rcl, h, false, lmax, sigma, total, reb_seed, cur, w, rtarget,
+                          moved, rb, cx.dev, s, var, body_ctr);
+          apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, s, dirty);
+        });
+      } else {
+        rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, rtarget, moved,
+                        rb, cx.dev, s, var);
+        apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, s, dirty);
+        pub = cx.publish();
+      }
       if (strong) {
         iw = 0;
         ++R.st.strong_iterations;
@@ -247,7 +326,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         ++R.st.weak_iterations;
       }
     }
-    cx.pull();
+    cx.wait(pub);
     j_cur += cx.host->dj;
     imb_cur = cx.host->maxw;
     if (imb_cur <= lmax) {
@@ -843,13 +922,20 @@ int pm_subgraphs(const pm_graph *g, const int32_t *part, int32_t parts, int32_t 
 int pm_map_hm(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
               int32_t workers, int32_t *part_out, int64_t *j_out, int32_t *calls_out,
               void *stream) {
+  return pm_map_hm_ex(g, h, eps, seed, workers, part_out, j_out, calls_out, nullptr, stream);
+}
+
+int pm_map_hm_ex(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed,
+                 int32_t workers, int32_t *part_out, int64_t *j_out, int32_t *calls_out,
+                 const pm_options *opts, void *stream) {
   return guarded([&] {
+    const Variants var = variants_of(opts);
     check_device();
     const DGraph dg = view(g);
     const Hier hh = make_hier(h);
     hipStream_t s = as_stream(stream);
     PM_HIP(hipStreamSynchronize(s));
-    const int rc = hm_impl(dg, h->a, h->levels, eps, seed, part_out, workers, calls_out, s);
+    const int rc = hm_impl(dg, h->a, h->levels, eps, seed, part_out, workers, calls_out, s, var);
     if (j_out) {
       *j_out = 0;
       if (dg.n > 0) {
@@ -910,10 +996,12 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
     std::memset(&st, 0, sizeof(st));
     st.lmax = lmax;
     KernelTimer timer;
+    timer.timing = (flags & PM_FLAG_KERNEL_TIMES) != 0;
+    timer.counting = (flags & PM_FLAG_KERNEL_COUNTS) != 0;
     struct TimerScope {
       explicit TimerScope(KernelTimer *t) { tl_timer = t; }
       ~TimerScope() { tl_timer = nullptr; }
-    } timer_scope((flags & PM_FLAG_KERNEL_TIMES) ? &timer : nullptr);
+    } timer_scope((timer.timing || timer.counting) ? &timer : nullptr);
 
     EventSet evs;
     auto mark_event = [&]() {
@@ -988,13 +1076,17 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
     int32_t status = PM_OK;
     for (int lv = t;; --lv) {
       const Level &L = levels[lv];
-      RefineResult R = refine_level(cx, L.g, L.cl, hh, lmax, sigma, total, seed, lv, part, var);
-      st.refine_ms += R.st.refine_ms;
-      st.refine_arcs += R.st.arcs_processed;
-      st.level_iterations[lv] = R.st.iterations;
-      st.j_final = R.st.j_final;
-      st.feasible = R.st.feasible;
-      status = R.status;
+      // "ultra": run r of Algorithm 6 starts from run r - 1's result
+      for (int32_t r = 0; r < var.repeats; ++r) {
+        RefineResult R = refine_level(cx, L.g, L.cl, hh, lmax, sigma, total,
+                                      seed + (uint64_t)r, lv, part, var);
+        st.refine_ms += R.st.refine_ms;
+        st.refine_arcs += R.st.arcs_processed;
+        st.level_iterations[lv] += R.st.iterations;
+        st.j_final = R.st.j_final;
+        st.feasible = R.st.feasible;
+        status = R.status;
+      }
       if (lv == 0) break;
       const Level &F = levels[lv - 1];
       int32_t *fine = ar.alloc_n<int32_t>(F.g.n);
@@ -1010,7 +1102,8 @@ int map_impl(const pm_graph *g, const pm_hierarchy *h, double eps, uint64_t seed
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) *sp.acc += ms;
     }
-    if (flags & PM_FLAG_KERNEL_TIMES) timer.finish(st.kernel_launches, st.kernel_ms, st.kernel_bytes);
+    if (timer.timing || timer.counting)
+      timer.finish(st.kernel_launches, st.kernel_ms, st.kernel_bytes, st.kernel_units);
     st.total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
             .count();

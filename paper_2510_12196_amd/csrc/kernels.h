@@ -23,6 +23,10 @@ struct Pub {
   Status *host;
   int64_t *seq_slot;
   int64_t seq;
+  // with a device counter the sequence number is the counter, incremented
+  // (a publication captured in a graph then releases a new number on every
+  // replay); the host expects the same numbers in the same order
+  int64_t *seq_ctr = nullptr;
 };
 
 // End of a refinement step, run by one workgroup of the commit: the heaviest
@@ -36,6 +40,7 @@ struct StepEnd {
   int32_t *elig_weak;    // blocks with w <= sigma, ascending
   int32_t *elig_strong;  // blocks with w <= L_max, ascending
   Status *st;
+  int64_t *body_ctr = nullptr;  // loop bodies done (incremented by each step end)
 };
 // StepEnd alone, as one workgroup (the start of a level).
 void step_status(const StepEnd &E, hipStream_t s);
@@ -55,8 +60,13 @@ __device__ __forceinline__ void publish_dev(const Status *st, const Pub &p) {
   const int64_t *src = reinterpret_cast<const int64_t *>(st);
   int64_t *dst = reinterpret_cast<int64_t *>(p.host);
   for (size_t i = 0; i < sizeof(Status) / sizeof(int64_t); ++i) dst[i] = agent_load(src + i);
+  int64_t seq = p.seq;
+  if (p.seq_ctr) {
+    seq = *p.seq_ctr + 1;
+    *p.seq_ctr = seq;
+  }
   __threadfence_system();
-  __hip_atomic_store(p.seq_slot, p.seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(p.seq_slot, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Striped accumulator buffers of one call (kStripes x 16 int64 each, zeroed
@@ -68,7 +78,7 @@ struct Stripes {
 // Copies *dev into the mapped host mirror (device view host_dev), then stores
 // seq into *seq_dev, all with system-scope visibility.
 void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
-                    hipStream_t s);
+                    hipStream_t s, int64_t *seq_ctr = nullptr);
 // Adds up the stripes into *out64 (if non-null) or *out32, clears them;
 // publishes if pub.host.
 void fold_stripes(int64_t *stripes, int64_t *out64, int32_t *out32, hipStream_t s,
@@ -78,16 +88,36 @@ unsigned classed_grid(const Classes &cl);   // one tile per workgroup
 unsigned capped_grid(const Classes &cl);    // at most kMaxGrid workgroups
 
 // ---- optional per-launch kernel timing --------------------------------------
-enum { KT_LP1 = 0, KT_LP2, KT_APPLY, KT_HEM, NKT };
+enum { KT_LP1 = 0, KT_LP2, KT_APPLY, KT_HEM, KT_REB, NKT };
+// What a counting launch counts as active (see count_units).
+enum { CU_UNLOCKED = 0, CU_IN_X, CU_MOVED, CU_HEM_ACTIVE, CU_SOURCE };
+constexpr int kCountStripes = 32;
 struct KernelTimer {
+  bool timing = false;    // start/stop events around every timed launch
+  bool counting = false;  // counting launches beside the timed ones
   std::vector<hipEvent_t> start[NKT], stop[NKT];
-  double bytes[NKT] = {0, 0, 0, 0};
-  // event pair for one launch of kernel id (created here, destroyed in finish)
+  int64_t *dcount = nullptr;  // device [NKT][3][kCountStripes][kStripeStride]
+  // event pair for one launch of kernel id (nullptrs when not timing)
   void pair(int id, hipEvent_t &a, hipEvent_t &b);
-  // sums the elapsed times; call after the stream has been synchronised
-  void finish(int64_t *launches, double *ms, double *bytes_out);
+  // the counters of kernel id (nullptr when not counting)
+  int64_t *counters(int id);
+  // sums the elapsed times and reads the counters; call after the stream has
+  // been synchronised
+  void finish(int64_t *launches, double *ms, double *bytes_out, int64_t (*units)[3]);
   ~KernelTimer();
 };
+// Counting launch: over the tiled vertices of cl, the number of vertices,
+// of those active by `what`, and of their arcs, into out (nullptr: none).
+struct CountArgs {
+  const uint8_t *flag8;  // lock (CU_UNLOCKED) or moved (CU_MOVED)
+  const uint8_t *dirty;  // CU_UNLOCKED with result caching: only dirty vertices
+  const int64_t *gain;   // CU_IN_X
+  const int32_t *key;    // CU_SOURCE
+  const int32_t *match;  // CU_HEM_ACTIVE
+  const int32_t *pref;
+};
+void count_units(const Classes &cl, const int64_t *xadj, int what, const CountArgs &a,
+                 int64_t *out, hipStream_t s);
 // timer of the call running on this host thread (nullptr: no timing)
 extern thread_local KernelTimer *tl_timer;
 
@@ -126,12 +156,15 @@ struct Variants {
   int64_t jet_num = 0;
   int64_t jet_den = 1;
   bool j_rebalance = false;
+  int32_t repeats = 1;  // runs of Algorithm 6 per level of a multilevel map
 };
 
 // ---- label propagation (Algorithm 4) --------------------------------------
+// dirty != nullptr: result caching (unlocked vertices that are not dirty keep
+// their last target and gain; see apply_moves)
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
-               const Variants &var = Variants{});
+               const Variants &var = Variants{}, uint8_t *dirty = nullptr);
 void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
@@ -142,9 +175,12 @@ void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
 constexpr int kWeightStripes = 32;
 int weight_stripes(const Hier &h, int64_t n);   // stripes in use (power of two)
 int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
+// dirty != nullptr: marks every mover and every neighbour of a mover (the
+// result caching of label propagation)
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s);
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s,
+                 uint8_t *dirty = nullptr);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
 struct RebalanceBuffers {
@@ -178,11 +214,14 @@ RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_
 // every other vertex gets key -1 (not a source) here.
 void reb_sources(Arena &ar, const Classes &cl, int32_t n, const int32_t *part, const int64_t *w,
                  int64_t lmax, int32_t *key, int32_t *list_out, int32_t *off_out, hipStream_t s);
+// body_ctr != nullptr: the pseudo-random destinations use
+// mix_hash(hseed, *body_ctr + 1) read on the device (a round captured in a
+// graph then draws for the body it runs in) instead of hseed itself.
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
-                     const Variants &var = Variants{});
+                     const Variants &var = Variants{}, const int64_t *body_ctr = nullptr);
 
 // ---- induced subgraphs (Section 4.1, Algorithm 1) ----------------------------
 // Layout of all blocks' subgraphs, concatenated in block order (device
@@ -216,7 +255,8 @@ void scatter_blocks(int32_t n, const int32_t *orig, const int32_t *part, int32_t
 // mapper as partitioner; part_out: device ids in [0, k).  Returns PM_OK or
 // PM_WARN_IMBALANCED (some partitioning call ended above its L_max).
 int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint64_t seed,
-            int32_t *part_out, int32_t workers, int32_t *calls_out, hipStream_t s);
+            int32_t *part_out, int32_t workers, int32_t *calls_out, hipStream_t s,
+            const Variants &var = Variants{});
 // equation (2) in parts per million, rounded, never negative
 int64_t adaptive_eps_ppm(int64_t eps_ppm, int64_t kp, int64_t k, int64_t cv, int64_t cvp,
                          int32_t d);

@@ -64,7 +64,8 @@ struct Streams {
 }  // namespace
 
 int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint64_t seed,
-            int32_t *part_out, int32_t workers, int32_t *calls_out, hipStream_t s) {
+            int32_t *part_out, int32_t workers, int32_t *calls_out, hipStream_t s,
+            const Variants &var) {
   if (calls_out) *calls_out = 0;
   if (levels < 1 || levels > PM_MAX_LEVELS) throw Error(PM_EINVAL, "bad hierarchy depth");
   int64_t k = 1;
@@ -146,7 +147,7 @@ int hm_impl(const DGraph &dg, const int32_t *a, int32_t levels, double eps, uint
           h1.a[0] = ai;
           h1.d[0] = 1;
           int32_t *pt = part + tk.voff;
-          rc[t] = map_impl(&pg, &h1, (double)ppm / 1e6, seed, pt, nullptr, 0, ws);
+          rc[t] = map_impl(&pg, &h1, (double)ppm / 1e6, seed, pt, nullptr, 0, ws, var);
           if (i == 1) {
             scatter_blocks(tk.n, tk.orig, pt, (int32_t)tk.base, part_out, ws);
             PM_HIP(hipStreamSynchronize(ws));

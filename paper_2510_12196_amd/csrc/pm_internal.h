@@ -137,7 +137,7 @@ constexpr int kHemRoundsPerRead = 4;  // matching rounds between status read-bac
 // Process-wide launch parameters (pm_set_tuning); read at each call.
 struct TuningValues {
   int32_t group_v, wave_min_count, hem_compact_min_n, reb_compact_min_n, contract_rows_min_nnz,
-      contract_rows_long_pct;
+      contract_rows_long_pct, lp_cache, graph_bodies;
 };
 TuningValues tuning();
 void set_tuning(const TuningValues &t);
@@ -177,6 +177,7 @@ class Arena {
   static constexpr size_t kMappedBytes = 4096;
   void *host_mapped(void **dev_view);
   int64_t next_publish() { return ++publish_seq_; }
+  int64_t publish_seq() const { return publish_seq_; }
 
  private:
   struct Chunk { char *ptr; size_t size; size_t base; };

@@ -51,11 +51,58 @@ void fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) { fill(p, v, n, s
 // memory, then releases the sequence number the host is polling
 // ===========================================================================
 __global__ void k_publish(const Status *dev, Pub pub) { publish_dev(dev, pub); }
+
+// Counting launch (PM_FLAG_KERNEL_COUNTS): per tiled vertex one unit, and
+// for the active ones their arcs.
+__global__ __launch_bounds__(kThreads) void k_count_units(Classes cl, const int64_t *xadj,
+                                                          int what, CountArgs a, int64_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  int64_t nt = 0, na = 0, ar = 0;
+  if (i < cl.off[NCLS]) {
+    const int32_t v = cl.list[i];
+    nt = 1;
+    bool act = false;
+    switch (what) {
+      case CU_UNLOCKED: act = a.flag8[v] == 0 && (!a.dirty || a.dirty[v]); break;
+      case CU_IN_X: act = a.gain[v] != kNotInX; break;
+      case CU_MOVED: act = a.flag8[v] != 0; break;
+      case CU_SOURCE: act = a.key[v] >= 0; break;
+      default: {  // a vertex that looks for a partner (matching preference)
+        const int32_t m = a.match[v], p = a.pref[v];
+        act = m < 0 && (p == -2 || (p >= 0 && a.match[p] >= 0));
+      }
+    }
+    if (act) {
+      na = 1;
+      ar = xadj[v + 1] - xadj[v];
+    }
+  }
+  nt = gsum64<64>(nt);
+  na = gsum64<64>(na);
+  ar = gsum64<64>(ar);
+  if ((threadIdx.x & 63) == 0) {
+    const size_t st = (size_t)(blockIdx.x & (kCountStripes - 1)) * kStripeStride;
+    const int64_t x[3] = {nt, na, ar};
+    for (int j = 0; j < 3; ++j)
+      if (x[j]) atomicAdd((unsigned long long *)&out[(size_t)j * kCountStripes * kStripeStride + st],
+                          (unsigned long long)x[j]);
+  }
+}
+
+void count_units(const Classes &cl, const int64_t *xadj, int what, const CountArgs &a,
+                 int64_t *out, hipStream_t s) {
+  const int64_t m = cl.off[NCLS];
+  if (!out || m <= 0) return;
+  hipLaunchKernelGGL(k_count_units, dim3((unsigned)((m + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, cl, xadj, what, a, out);
+  PM_LAUNCH_CHECK();
+}
 static_assert(sizeof(Status) % sizeof(int64_t) == 0, "Status is copied in 8-byte words");
 
 void publish_status(const Status *dev, Status *host_dev, int64_t *seq_dev, int64_t seq,
-                    hipStream_t s) {
-  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, dev, Pub{host_dev, seq_dev, seq});
+                    hipStream_t s, int64_t *seq_ctr) {
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, dev,
+                     Pub{host_dev, seq_dev, seq, seq_ctr});
   PM_LAUNCH_CHECK();
 }
 
@@ -507,7 +554,24 @@ struct LP1Args {
   int64_t jet_num;  // > 0: relaxed filter -G < floor(jet_num * conn(v,own) / jet_den)
   int64_t jet_den;
   int32_t whist;    // G64 vertices use a per-wave LDS histogram (LDS: 4 slices)
+  uint8_t *dirty;   // result caching (nullptr: off): see lp1_state
 };
+
+// Result caching.  The first filter's result for an unlocked vertex depends
+// only on its block and its neighbours' blocks; dirty[v] is set when v or a
+// neighbour moves (by the move accounting) and cleared when v is evaluated
+// here, so an unlocked vertex that is not dirty keeps the target and gain of
+// its last evaluation (they stay in target[] / gain[], which only this kernel
+// writes).  State of v: 0 locked (trivial result), 1 cached (nothing to
+// write), 2 evaluated.
+__device__ __forceinline__ int lp1_state(const LP1Args &A, int32_t v) {
+  if (A.lock[v]) return 0;
+  if (A.dirty && !A.dirty[v]) return 1;
+  return 2;
+}
+__device__ __forceinline__ void lp1_evaluated(const LP1Args &A, int32_t v) {
+  if (A.dirty) A.dirty[v] = 0;
+}
 
 // First filter: G >= 0, or with Jet's relaxed filter -G < floor(c conn_own).
 __device__ __forceinline__ bool lp1_pass(const LP1Args &A, int64_t g, int64_t conn_own) {
@@ -516,6 +580,7 @@ __device__ __forceinline__ bool lp1_pass(const LP1Args &A, int64_t g, int64_t co
 
 struct Lp1V {
   uint32_t p;
+  int state;
 };
 struct Lp1N {
   uint32_t bu;
@@ -527,18 +592,20 @@ __device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) 
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
       [&](int32_t v, bool &act) {
-        act = !A.lock[v];
-        return Lp1V{(uint32_t)A.part[v]};
+        const int st = lp1_state(A, v);
+        act = st == 2;
+        return Lp1V{(uint32_t)A.part[v], st};
       },
       [&](int32_t u, int64_t e) { return Lp1N{(uint32_t)A.part[u], A.g.w[e]}; },
       [&](int, bool ok, int32_t v, const Lp1V &vv, bool act, int deg, bool valid,
           const Lp1N &nv) {
-        if (!ok) return;
+        if (!ok || vv.state == 1) return;
         const int lane = threadIdx.x % G;
         const uint32_t p = vv.p;
         const uint32_t bu = valid ? nv.bu : p;
         const int32_t wu = valid ? nv.wu : 0;
         const bool cand = valid && bu != p;
+        if (act && lane == 0) lp1_evaluated(A, v);
         if (!act || !gor<G>(cand ? 1 : 0)) {
           if (lane == 0) {
             A.target[v] = (int32_t)p;
@@ -604,7 +671,9 @@ __device__ __forceinline__ void big_histogram(const DGraph &g, const int32_t *pa
 __device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X,
                                         BlockScratch &sc) {
   const uint32_t p = (uint32_t)A.part[v];
-  if (A.lock[v]) {
+  const int st = lp1_state(A, v);
+  if (st == 1) return;
+  if (st == 0) {
     if (threadIdx.x == 0) {
       A.target[v] = (int32_t)p;
       A.gain[v] = kNotInX;
@@ -613,6 +682,9 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X
   }
   const int32_t ncodes = 1 << A.h.bits;
   big_histogram(A.g, A.part, v, X, ncodes, sc);
+  // (cleared only now: every wave of the workgroup has read the flag before
+  // the histogram's barriers)
+  if (threadIdx.x == 0) lp1_evaluated(A, v);
   const uint32_t total = X[ncodes];
   const uint32_t connp = X[p + 1] - X[p];
   if (total == connp) {
@@ -656,16 +728,18 @@ __device__ __forceinline__ void lp1_wave(const LP1Args &A, int local, uint32_t *
   group_tiles<64, V>(
       A.g.xadj, A.g.adj, A.cl, CLS_G64, local,
       [&](int32_t v, bool &act) {
-        act = !A.lock[v];
-        return Lp1V{(uint32_t)A.part[v]};
+        const int st = lp1_state(A, v);
+        act = st == 2;
+        return Lp1V{(uint32_t)A.part[v], st};
       },
       [&](int32_t u, int64_t e) { return Lp1N{(uint32_t)A.part[u], A.g.w[e]}; },
       [&](int, bool ok, int32_t v, const Lp1V &vv, bool act, int, bool valid, const Lp1N &nv) {
-        if (!ok) return;
+        if (!ok || vv.state == 1) return;
         const int lane = threadIdx.x & 63;
         const uint32_t p = vv.p;
         const uint32_t bu = valid ? nv.bu : p;
         const bool cand = valid && bu != p;
+        if (act && lane == 0) lp1_evaluated(A, v);
         if (!act || !gor<64>(cand ? 1 : 0)) {
           if (lane == 0) {
             A.target[v] = (int32_t)p;
@@ -703,13 +777,16 @@ __device__ __forceinline__ void lp1_w(const LP1Args &A, int local, uint32_t *X) 
   if (!w_vertex(A.cl, local, v)) return;
   const int lane = threadIdx.x & 63;
   const uint32_t p = (uint32_t)A.part[v];
-  if (A.lock[v]) {
+  const int st = lp1_state(A, v);
+  if (st == 1) return;
+  if (st == 0) {
     if (lane == 0) {
       A.target[v] = (int32_t)p;
       A.gain[v] = kNotInX;
     }
     return;
   }
+  if (lane == 0) lp1_evaluated(A, v);
   const int32_t ncodes = 1 << A.h.bits;
   uint32_t *Xw = X + (threadIdx.x >> 6) * (ncodes + 1);
   for (int c = lane; c <= ncodes; c += 64) Xw[c] = 0;
@@ -788,7 +865,7 @@ static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << 
 
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
                const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
-               const Variants &var) {
+               const Variants &var, uint8_t *dirty) {
   const int V = group_v();
   // four per-wave histogram slices fit in 32 KiB up to 2^10 codes
   const int whist = h.bits <= 10;
@@ -796,13 +873,15 @@ void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
   LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1,
-            whist};
+            whist, dirty};
   const size_t lds = whist ? 4 * big_lds(h) : big_lds(h);
   auto kern = V == 2 ? k_lp_phase1<2> : k_lp_phase1<1>;
-  if (tl_timer) {
-    hipEvent_t a, b;
-    tl_timer->pair(KT_LP1, a, b);
-    tl_timer->bytes[KT_LP1] += 12.0 * (double)g.nnz + 25.0 * (double)g.n;
+  if (tl_timer) count_units(cl, g.xadj, CU_UNLOCKED, CountArgs{lock, dirty, nullptr, nullptr,
+                                                               nullptr, nullptr},
+                            tl_timer->counters(KT_LP1), s);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tl_timer) tl_timer->pair(KT_LP1, a, b);
+  if (a) {
     hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
   } else {
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, A);
@@ -941,9 +1020,12 @@ void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t 
   if (nwg == 0) return;
   LP2Args A{g, tc, h, part, target, gain, moved};
   auto kern = V == 2 ? k_lp_phase2<2> : k_lp_phase2<1>;
-  if (tl_timer) {
-    hipEvent_t a, b;
-    tl_timer->pair(KT_LP2, a, b);
+  if (tl_timer) count_units(cl, g.xadj, CU_IN_X, CountArgs{nullptr, nullptr, gain, nullptr,
+                                                           nullptr, nullptr},
+                            tl_timer->counters(KT_LP2), s);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (tl_timer) tl_timer->pair(KT_LP2, a, b);
+  if (a) {
     hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
   } else {
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
@@ -972,6 +1054,7 @@ struct ApplyArgs {
   int64_t *wst;  // weight-delta stripes [nstripes][ncodes]
   int32_t nstripes;
   int64_t *dj;
+  uint8_t *dirty;  // label-propagation result caching (nullptr: off)
 };
 
 // Block-weight deltas of one mover (+c to its target, -c to its block): added
@@ -992,6 +1075,35 @@ struct ApV {
   uint32_t p, t;
 };
 
+// One arc of a mover: neighbour, weight, its block, target and moved flag.
+struct ApArc {
+  int32_t u, w, pu, tu;
+  uint8_t mu;
+};
+__device__ __forceinline__ ApArc ap_arc(const ApplyArgs &A, int64_t e) {
+  const int32_t u = A.g.adj[e];
+  return ApArc{u, A.g.w[e], A.part[u], A.target[u], A.moved[u]};
+}
+// J change of one arc of a mover p -> t: an arc whose other end moved too is
+// seen from both sides (once each), else from the mover only (twice).  With
+// result caching the neighbour is marked.
+__device__ __forceinline__ int64_t ap_delta(const ApplyArgs &A, uint32_t p, uint32_t t,
+                                            const ApArc &a) {
+  if (A.dirty) A.dirty[a.u] = 1;
+  const uint32_t old_u = (uint32_t)a.pu;
+  if (a.mu) return (int64_t)a.w * (dist(A.h, t, (uint32_t)a.tu) - dist(A.h, p, old_u));
+  return 2 * (int64_t)a.w * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+}
+// The mover's own record: block-weight deltas, and its mark.
+__device__ __forceinline__ void ap_mover(const ApplyArgs &A, int32_t v, uint32_t p, uint32_t t,
+                                         WMove &mv) {
+  mv.has = true;
+  mv.p = p;
+  mv.t = t;
+  mv.c = A.g.c[v];
+  if (A.dirty) A.dirty[v] = 1;
+}
+
 template <int G, int V>
 __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int local) {
   int64_t x = 0;
@@ -1002,24 +1114,14 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
         act = A.moved[v] != 0;
         return ApV{(uint32_t)A.part[v], (uint32_t)A.target[v]};
       },
-      [&](int32_t u, int64_t e) {
-        return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
-      },
-      [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, int4 a) {
+      [&](int32_t, int64_t e) { return ap_arc(A, e); },
+      [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, const ApArc &a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
         if (A.lock && lane == 0) A.lock[v] = act ? 1 : 0;
         if (!act) return;
-        if (lane == 0) {
-          mv[r].has = true;
-          mv[r].p = vv.p;
-          mv[r].t = vv.t;
-          mv[r].c = A.g.c[v];
-        }
-        if (!valid) return;
-        const uint32_t old_u = (uint32_t)a.y;
-        if (a.w) x += (int64_t)a.x * (dist(A.h, vv.t, (uint32_t)a.z) - dist(A.h, vv.p, old_u));
-        else x += 2 * (int64_t)a.x * (dist(A.h, vv.t, old_u) - dist(A.h, vv.p, old_u));
+        if (lane == 0) ap_mover(A, v, vv.p, vv.t, mv[r]);
+        if (valid) x += ap_delta(A, vv.p, vv.t, a);
       });
 #pragma unroll
   for (int r = 0; r < V; ++r) wmove_flush(A, mv[r]);
@@ -1045,12 +1147,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
           const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
           const uint8_t m = A.moved[v];
           if (A.lock) A.lock[v] = m;
-          if (m) {
-            mv[r].has = true;
-            mv[r].p = (uint32_t)A.part[v];
-            mv[r].t = (uint32_t)A.target[v];
-            mv[r].c = A.g.c[v];
-          }
+          if (m) ap_mover(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v], mv[r]);
         }
       }
 #pragma unroll
@@ -1069,23 +1166,10 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
         if (A.lock && (threadIdx.x & 63) == 0) A.lock[v] = m;
         if (m) {
           const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
-          if ((threadIdx.x & 63) == 0) {
-            mv.has = true;
-            mv.p = p;
-            mv.t = t;
-            mv.c = A.g.c[v];
-          }
+          if ((threadIdx.x & 63) == 0) ap_mover(A, v, p, t, mv);
           wave_arcs<4>(
-              A.g.xadj[v], A.g.xadj[v + 1],
-              [&](int64_t e) {
-                const int32_t u = A.g.adj[e];
-                return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
-              },
-              [&](int64_t, int4 a) {
-                const uint32_t old_u = (uint32_t)a.y;
-                if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
-                else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
-              });
+              A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return ap_arc(A, e); },
+              [&](int64_t, const ApArc &a) { x += ap_delta(A, p, t, a); });
         }
       }
       wmove_flush(A, mv);
@@ -1098,24 +1182,11 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
       if (m) {
         const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
         WMove mv;
-        if (threadIdx.x == 0) {
-          mv.has = true;
-          mv.p = p;
-          mv.t = t;
-          mv.c = A.g.c[v];
-        }
+        if (threadIdx.x == 0) ap_mover(A, v, p, t, mv);
         wmove_flush(A, mv);
         big_arcs(
-            A.g.xadj[v], A.g.xadj[v + 1],
-            [&](int64_t e) {
-              const int32_t u = A.g.adj[e];
-              return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
-            },
-            [&](int64_t, int4 a) {
-              const uint32_t old_u = (uint32_t)a.y;
-              if (a.w) x += (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
-              else x += 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
-            });
+            A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return ap_arc(A, e); },
+            [&](int64_t, const ApArc &a) { x += ap_delta(A, p, t, a); });
       }
       break;
     }
@@ -1135,7 +1206,10 @@ __global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part,
   extern __shared__ int64_t wl[];
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v < n && moved[v]) part[v] = target[v];
-  if (blockIdx.x == 0) step_epilogue(E, wst, nstripes, wl, has_end != 0);
+  if (blockIdx.x == 0) {
+    step_epilogue(E, wst, nstripes, wl, has_end != 0);
+    if (has_end && E.body_ctr && threadIdx.x == 0) *E.body_ctr += 1;
+  }
 }
 
 // Weight-delta stripes: at most kWeightStripes, and at most 8192 words in all
@@ -1158,21 +1232,24 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s) {
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s,
+                 uint8_t *dirty) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   const int nstripes = weight_stripes(h, g.n);
-  ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes};
+  ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes, dirty};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
   if (nwg > 0) {
+    hipEvent_t ta = nullptr, tb = nullptr;
     if (tl_timer) {
-      hipEvent_t a, b;
-      tl_timer->pair(KT_APPLY, a, b);
-      hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, a, b, 0, A);
-    } else {
-      hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
+      count_units(cl, g.xadj, CU_MOVED, CountArgs{moved, nullptr, nullptr, nullptr, nullptr,
+                                                  nullptr},
+                  tl_timer->counters(KT_APPLY), s);
+      tl_timer->pair(KT_APPLY, ta, tb);
     }
+    if (ta) hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, ta, tb, 0, A);
+    else hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A);
     PM_LAUNCH_CHECK();
   }
   StepEnd E{};
@@ -1219,6 +1296,7 @@ struct RebArgs {
   uint64_t hseed;
   const int32_t *elig;
   const int32_t *n_elig;
+  const int64_t *body_ctr;  // non-null: hseed is the base, mixed with the body number
   const Status *st;
   int32_t *key;
   int32_t *dest;
@@ -1500,6 +1578,7 @@ template <int V>
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
+  if (A.body_ctr) A.hseed = mix_hash(A.hseed, (uint64_t)(*A.body_ctr + 1));
   const int blk = blockIdx.x;
   const int cls = find_class(A.cl, blk);
   const int local = blk - A.cl.wg[cls];
@@ -2088,7 +2167,7 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
                      const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
-                     const Variants &var) {
+                     const Variants &var, const int64_t *body_ctr) {
   const int V = group_v();
   const bool whist = h.bits <= 10;  // as in lp_phase1
   const Classes tc = tiled(cl, V, !whist);
@@ -2109,6 +2188,7 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
               hseed,
               strong ? rb.elig_strong : rb.elig_weak,
               strong ? &st_dev->n_elig_strong : &st_dev->n_elig_weak,
+              body_ctr,
               st_dev,
               rb.key,
               rb.dest,
@@ -2116,9 +2196,15 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
               var.j_rebalance ? 1 : 0,
               whist ? 1 : 0};
     auto kern = V == 2 ? k_reb_select<2> : k_reb_select<1>;
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), A.whist ? 4 * big_lds(h) : big_lds(h), s,
-                       A);
+    const size_t lds = A.whist ? 4 * big_lds(h) : big_lds(h);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (tl_timer) tl_timer->pair(KT_REB, a, b);
+    if (a) hipExtLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, a, b, 0, A);
+    else hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), lds, s, A);
     PM_LAUNCH_CHECK();
+    if (tl_timer)
+      count_units(cl, g.xadj, CU_SOURCE, CountArgs{nullptr, nullptr, nullptr, rb.key, nullptr, nullptr},
+                  tl_timer->counters(KT_REB), s);
   }
   KPArgs K{};
   K.n = (int32_t)n;

@@ -25,7 +25,7 @@ int32_t env_pct(const char *name, int32_t dflt) {
 
 struct Store {
   std::atomic<int32_t> group_v, wave_min_count, hem_compact_min_n, reb_compact_min_n,
-      contract_rows_min_nnz, contract_rows_long_pct;
+      contract_rows_min_nnz, contract_rows_long_pct, lp_cache, graph_bodies;
   Store() {
     const int32_t v = env_or("PM_GROUP_V", 1);
     group_v = v == 2 ? 2 : 1;
@@ -34,6 +34,10 @@ struct Store {
     reb_compact_min_n = env_or("PM_REB_COMPACT_MIN_N", kRebCompactMinN);
     contract_rows_min_nnz = env_or("PM_CONTRACT_ROWS_MIN_NNZ", kContractRowsMinNnz);
     contract_rows_long_pct = env_pct("PM_CONTRACT_ROWS_LONG_PCT", kContractRowsLongPct);
+    const char *lc = std::getenv("PM_LP_CACHE");
+    lp_cache = (lc && lc[0] == '1' && lc[1] == 0) ? 1 : 0;
+    const char *gb = std::getenv("PM_GRAPH_BODIES");
+    graph_bodies = (gb && gb[0] == '1' && gb[1] == 0) ? 1 : 0;
   }
 };
 
@@ -51,7 +55,9 @@ TuningValues tuning() {
                       s.hem_compact_min_n.load(std::memory_order_relaxed),
                       s.reb_compact_min_n.load(std::memory_order_relaxed),
                       s.contract_rows_min_nnz.load(std::memory_order_relaxed),
-                      s.contract_rows_long_pct.load(std::memory_order_relaxed)};
+                      s.contract_rows_long_pct.load(std::memory_order_relaxed),
+                      s.lp_cache.load(std::memory_order_relaxed),
+                      s.graph_bodies.load(std::memory_order_relaxed)};
 }
 
 void set_tuning(const TuningValues &t) {
@@ -62,6 +68,8 @@ void set_tuning(const TuningValues &t) {
   s.reb_compact_min_n.store(t.reb_compact_min_n, std::memory_order_relaxed);
   s.contract_rows_min_nnz.store(t.contract_rows_min_nnz, std::memory_order_relaxed);
   s.contract_rows_long_pct.store(t.contract_rows_long_pct, std::memory_order_relaxed);
+  s.lp_cache.store(t.lp_cache, std::memory_order_relaxed);
+  s.graph_bodies.store(t.graph_bodies, std::memory_order_relaxed);
 }
 
 }  // namespace pm
@@ -79,6 +87,8 @@ int pm_get_tuning(pm_tuning *out) {
   out->reb_compact_min_n = t.reb_compact_min_n;
   out->contract_rows_min_nnz = t.contract_rows_min_nnz;
   out->contract_rows_long_pct = t.contract_rows_long_pct;
+  out->lp_cache = t.lp_cache;
+  out->graph_bodies = t.graph_bodies;
   return PM_OK;
 }
 
@@ -86,11 +96,13 @@ int pm_set_tuning(const pm_tuning *t) {
   if (!t) return PM_EINVAL;
   if ((t->group_v != 1 && t->group_v != 2) || t->wave_min_count < 1 ||
       t->hem_compact_min_n < 1 || t->reb_compact_min_n < 1 || t->contract_rows_min_nnz < 1 ||
-      t->contract_rows_long_pct < 0 || t->contract_rows_long_pct > 100)
+      t->contract_rows_long_pct < 0 || t->contract_rows_long_pct > 100 ||
+      (t->lp_cache != 0 && t->lp_cache != 1) ||
+      (t->graph_bodies != 0 && t->graph_bodies != 1))
     return PM_EINVAL;
   set_tuning(TuningValues{t->group_v, t->wave_min_count, t->hem_compact_min_n,
                           t->reb_compact_min_n, t->contract_rows_min_nnz,
-                          t->contract_rows_long_pct});
+                          t->contract_rows_long_pct, t->lp_cache, t->graph_bodies});
   return PM_OK;
 }
 

@@ -3,9 +3,12 @@ benchmark times (one pm_map call on a graph resident in HBM).
 
 rgg20 (n = 2^20): the oracle finishes the whole multilevel map in seconds,
 so the mapping is compared element by element.  rmat22 (n = 2^22, 2^25
-draws): the oracle cannot finish the whole map in test time, so the test
-checks J and the block weights of the GPU mapping with the oracle's plain
-definitions, the matching and contraction invariants at full size, and the
+draws): the oracle needs about an hour for the whole map, so its result for
+seed 1 is stored (tests/golden/rmat22_seed1.json, written by a script that
+calls only the oracle) and compared with the GPU's map; beside it, J and the
+block weights of the GPU mapping by the oracle's plain definitions, the
+matching and contraction invariants at full size, weak and strong
+rebalancing rounds on the whole graph element by element, and the
 first-filter results of a label-propagation round on a sample of vertices,
 each computed one by one with the oracle's equation-(1) gain; its two
 contraction paths must also give the same coarse graph.
@@ -204,3 +207,38 @@ def test_rmat22_rebalance_round_full_parity(pm, pmo, rmat22, strong):
         w0 = pmo.block_weights(g, part, w.k)
         w1 = pmo.block_weights(g, exp_part, w.k)
         assert not np.any((w0 <= lm) & (w1 > lm))
+
+
+def test_rmat22_map_equals_oracle_golden(pm, rmat22):
+    """The whole multilevel map of rmat22 (seed 1) against the oracle's result
+    stored by tests/golden/make_fullsize_golden.py (the oracle takes about an
+    hour single-threaded): the same input (SHA-256 of the CSR arrays), status,
+    J, graph sizes, loop bodies and matching rounds per level, block weights,
+    every 4096th block and the SHA-256 of the whole mapping."""
+    import hashlib
+
+    from conftest import golden
+    fx = golden("rmat22_seed1.json")
+    w, g = rmat22
+
+    def sha(a):
+        return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+    assert fx["graph"] == {"n": g.n, "nnz": g.nnz, "xadj": sha(g.xadj.astype("<i8")),
+                           "adjncy": sha(g.adjncy.astype("<i4")),
+                           "adjwgt": sha(g.adjwgt.astype("<i4")),
+                           "vwgt": sha(g.vwgt.astype("<i4"))}
+    say("rmat22 map against the golden result")
+    rc, part, st = pm.pm_map(pm.DeviceGraph.from_host(g), w.a, w.d, w.eps, fx["seed"])
+    p = host(part)
+    L = st.levels
+    assert rc == fx["status"] and st.j_final == fx["j_final"] and st.lmax == fx["lmax"]
+    assert L == fx["levels"]
+    assert list(st.level_n[:L]) == fx["level_n"]
+    assert list(st.level_nnz[:L]) == fx["level_nnz"]
+    assert list(st.level_iterations[:L]) == fx["level_iterations"]
+    assert list(st.level_hem_rounds[:L]) == fx["level_hem_rounds"]
+    assert p[::4096].tolist() == fx["part_every_4096"]
+    assert np.bincount(p, weights=g.vwgt, minlength=w.k).astype(np.int64).tolist() == \
+        fx["block_weights"]
+    assert sha(p.astype("<i4")) == fx["part_sha256"]

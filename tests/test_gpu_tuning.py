@@ -32,7 +32,8 @@ def test_invalid_tuning_is_refused(pm):
     before = pm.get_tuning()
     for bad in ({"group_v": 3}, {"wave_min_count": 0}, {"hem_compact_min_n": -1},
                 {"reb_compact_min_n": 0}, {"contract_rows_min_nnz": 0},
-                {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101}):
+                {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101},
+                {"lp_cache": 2}, {"graph_bodies": 2}):
         with pytest.raises(pm.PmError) as e:
             pm.set_tuning(**bad)
         assert e.value.code == pm.PM_EINVAL
@@ -48,7 +49,8 @@ def test_results_do_not_depend_on_tuning(pm, name):
     ref = host(part0, dg.n).copy()
     for c in candidates() + [{"wave_min_count": 1, "hem_compact_min_n": 1,
                               "reb_compact_min_n": 1, "contract_rows_min_nnz": 1,
-                              "contract_rows_long_pct": 100}]:
+                              "contract_rows_long_pct": 100}, {"lp_cache": 0},
+                             {"graph_bodies": 1}]:
         say("tuning", name, c)
         with pm.tuned(**c):
             rc, part, st = pm.pm_map(dg, w.a, w.d, w.eps, 3)
@@ -98,3 +100,63 @@ def test_batch_with_every_path_forced_equals_plain(pm):
         rc, part, st = pm.pm_map(*x)
         assert rc == rc_p and st.j_final == st_p.j_final
         assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n))
+
+
+def test_result_caching_is_exact_on_hubs(pm):
+    """Label propagation's result caching on a graph with many workgroup-sized
+    (BIG) vertices: three maps with caching and one without give the same
+    mapping (a vertex's cached result must be read by every wave of its
+    workgroup before it is marked evaluated)."""
+    g = gen.rmat(18, 1 << 21, 0xC3, name="rmat18")
+    dg = pm.DeviceGraph.from_host(g)
+    a, d = (4, 16, 8), (1, 10, 100)
+    say("cache off")
+    with pm.tuned(lp_cache=0):
+        rc0, part0, st0 = pm.pm_map(dg, a, d, 0.03, 1)
+    ref = host(part0, dg.n).copy()
+    for rep in range(3):
+        say("cache on", rep)
+        with pm.tuned(lp_cache=1):
+            rc, part, st = pm.pm_map(dg, a, d, 0.03, 1)
+        assert rc == rc0 and st.j_final == st0.j_final, rep
+        assert np.array_equal(host(part, dg.n), ref), rep
+
+
+@pytest.mark.parametrize("name", ["grid64", "rgg14", "rmat14", "rgg16p", "del16"])
+def test_graph_bodies_equal_the_oracle(pm, pmo, name):
+    """Loop bodies replayed from captured HIP graphs (graph_bodies=1): every
+    level replays its label-propagation and weak-rebalancing graphs many
+    times, with launched strong rounds and mapping copies between the
+    replays; the maps (two seeds, twice each) equal the oracle's."""
+    import torch
+    w = gen.get(name)
+    g = w.graph()
+    dg = pm.DeviceGraph.from_host(g)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()  # (the null stream cannot be captured)
+    for seed in (1, 2):
+        rc_h, part_h, st_h = pmo.map_graph(g, w.a, w.d, w.eps, seed)
+        for rep in range(2):
+            say("graph bodies", name, seed, rep)
+            with pm.tuned(graph_bodies=1), torch.cuda.stream(stream):
+                rc, part, st = pm.pm_map(dg, w.a, w.d, w.eps, seed)
+            stream.synchronize()
+            assert rc == rc_h and st.j_final == st_h.j_final, (seed, rep)
+            assert list(st.level_iterations[:st.levels]) == \
+                list(st_h.level_iterations[:st_h.levels])
+            assert np.array_equal(host(part, dg.n), part_h), (seed, rep)
+
+
+def test_graph_bodies_in_a_batch(pm):
+    """Concurrent jobs, each capturing and replaying its own bodies on its
+    worker's stream, equal the plain runs without graphs."""
+    members = gen.batch_members(32, log2_lo=10.0, log2_hi=14.0)
+    inst = [(pm.DeviceGraph.from_host(m.graph), m.a, m.d, m.eps, m.seed) for m in members]
+    plain = [pm.pm_map(*x) for x in inst]
+    say("batch with graph bodies")
+    with pm.tuned(graph_bodies=1):
+        for rep in range(2):
+            res = pm.pm_map_batch(inst, workers=8)
+            for m, (rc, part, job), (rc_p, part_p, st_p) in zip(members, res, plain):
+                assert rc == rc_p and job.j_final == st_p.j_final, rep
+                assert np.array_equal(host(part, m.graph.n), host(part_p, m.graph.n)), rep

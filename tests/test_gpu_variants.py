@@ -136,3 +136,38 @@ def test_invalid_options_are_rejected(pm, torch_mod):
         with pytest.raises(pm.PmError) as e:
             pm.pm_map(dg, (2, 2, 4), (1, 10, 100), 0.03, 1, opts=bad)
         assert e.value.code == pm.PM_EINVAL
+
+
+@pytest.mark.parametrize("name,a,d", CASES + [("grid64", (2, 2, 4), (1, 10, 100))])
+@pytest.mark.parametrize("repeats", [2, 5])
+def test_map_ultra_parity(pm, pmo, torch_mod, name, a, d, repeats):
+    """The "ultra" repetition (Algorithm 6 run `repeats` times per level) on
+    the GPU against the oracle: mapping, J and the loop bodies per level."""
+    g = gen.get(name).graph()
+    say("map ultra", repeats, name, a)
+    rc_h, part_h, st_h = pmo.map_graph(g, a, d, 0.03, 3, pmo.variants(repeats=repeats))
+    rc_d, part_d, st_d = pm.pm_map(pm.DeviceGraph.from_host(g), a, d, 0.03, 3,
+                                   opts=pm.options(repeats=repeats))
+    assert rc_d == rc_h and st_d.j_final == st_h.j_final
+    assert list(st_d.level_iterations[:st_d.levels]) == list(st_h.level_iterations[:st_h.levels])
+    assert np.array_equal(host(part_d), part_h)
+
+
+@pytest.mark.parametrize("name,a", [("rgg14", (4, 8, 8)), ("rmat14", (4, 16, 8))])
+def test_hm_ultra_parity(pm, pmo, name, a):
+    """GPU-HM-ultra: every partitioning call refines 18 times per level."""
+    g = gen.get(name).graph()
+    say("hm ultra", name, a)
+    rc_o, part_o = pmo.hm(g, a, 0.03, 2, pmo.variants(repeats=18))
+    rc, part, j, calls = pm.pm_map_hm(pm.DeviceGraph.from_host(g), a, (1, 10, 100), 0.03, 2,
+                                      opts=pm.options(repeats=18))
+    assert rc == rc_o and np.array_equal(host(part), part_o)
+
+
+def test_invalid_repeats_are_rejected(pm):
+    g = gen.get("grid64").graph()
+    dg = pm.DeviceGraph.from_host(g)
+    for r in (-1, 65):
+        with pytest.raises(pm.PmError) as e:
+            pm.pm_map(dg, (2, 2, 4), (1, 10, 100), 0.03, 1, opts=pm.options(repeats=r))
+        assert e.value.code == pm.PM_EINVAL

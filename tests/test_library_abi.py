@@ -56,7 +56,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(pm.PmGraph) == 8 + 8 + 4 * 8
     assert ctypes.sizeof(pm.PmHierarchy) == 4 + 8 * 4 + 8 * 4
     assert ctypes.sizeof(pm.PmRefineStats) == 4 * 8 + 6 * 4 + 8 + 8
-    assert pm.PmMapStats.kernel_bytes.offset == ctypes.sizeof(pm.PmMapStats) - 4 * 8
+    assert pm.PmMapStats.kernel_units.offset == ctypes.sizeof(pm.PmMapStats) - 5 * 3 * 8
+    assert pm.PmMapStats.kernel_bytes.offset == pm.PmMapStats.kernel_units.offset - 5 * 8
     assert pm.PmMapStats.refine_arcs.offset + 8 == pm.PmMapStats.kernel_launches.offset
     # pm_map_job: graph 48, hierarchy 68 (+4 padding), eps, seed, part, 2 x int32, j, ms
     assert ctypes.sizeof(pm.PmMapJob) == 168 and pm.PmMapJob.eps.offset == 120
@@ -73,7 +74,7 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
 
 def test_tuning_struct_layout():
     import paper_2510_12196_amd as pm
-    assert ctypes.sizeof(pm.PmTuning) == 24
+    assert ctypes.sizeof(pm.PmTuning) == 32
 
 
 def test_tuning_host_logic_without_gpu():
@@ -84,7 +85,8 @@ def test_tuning_host_logic_without_gpu():
     before = pm.get_tuning()
     try:
         for bad in ({"group_v": 0}, {"wave_min_count": 0}, {"contract_rows_min_nnz": 0},
-                    {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101}):
+                    {"contract_rows_long_pct": -1}, {"contract_rows_long_pct": 101},
+                    {"lp_cache": 2}, {"lp_cache": -1}, {"graph_bodies": 2}):
             with pytest.raises(pm.PmError) as e:
                 pm.set_tuning(**bad)
             assert e.value.code == pm.PM_EINVAL and pm.get_tuning() == before

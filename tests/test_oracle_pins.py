@@ -880,3 +880,54 @@ def test_hm_is_hierarchical_and_balanced(pmo, name, a):
     if rc == 0:
         w = pmo.block_weights(g, part, k)
         assert w.max() <= pmo.lmax(int(g.vwgt.sum()), k, 0.03)
+
+
+# ----------------------------------------------------------------------------
+# the "ultra" repetition (Section 5: Jet's ultra configuration runs the complete
+# refinement 18 times): Algorithm 6 runs `repeats` times per level
+# ----------------------------------------------------------------------------
+
+def test_ultra_one_run_is_the_method(pmo):
+    w = gen.get("rgg14")
+    g = w.graph()
+    base = pmo.map_graph(g, w.a, w.d, w.eps, 3)
+    for r in (0, 1):
+        rc, part, st = pmo.map_graph(g, w.a, w.d, w.eps, 3, pmo.variants(repeats=r))
+        assert rc == base[0] and np.array_equal(part, base[1]) and st.j_final == base[2].j_final
+
+
+def test_ultra_single_level_is_refinement_repeated(pmo):
+    """Below 8k vertices nothing is coarsened: the map is the initial
+    partition refined; with repeats R it is that refinement run R times, run r
+    from run r - 1's result with seed + r."""
+    g = gen.grid2d(10, 11)
+    a, d, eps = (2, 2, 4), (1, 10, 100), 0.03     # k = 16: 110 < 8k, one level
+    part = pmo.initial_partition(g, a)
+    for r in range(3):
+        rc_r, part, st_r = pmo.refine(g, a, d, eps, 7 + r, part, level=0)
+    rc, mp, st = pmo.map_graph(g, a, d, eps, 7, pmo.variants(repeats=3))
+    assert st.levels == 1
+    assert rc == rc_r and np.array_equal(mp, part) and st.j_final == st_r.j_final
+
+
+@pytest.mark.parametrize("name", ["rgg14", "rmat14"])
+def test_ultra_repeats_refinement_at_every_level(pmo, name):
+    """Every run of Algorithm 6 has at least 12 loop bodies, so with R runs a
+    level records at least 12 R; a second run from a run's own result never
+    raises J (only strictly better feasible mappings replace the best)."""
+    w = gen.get(name)
+    g = w.graph()
+    rc, part, st = pmo.map_graph(g, w.a, w.d, w.eps, 5, pmo.variants(repeats=4))
+    assert all(st.level_iterations[s] >= 48 for s in range(st.levels))
+    assert pmo.block_weights(g, part, w.k).max() <= st.lmax
+    rc1, p1, s1 = pmo.refine(g, w.a, w.d, w.eps, 5, gen.random_balanced_mapping(g.n, w.k, 2))
+    rc2, p2, s2 = pmo.refine(g, w.a, w.d, w.eps, 6, p1)
+    assert s1.feasible and s2.feasible and s2.j_final <= s1.j_final
+
+
+def test_ultra_hm_one_run_is_the_method(pmo):
+    w = gen.get("rgg14")
+    g = w.graph()
+    rc0, p0 = pmo.hm(g, w.a, w.eps, 2)
+    rc1, p1 = pmo.hm(g, w.a, w.eps, 2, pmo.variants(repeats=1))
+    assert rc0 == rc1 and np.array_equal(p0, p1)
