@@ -1075,24 +1075,22 @@ struct ApV {
   uint32_t p, t;
 };
 
-// One arc of a mover: neighbour, weight, its block, target and moved flag.
-struct ApArc {
-  int32_t u, w, pu, tu;
-  uint8_t mu;
-};
-__device__ __forceinline__ ApArc ap_arc(const ApplyArgs &A, int64_t e) {
-  const int32_t u = A.g.adj[e];
-  return ApArc{u, A.g.w[e], A.part[u], A.target[u], A.moved[u]};
+// One arc of a mover (u its other end): weight, u's block, target and moved
+// flag.  With result caching u is marked here, where it is known.
+__device__ __forceinline__ int4 ap_arc(const ApplyArgs &A, int32_t u, int64_t e) {
+  if (A.dirty) A.dirty[u] = 1;
+  return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+}
+__device__ __forceinline__ int4 ap_arc(const ApplyArgs &A, int64_t e) {
+  return ap_arc(A, A.g.adj[e], e);
 }
 // J change of one arc of a mover p -> t: an arc whose other end moved too is
-// seen from both sides (once each), else from the mover only (twice).  With
-// result caching the neighbour is marked.
+// seen from both sides (once each), else from the mover only (twice).
 __device__ __forceinline__ int64_t ap_delta(const ApplyArgs &A, uint32_t p, uint32_t t,
-                                            const ApArc &a) {
-  if (A.dirty) A.dirty[a.u] = 1;
-  const uint32_t old_u = (uint32_t)a.pu;
-  if (a.mu) return (int64_t)a.w * (dist(A.h, t, (uint32_t)a.tu) - dist(A.h, p, old_u));
-  return 2 * (int64_t)a.w * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
+                                            const int4 &a) {
+  const uint32_t old_u = (uint32_t)a.y;
+  if (a.w) return (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
+  return 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
 }
 // The mover's own record: block-weight deltas, and its mark.
 __device__ __forceinline__ void ap_mover(const ApplyArgs &A, int32_t v, uint32_t p, uint32_t t,
@@ -1114,8 +1112,8 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
         act = A.moved[v] != 0;
         return ApV{(uint32_t)A.part[v], (uint32_t)A.target[v]};
       },
-      [&](int32_t, int64_t e) { return ap_arc(A, e); },
-      [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, const ApArc &a) {
+      [&](int32_t u, int64_t e) { return ap_arc(A, u, e); },
+      [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, const int4 &a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
         if (A.lock && lane == 0) A.lock[v] = act ? 1 : 0;
@@ -1169,7 +1167,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
           if ((threadIdx.x & 63) == 0) ap_mover(A, v, p, t, mv);
           wave_arcs<4>(
               A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return ap_arc(A, e); },
-              [&](int64_t, const ApArc &a) { x += ap_delta(A, p, t, a); });
+              [&](int64_t, const int4 &a) { x += ap_delta(A, p, t, a); });
         }
       }
       wmove_flush(A, mv);
@@ -1186,7 +1184,7 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
         wmove_flush(A, mv);
         big_arcs(
             A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return ap_arc(A, e); },
-            [&](int64_t, const ApArc &a) { x += ap_delta(A, p, t, a); });
+            [&](int64_t, const int4 &a) { x += ap_delta(A, p, t, a); });
       }
       break;
     }
@@ -1346,7 +1344,10 @@ __device__ __forceinline__ void reb_finish(const RebArgs &A, int32_t v, uint32_t
 __device__ __forceinline__ bool reb_random(const RebArgs &A, int32_t v, uint32_t &b) {
   const int32_t ne = *A.n_elig;
   if (ne <= 0) return false;
-  b = (uint32_t)A.elig[mix_hash(A.hseed, (uint64_t)v) % (uint64_t)ne];
+  // (the arguments stay unmodified: a written kernel argument is copied to
+  // private memory, with the tables indexed from it)
+  const uint64_t hs = A.body_ctr ? mix_hash(A.hseed, (uint64_t)(*A.body_ctr + 1)) : A.hseed;
+  b = (uint32_t)A.elig[mix_hash(hs, (uint64_t)v) % (uint64_t)ne];
   return true;
 }
 
@@ -1578,7 +1579,6 @@ template <int V>
 __global__ __launch_bounds__(kThreads) void k_reb_select(RebArgs A) {
   extern __shared__ uint32_t X[];
   __shared__ BlockScratch sc;
-  if (A.body_ctr) A.hseed = mix_hash(A.hseed, (uint64_t)(*A.body_ctr + 1));
   const int blk = blockIdx.x;
   const int cls = find_class(A.cl, blk);
   const int local = blk - A.cl.wg[cls];
