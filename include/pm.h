@@ -240,6 +240,21 @@ int pm_set_tuning(const pm_tuning *t);
 int pm_comm_cost(const pm_graph *g, const pm_hierarchy *h, const int32_t *part,
                  int64_t *j_out, uint32_t flags, void *stream);
 
+/* pm_comm_cost without any allocation, for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc).
+ * Same J and the same mapping check (a block id outside [0,k) returns
+ * PM_EINVAL, *j_out = 0); the CSR structure and weights are trusted as
+ * pm_comm_cost without PM_FLAG_VALIDATE trusts the structure.  Arguments as
+ * for pm_comm_cost; more than INT32_MAX arcs returns PM_EOVERFLOW.  Its work
+ * space is a fixed device array of the library (4096 partial sums, 33 280
+ * bytes per device, kept until the process ends): any graph size fits it, as
+ * a grid of at most 4096 workgroups walks the vertices.  Every call on
+ * one device shares that array, so calls that overlap on a device (several
+ * streams or threads at once) race and must be serialised by the caller.
+ * Returns after the result is on the host (the stream is synchronised). */
+int pm_comm_cost_noalloc(const pm_graph *g, const pm_hierarchy *h, const int32_t *part,
+                         int64_t *j_out, void *stream);
+
 /* Block weights c(V_b) for b in [0,k) (Section 2).  w_out: device int64[k]. */
 int pm_block_weights(const pm_graph *g, const pm_hierarchy *h,
                      const int32_t *part, int64_t *w_out, void *stream);

@@ -89,6 +89,7 @@ _SIGS = {
     "pm_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pm_release": (None, []),
     "pm_comm_cost": (ctypes.c_int, [_P, _P, _P, _P, _U32, _P]),
+    "pm_comm_cost_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "pm_block_weights": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "pm_lp_round": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, _P]),
     "pm_rebalance": (ctypes.c_int, [_P, _P, _I32, _I64, _I64, _U64, _I32, _I32, _P, _P, _P]),
@@ -300,6 +301,16 @@ def pm_comm_cost(g: DeviceGraph, a, d, part, validate: bool = False) -> int:
     _check(lib().pm_comm_cost(ctypes.byref(gs), ctypes.byref(hs), _dev(part, "int32", g.n),
                               ctypes.byref(out), PM_FLAG_VALIDATE if validate else 0, _stream()),
            "pm_comm_cost")
+    return int(out.value)
+
+
+def pm_comm_cost_noalloc(g: DeviceGraph, a, d, part) -> int:
+    """pm_comm_cost through the entry point that allocates nothing."""
+    out = ctypes.c_int64(0)
+    gs, hs = g.struct(), hierarchy(a, d)
+    _check(lib().pm_comm_cost_noalloc(ctypes.byref(gs), ctypes.byref(hs),
+                                      _dev(part, "int32", g.n), ctypes.byref(out), _stream()),
+           "pm_comm_cost_noalloc")
     return int(out.value)
 
 
@@ -541,7 +552,8 @@ class PmServer:
 
 __all__ = ["PmOptions", "options", "PM_VARIANT_JET_FILTER", "PM_VARIANT_J_REBALANCE",
            "DeviceGraph", "PmError", "PmGraph", "PmHierarchy", "PmMapStats", "PmRefineStats",
-           "hierarchy", "lib", "pm_version", "pm_release", "pm_comm_cost", "pm_block_weights",
+           "hierarchy", "lib", "pm_version", "pm_release", "pm_comm_cost", "pm_comm_cost_noalloc",
+           "pm_block_weights",
            "pm_lp_round", "pm_rebalance", "pm_refine", "pm_hem", "pm_contract",
            "pm_initial_partition", "pm_map", "PmMapJob", "make_job", "pm_map_batch",
            "pm_job_footprint", "PmServer"]
