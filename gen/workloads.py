@@ -124,23 +124,31 @@ def instance(kind: str, n: int, a, seed: int, name: str) -> Instance:
     return Instance(name, g, tuple(a), D3, 0.03, 1)
 
 
+def batch_spec(i: int, base_seed: int = 0xC4, log2_lo: float = 10.0, log2_hi: float = 16.0):
+    """Member i of the batched workload, unbuilt: (kind, n, a, graph_seed,
+    seed) with n = floor(2^U(lo,hi)), kind grid / rgg / rmat with probability
+    1/3 each, hierarchy drawn from 2:2:4, 4:4:8, 4:8:8."""
+    rng = _member_rng(base_seed, i)
+    n = int(np.floor(2.0 ** rng.uniform(log2_lo, log2_hi)))
+    kind = ["grid", "rgg", "rmat"][int(rng.integers(0, 3))]
+    a = BATCH_HIERARCHIES[int(rng.integers(0, 3))]
+    gseed = int(rng.integers(0, 2 ** 31))
+    return kind, n, a, gseed, 1 + int(rng.integers(0, 5))
+
+
+def batch_member(i: int, base_seed: int = 0xC4, log2_lo: float = 10.0,
+                 log2_hi: float = 16.0) -> Instance:
+    kind, n, a, gseed, seed = batch_spec(i, base_seed, log2_lo, log2_hi)
+    inst = instance(kind, n, a, gseed, f"{kind}{n}")
+    inst.seed = seed
+    return inst
+
+
 def batch_members(count: int = 512, base_seed: int = 0xC4, log2_lo: float = 10.0,
                   log2_hi: float = 16.0):
-    """Instances of the batched workload: n = floor(2^U(lo,hi)), kind grid /
-    rgg / rmat with probability 1/3 each, hierarchy drawn from 2:2:4, 4:4:8,
-    4:8:8, distances 1:10:100, eps 3 %; everything derived from
-    (base_seed, index)."""
-    out = []
-    for i in range(count):
-        rng = _member_rng(base_seed, i)
-        n = int(np.floor(2.0 ** rng.uniform(log2_lo, log2_hi)))
-        kind = ["grid", "rgg", "rmat"][int(rng.integers(0, 3))]
-        a = BATCH_HIERARCHIES[int(rng.integers(0, 3))]
-        gseed = int(rng.integers(0, 2 ** 31))
-        inst = instance(kind, n, a, gseed, f"{kind}{n}")
-        inst.seed = 1 + int(rng.integers(0, 5))
-        out.append(inst)
-    return out
+    """Instances of the batched workload (batch_spec), distances 1:10:100,
+    eps 3 %; everything derived from (base_seed, index)."""
+    return [batch_member(i, base_seed, log2_lo, log2_hi) for i in range(count)]
 
 
 def serve_arrivals(count: int, qps: float, base_seed: int = 0xC5):
@@ -170,4 +178,35 @@ def serve_stream(count: int, qps: float, base_seed: int = 0xC5, log2_lo: float =
         inst = instance(kind, n, a, gseed, f"{kind}{n}")
         inst.seed = 1 + int(rng.integers(0, 5))
         out.append((t, inst))
+    return out
+
+
+SERVE_HIERARCHIES = ((4, 8, 8), (4, 16, 8))
+
+
+def serve_pool_spec(pool: int, base_seed: int = 0xC5, log2_lo: float = 12.0,
+                    log2_hi: float = 20.0):
+    """The resident graphs of the pooled served workload, as (kind, n,
+    graph_seed, name) tuples: n = floor(2^U(lo,hi)), rgg or rmat 1/2 each;
+    instance(kind, n, a, graph_seed, name) builds one (a is per request)."""
+    out = []
+    for i in range(pool):
+        rng = _member_rng(base_seed ^ 0x9001, i)
+        n = int(np.floor(2.0 ** rng.uniform(log2_lo, log2_hi)))
+        kind = "rgg" if rng.integers(0, 2) == 0 else "rmat"
+        out.append((kind, n, int(rng.integers(0, 2 ** 31)), f"{kind}{n}"))
+    return out
+
+
+def serve_requests(count: int, pool: int, base_seed: int = 0xC5):
+    """Requests of the pooled served workload: request i maps pool graph
+    `graph` (uniform over the pool) onto hierarchy 4:8:8 or 4:16:8 (1/2
+    each) with seed 1..5; arrival times come from serve_arrivals(count, qps,
+    base_seed).  Returns (graph_index, a, seed) triples."""
+    out = []
+    for i in range(count):
+        rng = _member_rng(base_seed ^ 0x9002, i)
+        out.append((int(rng.integers(0, pool)),
+                    SERVE_HIERARCHIES[int(rng.integers(0, 2))],
+                    1 + int(rng.integers(0, 5))))
     return out
