@@ -164,8 +164,9 @@ typedef struct pm_map_stats {
    *   [1] 24 per active arc (neighbour id, weight, block, target, gain)
    *       + 16 per active vertex (row offsets, block, target) + 9 per tiled
    *       vertex (gain, moved flag)
-   *   [2] 17 per active arc (neighbour id, weight, block, target, moved
-   *       flag) + 20 per mover (row offsets, block, target, weight)
+   *   [2] 16 per active arc (neighbour id, weight, and the neighbour's
+   *       block and target-or-none) + 20 per mover (row offsets, block,
+   *       target, weight)
    *   [3] 16 per active arc (neighbour id, weight, its match, its weight)
    *       + 12 per tiled vertex (match, preference, weight)
    *   [4] 12 per active arc + 24 per source (row offsets, block, weight,

@@ -182,9 +182,9 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
   const int64_t n = g.n;
   const int32_t ncodes = 1 << h.bits;
   int32_t *cur = ar.alloc_n<int32_t>(n);
-  int32_t *target = ar.alloc_n<int32_t>(n);   // label propagation (kept between its rounds)
+  LpRec *rec = ar.alloc_n<LpRec>(n);          // label propagation (kept between its rounds)
   int32_t *rtarget = ar.alloc_n<int32_t>(n);  // rebalancing
-  int64_t *gain = ar.alloc_n<int64_t>(n);
+  int2 *pn = ar.alloc_n<int2>(n);             // apply's neighbour records
   uint8_t *moved = ar.alloc_n<uint8_t>(n);
   uint8_t *lock = ar.alloc_n<uint8_t>(n);
   int64_t *w = ar.alloc_n<int64_t>(ncodes);
@@ -278,9 +278,9 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     Pub pub{};
     if (imb_cur <= lmax) {
       auto body = [&] {
-        lp_phase1(g, cl, h, cur, lock, target, gain, s, var, dirty);
-        lp_phase2(g, cl, h, cur, target, gain, moved, s);
-        apply_moves(g, cl, h, cur, target, moved, lock, w, wst, cx.sp.a, &E, s, dirty);
+        lp_phase1(g, cl, h, cur, lock, rec, s, var, dirty);
+        lp_phase2(g, cl, h, rec, moved, pn, s);
+        apply_moves(g, cl, h, cur, nullptr, moved, lock, w, wst, cx.sp.a, &E, pn, s, dirty);
       };
       if (use_graphs) {
         pub = replay(bgs[0], body);
@@ -310,12 +310,12 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
         pub = replay(bgs[1], [&] {
           rebalance_round(ar, g, rcl, h, false, lmax, sigma, total, reb_seed, cur, w, rtarget,
                           moved, rb, cx.dev, s, var, body_ctr);
-          apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, s, dirty);
+          apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
         });
       } else {
         rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, rtarget, moved,
                         rb, cx.dev, s, var);
-        apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, s, dirty);
+        apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
         pub = cx.publish();
       }
       if (strong) {
@@ -728,10 +728,13 @@ int pm_lp_round_ex(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint
     Classes cl = build_classes(*lease, dg, list, cx.dev, cx.host, s);
     int64_t *w = lease->alloc_n<int64_t>((size_t)1 << hh.bits);
     block_weights(dg, hh, codes, w, s);
-    lp_phase1(dg, cl, hh, codes, lock, target_out, gain_out, s, var);
-    lp_phase2(dg, cl, hh, codes, target_out, gain_out, moved_out, s);
-    apply_moves(dg, cl, hh, codes, target_out, moved_out, lock, w,
-                alloc_weight_stripes(*lease, hh, s), cx.sp.a, nullptr, s);
+    LpRec *rec = lease->alloc_n<LpRec>(dg.n);
+    int2 *pn = lease->alloc_n<int2>(dg.n);
+    lp_phase1(dg, cl, hh, codes, lock, rec, s, var);
+    unpack_lp(rec, target_out, gain_out, dg.n, s);
+    lp_phase2(dg, cl, hh, rec, moved_out, pn, s);
+    apply_moves(dg, cl, hh, codes, nullptr, moved_out, lock, w,
+                alloc_weight_stripes(*lease, hh, s), cx.sp.a, nullptr, pn, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     codes_to_ids(hh, target_out, target_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
@@ -778,7 +781,7 @@ int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong, in
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
                     moved_out, rb, cx.dev, s, var);
     apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s),
-                cx.sp.a, nullptr, s);
+                cx.sp.a, nullptr, ar.alloc_n<int2>(dg.n), s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;

@@ -16,6 +16,14 @@ struct Status {
   int64_t aux;         // generic 64-bit result
 };
 
+// Label propagation's per-vertex result: block, target and gain (one 16-byte
+// record, so that phase 2 gathers a neighbour's in one load).
+struct __align__(16) LpRec {
+  int32_t p;
+  int32_t t;
+  int64_t g;
+};
+
 // A status publication: the kernel that ends a step copies the Status into
 // mapped host memory (host, device view) and then stores seq into seq_slot;
 // the host polls seq_slot.  host == nullptr: no publication.
@@ -111,7 +119,7 @@ struct KernelTimer {
 struct CountArgs {
   const uint8_t *flag8;  // lock (CU_UNLOCKED) or moved (CU_MOVED)
   const uint8_t *dirty;  // CU_UNLOCKED with result caching: only dirty vertices
-  const int64_t *gain;   // CU_IN_X
+  const LpRec *rec;      // CU_IN_X
   const int32_t *key;    // CU_SOURCE
   const int32_t *match;  // CU_HEM_ACTIVE
   const int32_t *pref;
@@ -160,13 +168,18 @@ struct Variants {
 };
 
 // ---- label propagation (Algorithm 4) --------------------------------------
-// dirty != nullptr: result caching (unlocked vertices that are not dirty keep
-// their last target and gain; see apply_moves)
+// Phase 1 writes rec[v] = {block, target, gain} for every vertex (gain
+// kNotInX outside X).  dirty != nullptr: result caching (unlocked vertices
+// that are not dirty keep their last record; see apply_moves)
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
+               const uint8_t *lock, LpRec *rec, hipStream_t s,
                const Variants &var = Variants{}, uint8_t *dirty = nullptr);
-void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s);
+// target[v], gain[v] <- rec[v] (the per-phase entry point's outputs)
+void unpack_lp(const LpRec *rec, int32_t *target, int64_t *gain, int64_t n, hipStream_t s);
+// Phase 2 writes moved[v] and pn[v] = {block, moved ? target : -1} (every
+// vertex with a neighbour), the records apply_moves gathers.
+void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const LpRec *rec,
+               uint8_t *moved, int2 *pn, hipStream_t s);
 // Applies moved[v] -> part[v] = target[v]; accumulates the exact J change into
 // dj_stripes and the block weight changes into w (through the weight-delta
 // stripes wst, zero on entry and on return); sets lock = moved if lock != 0.
@@ -177,9 +190,12 @@ int weight_stripes(const Hier &h, int64_t n);   // stripes in use (power of two)
 int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 // dirty != nullptr: marks every mover and every neighbour of a mover (the
 // result caching of label propagation)
+// pn: g.n records {block, moved ? target : -1} gathered for the neighbours of
+// movers; with target != nullptr they are first written from (part, target,
+// moved), with target == nullptr they are phase 2's.
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s,
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, int2 *pn, hipStream_t s,
                  uint8_t *dirty = nullptr);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_count_units(Classes cl, const int6
     bool act = false;
     switch (what) {
       case CU_UNLOCKED: act = a.flag8[v] == 0 && (!a.dirty || a.dirty[v]); break;
-      case CU_IN_X: act = a.gain[v] != kNotInX; break;
+      case CU_IN_X: act = a.rec[v].g != kNotInX; break;
       case CU_MOVED: act = a.flag8[v] != 0; break;
       case CU_SOURCE: act = a.key[v] >= 0; break;
       default: {  // a vertex that looks for a partner (matching preference)
@@ -549,8 +549,7 @@ struct LP1Args {
   Hier h;
   const int32_t *part;
   const uint8_t *lock;
-  int32_t *target;
-  int64_t *gain;
+  LpRec *rec;       // per vertex {block, target, gain}
   int64_t jet_num;  // > 0: relaxed filter -G < floor(jet_num * conn(v,own) / jet_den)
   int64_t jet_den;
   int32_t whist;    // G64 vertices use a per-wave LDS histogram (LDS: 4 slices)
@@ -561,8 +560,7 @@ struct LP1Args {
 // only on its block and its neighbours' blocks; dirty[v] is set when v or a
 // neighbour moves (by the move accounting) and cleared when v is evaluated
 // here, so an unlocked vertex that is not dirty keeps the target and gain of
-// its last evaluation (they stay in target[] / gain[], which only this kernel
-// writes).  State of v: 0 locked (trivial result), 1 cached (nothing to
+// its last evaluation (they stay in rec[], which only this kernel writes).  State of v: 0 locked (trivial result), 1 cached (nothing to
 // write), 2 evaluated.
 __device__ __forceinline__ int lp1_state(const LP1Args &A, int32_t v) {
   if (A.lock[v]) return 0;
@@ -571,6 +569,12 @@ __device__ __forceinline__ int lp1_state(const LP1Args &A, int32_t v) {
 }
 __device__ __forceinline__ void lp1_evaluated(const LP1Args &A, int32_t v) {
   if (A.dirty) A.dirty[v] = 0;
+}
+// The result of v: one 16-byte record (block, target, gain); gain kNotInX
+// (and target = block) for a vertex outside X.
+__device__ __forceinline__ void lp1_put(const LP1Args &A, int32_t v, uint32_t p, uint32_t t,
+                                        int64_t g) {
+  A.rec[v] = LpRec{(int32_t)p, (int32_t)t, g};
 }
 
 // First filter: G >= 0, or with Jet's relaxed filter -G < floor(c conn_own).
@@ -608,8 +612,7 @@ __device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) 
         if (act && lane == 0) lp1_evaluated(A, v);
         if (!act || !gor<G>(cand ? 1 : 0)) {
           if (lane == 0) {
-            A.target[v] = (int32_t)p;
-            A.gain[v] = kNotInX;
+            lp1_put(A, v, p, p, kNotInX);
           }
           return;
         }
@@ -626,11 +629,9 @@ __device__ __forceinline__ void lp1_group(const LP1Args &A, int cls, int local) 
         const int64_t conn_own = A.jet_num > 0 ? gsum64<G>(valid && bu == p ? wu : 0) : 0;
         if (lane == 0) {
           if (lp1_pass(A, g, conn_own)) {
-            A.target[v] = (int32_t)b;
-            A.gain[v] = g;
+            lp1_put(A, v, p, b, g);
           } else {
-            A.target[v] = (int32_t)p;
-            A.gain[v] = kNotInX;
+            lp1_put(A, v, p, p, kNotInX);
           }
         }
       });
@@ -675,8 +676,7 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X
   if (st == 1) return;
   if (st == 0) {
     if (threadIdx.x == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
     return;
   }
@@ -689,8 +689,7 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X
   const uint32_t connp = X[p + 1] - X[p];
   if (total == connp) {
     if (threadIdx.x == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
     return;
   }
@@ -708,11 +707,9 @@ __device__ __forceinline__ void lp1_big(const LP1Args &A, int32_t v, uint32_t *X
   block_argmax(g, b, sc);
   if (threadIdx.x == 0) {
     if (lp1_pass(A, g, (int64_t)connp)) {
-      A.target[v] = (int32_t)b;
-      A.gain[v] = g;
+      lp1_put(A, v, p, b, g);
     } else {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
   }
 }
@@ -742,8 +739,7 @@ __device__ __forceinline__ void lp1_wave(const LP1Args &A, int local, uint32_t *
         if (act && lane == 0) lp1_evaluated(A, v);
         if (!act || !gor<64>(cand ? 1 : 0)) {
           if (lane == 0) {
-            A.target[v] = (int32_t)p;
-            A.gain[v] = kNotInX;
+            lp1_put(A, v, p, p, kNotInX);
           }
           return;
         }
@@ -759,11 +755,9 @@ __device__ __forceinline__ void lp1_wave(const LP1Args &A, int local, uint32_t *
         gargmax<64>(g, b);
         if (lane == 0) {
           if (lp1_pass(A, g, (int64_t)(Xw[p + 1] - Xw[p]))) {
-            A.target[v] = (int32_t)b;
-            A.gain[v] = g;
+            lp1_put(A, v, p, b, g);
           } else {
-            A.target[v] = (int32_t)p;
-            A.gain[v] = kNotInX;
+            lp1_put(A, v, p, p, kNotInX);
           }
         }
         wave_lds_sync();  // the slice is cleared again for the next vertex
@@ -781,8 +775,7 @@ __device__ __forceinline__ void lp1_w(const LP1Args &A, int local, uint32_t *X) 
   if (st == 1) return;
   if (st == 0) {
     if (lane == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
     return;
   }
@@ -801,8 +794,7 @@ __device__ __forceinline__ void lp1_w(const LP1Args &A, int local, uint32_t *X) 
   const uint32_t connp = Xw[p + 1] - Xw[p];
   if (Xw[ncodes] == connp) {
     if (lane == 0) {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
     return;
   }
@@ -820,11 +812,9 @@ __device__ __forceinline__ void lp1_w(const LP1Args &A, int local, uint32_t *X) 
   gargmax<64>(g, b);
   if (lane == 0) {
     if (lp1_pass(A, g, (int64_t)connp)) {
-      A.target[v] = (int32_t)b;
-      A.gain[v] = g;
+      lp1_put(A, v, p, b, g);
     } else {
-      A.target[v] = (int32_t)p;
-      A.gain[v] = kNotInX;
+      lp1_put(A, v, p, p, kNotInX);
     }
   }
 }
@@ -840,8 +830,8 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
     switch (cls) {
       case CLS_ISO:
         iso_tiles<V>(A.cl, local, [&](int32_t v) {
-          A.target[v] = A.part[v];
-          A.gain[v] = kNotInX;
+          const uint32_t p = (uint32_t)A.part[v];
+          lp1_put(A, v, p, p, kNotInX);
         });
         break;
       case CLS_G8: lp1_group<8, V>(A, cls, local); break;
@@ -861,19 +851,34 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase1(LP1Args A) {
   }
 }
 
+__global__ __launch_bounds__(kThreads) void k_unpack_lp(const LpRec *rec, int32_t *target,
+                                                        int64_t *gain, int64_t n) {
+  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (v >= n) return;
+  const LpRec r = rec[v];
+  target[v] = r.t;
+  gain[v] = r.g;
+}
+
+void unpack_lp(const LpRec *rec, int32_t *target, int64_t *gain, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_unpack_lp, dim3(grid_for(n)), dim3(kThreads), 0, s, rec, target, gain, n);
+  PM_LAUNCH_CHECK();
+}
+
 static size_t big_lds(const Hier &h) { return sizeof(uint32_t) * ((size_t(1) << h.bits) + 1); }
 
 void lp_phase1(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const uint8_t *lock, int32_t *target, int64_t *gain, hipStream_t s,
-               const Variants &var, uint8_t *dirty) {
+               const uint8_t *lock, LpRec *rec, hipStream_t s, const Variants &var,
+               uint8_t *dirty) {
   const int V = group_v();
   // four per-wave histogram slices fit in 32 KiB up to 2^10 codes
   const int whist = h.bits <= 10;
   const Classes tc = tiled(cl, V, !whist);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP1Args A{g, tc, h, part, lock, target, gain, var.jet_num, var.jet_den > 0 ? var.jet_den : 1,
-            whist, dirty};
+  LP1Args A{g, tc, h, part, lock, rec, var.jet_num, var.jet_den > 0 ? var.jet_den : 1, whist,
+            dirty};
   const size_t lds = whist ? 4 * big_lds(h) : big_lds(h);
   auto kern = V == 2 ? k_lp_phase1<2> : k_lp_phase1<1>;
   if (tl_timer) count_units(cl, g.xadj, CU_UNLOCKED, CountArgs{lock, dirty, nullptr, nullptr,
@@ -900,10 +905,9 @@ struct LP2Args {
   DGraph g;
   Classes cl;
   Hier h;
-  const int32_t *part;
-  const int32_t *target;
-  const int64_t *gain;
+  const LpRec *rec;  // phase 1's {block, target, gain} per vertex
   uint8_t *moved;
+  int2 *pn;          // out: {block, moved ? target : -1} per vertex (k_apply's records)
 };
 
 struct Lp2Arc {
@@ -916,21 +920,33 @@ struct Lp2V {
   uint32_t p, t;
 };
 
+// one 16-byte gather per arc: the neighbour's block, target and gain
+__device__ __forceinline__ Lp2Arc lp2_arc(const LP2Args &A, int32_t u, int64_t e) {
+  const LpRec r = A.rec[u];
+  return Lp2Arc{u, A.g.w[e], r.p, r.t, r.g};
+}
+// v's outcome: moved flag and k_apply's record
+__device__ __forceinline__ void lp2_put(const LP2Args &A, int32_t v, uint32_t p, uint32_t t,
+                                        bool m) {
+  A.moved[v] = m ? 1 : 0;
+  A.pn[v] = make_int2((int32_t)p, m ? (int32_t)t : -1);
+}
+
 template <int G, int V>
 __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) {
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
       [&](int32_t v, bool &act) {
-        const Lp2V x{A.gain[v], (uint32_t)A.part[v], (uint32_t)A.target[v]};
-        act = x.gv != kNotInX;
-        return x;
+        const LpRec r = A.rec[v];
+        act = r.g != kNotInX;
+        return Lp2V{r.g, (uint32_t)r.p, (uint32_t)r.t};
       },
-      [&](int32_t u, int64_t e) { return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]}; },
+      [&](int32_t u, int64_t e) { return lp2_arc(A, u, e); },
       [&](int, bool ok, int32_t v, const Lp2V &vv, bool act, int, bool valid, const Lp2Arc &a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
         if (!act) {
-          if (lane == 0) A.moved[v] = 0;
+          if (lane == 0) lp2_put(A, v, vv.p, vv.t, false);
           return;
         }
         int64_t x = 0;
@@ -940,7 +956,7 @@ __device__ __forceinline__ void lp2_group(const LP2Args &A, int cls, int local) 
           x = (int64_t)a.w * (dist(A.h, vv.p, pu) - dist(A.h, vv.t, pu));
         }
         x = gsum64<G>(x);
-        if (lane == 0) A.moved[v] = x >= 0 ? 1 : 0;
+        if (lane == 0) lp2_put(A, v, vv.p, vv.t, x >= 0);
       });
 }
 
@@ -953,6 +969,8 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
     const int local = blk - A.cl.wg[cls];
     switch (cls) {
       case CLS_ISO:
+        // (an isolated vertex is nobody's neighbour and never moves: its
+        // record is never read)
         iso_tiles<V>(A.cl, local, [&](int32_t v) { A.moved[v] = 0; });
         break;
       case CLS_G8: lp2_group<8, V>(A, cls, local); break;
@@ -962,65 +980,59 @@ __global__ __launch_bounds__(kThreads) void k_lp_phase2(LP2Args A) {
       case CLS_W: {
         int32_t v;
         if (!w_vertex(A.cl, local, v)) break;
-        const int64_t gv = A.gain[v];
+        const LpRec r = A.rec[v];
+        const int64_t gv = r.g;
+        const uint32_t p = (uint32_t)r.p, t = (uint32_t)r.t;
         if (gv == kNotInX) {
-          if ((threadIdx.x & 63) == 0) A.moved[v] = 0;
+          if ((threadIdx.x & 63) == 0) lp2_put(A, v, p, t, false);
           break;
         }
-        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
         int64_t x = 0;
         wave_arcs<2>(
-            A.g.xadj[v], A.g.xadj[v + 1],
-            [&](int64_t e) {
-              const int32_t u = A.g.adj[e];
-              return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]};
-            },
+            A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return lp2_arc(A, A.g.adj[e], e); },
             [&](int64_t, const Lp2Arc &a) {
               uint32_t pu = (uint32_t)a.pu;
               if (a.gu != kNotInX && (a.gu > gv || (a.gu == gv && a.u < v))) pu = (uint32_t)a.tu;
               x += (int64_t)a.w * (dist(A.h, p, pu) - dist(A.h, t, pu));
             });
         x = gsum64<64>(x);
-        if ((threadIdx.x & 63) == 0) A.moved[v] = x >= 0 ? 1 : 0;
+        if ((threadIdx.x & 63) == 0) lp2_put(A, v, p, t, x >= 0);
         break;
       }
       default: {
         const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-        const int64_t gv = A.gain[v];
+        const LpRec r = A.rec[v];
+        const int64_t gv = r.g;
+        const uint32_t p = (uint32_t)r.p, t = (uint32_t)r.t;
         if (gv == kNotInX) {
-          if (threadIdx.x == 0) A.moved[v] = 0;
+          if (threadIdx.x == 0) lp2_put(A, v, p, t, false);
           break;
         }
-        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
         int64_t x = 0;
         big_arcs(
-            A.g.xadj[v], A.g.xadj[v + 1],
-            [&](int64_t e) {
-              const int32_t u = A.g.adj[e];
-              return Lp2Arc{u, A.g.w[e], A.part[u], A.target[u], A.gain[u]};
-            },
+            A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return lp2_arc(A, A.g.adj[e], e); },
             [&](int64_t, const Lp2Arc &a) {
               uint32_t pu = (uint32_t)a.pu;
               if (a.gu != kNotInX && (a.gu > gv || (a.gu == gv && a.u < v))) pu = (uint32_t)a.tu;
               x += (int64_t)a.w * (dist(A.h, p, pu) - dist(A.h, t, pu));
             });
         x = block_sum64(x, sc);
-        if (threadIdx.x == 0) A.moved[v] = x >= 0 ? 1 : 0;
+        if (threadIdx.x == 0) lp2_put(A, v, p, t, x >= 0);
         break;
       }
     }
   }
 }
 
-void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const int32_t *part,
-               const int32_t *target, const int64_t *gain, uint8_t *moved, hipStream_t s) {
+void lp_phase2(const DGraph &g, const Classes &cl, const Hier &h, const LpRec *rec,
+               uint8_t *moved, int2 *pn, hipStream_t s) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  LP2Args A{g, tc, h, part, target, gain, moved};
+  LP2Args A{g, tc, h, rec, moved, pn};
   auto kern = V == 2 ? k_lp_phase2<2> : k_lp_phase2<1>;
-  if (tl_timer) count_units(cl, g.xadj, CU_IN_X, CountArgs{nullptr, nullptr, gain, nullptr,
+  if (tl_timer) count_units(cl, g.xadj, CU_IN_X, CountArgs{nullptr, nullptr, rec, nullptr,
                                                            nullptr, nullptr},
                             tl_timer->counters(KT_LP2), s);
   hipEvent_t a = nullptr, b = nullptr;
@@ -1047,14 +1059,13 @@ struct ApplyArgs {
   DGraph g;
   Classes cl;
   Hier h;
-  const int32_t *part;
-  const int32_t *target;
   const uint8_t *moved;
   uint8_t *lock;
   int64_t *wst;  // weight-delta stripes [nstripes][ncodes]
   int32_t nstripes;
   int64_t *dj;
   uint8_t *dirty;  // label-propagation result caching (nullptr: off)
+  const int2 *pn;  // per vertex {block, moved ? target : -1} (k_pack_moves)
 };
 
 // Block-weight deltas of one mover (+c to its target, -c to its block): added
@@ -1076,10 +1087,12 @@ struct ApV {
 };
 
 // One arc of a mover (u its other end): weight, u's block, target and moved
-// flag.  With result caching u is marked here, where it is known.
+// flag, from one 8-byte gather of u's packed record.  With result caching u
+// is marked here, where it is known.
 __device__ __forceinline__ int4 ap_arc(const ApplyArgs &A, int32_t u, int64_t e) {
   if (A.dirty) A.dirty[u] = 1;
-  return make_int4(A.g.w[e], A.part[u], A.target[u], (int32_t)A.moved[u]);
+  const int2 q = A.pn[u];
+  return make_int4(A.g.w[e], q.x, q.y, q.y >= 0 ? 1 : 0);
 }
 __device__ __forceinline__ int4 ap_arc(const ApplyArgs &A, int64_t e) {
   return ap_arc(A, A.g.adj[e], e);
@@ -1109,8 +1122,9 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
       [&](int32_t v, bool &act) {
-        act = A.moved[v] != 0;
-        return ApV{(uint32_t)A.part[v], (uint32_t)A.target[v]};
+        const int2 q = A.pn[v];
+        act = q.y >= 0;
+        return ApV{(uint32_t)q.x, (uint32_t)q.y};
       },
       [&](int32_t u, int64_t e) { return ap_arc(A, u, e); },
       [&](int r, bool ok, int32_t v, const ApV &vv, bool act, int, bool valid, const int4 &a) {
@@ -1124,6 +1138,16 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
 #pragma unroll
   for (int r = 0; r < V; ++r) wmove_flush(A, mv[r]);
   return x;
+}
+
+// The record k_apply gathers for every neighbour of a mover: block and, for
+// a moved vertex, its target (else -1), so that an arc costs one gather
+// instead of three (block, target, moved flag).
+__global__ __launch_bounds__(kThreads) void k_pack_moves(int64_t n, const int32_t *part,
+                                                         const int32_t *target,
+                                                         const uint8_t *moved, int2 *pn) {
+  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (v < n) pn[v] = make_int2(part[v], moved[v] ? target[v] : -1);
 }
 
 // One class tile per workgroup; no LDS and no workgroup barrier, so that a
@@ -1145,7 +1169,10 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
           const int32_t v = A.cl.list[A.cl.off[CLS_ISO] + idx];
           const uint8_t m = A.moved[v];
           if (A.lock) A.lock[v] = m;
-          if (m) ap_mover(A, v, (uint32_t)A.part[v], (uint32_t)A.target[v], mv[r]);
+          if (m) {
+            const int2 q = A.pn[v];
+            ap_mover(A, v, (uint32_t)q.x, (uint32_t)q.y, mv[r]);
+          }
         }
       }
 #pragma unroll
@@ -1160,10 +1187,11 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
       int32_t v;
       WMove mv;
       if (w_vertex(A.cl, local, v)) {
-        const uint8_t m = A.moved[v];
-        if (A.lock && (threadIdx.x & 63) == 0) A.lock[v] = m;
+        const int2 q = A.pn[v];
+        const bool m = q.y >= 0;
+        if (A.lock && (threadIdx.x & 63) == 0) A.lock[v] = m ? 1 : 0;
         if (m) {
-          const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+          const uint32_t p = (uint32_t)q.x, t = (uint32_t)q.y;
           if ((threadIdx.x & 63) == 0) ap_mover(A, v, p, t, mv);
           wave_arcs<4>(
               A.g.xadj[v], A.g.xadj[v + 1], [&](int64_t e) { return ap_arc(A, e); },
@@ -1175,10 +1203,11 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
     }
     default: {
       const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
-      const uint8_t m = A.moved[v];
-      if (A.lock && threadIdx.x == 0) A.lock[v] = m;
+      const int2 q = A.pn[v];
+      const bool m = q.y >= 0;
+      if (A.lock && threadIdx.x == 0) A.lock[v] = m ? 1 : 0;
       if (m) {
-        const uint32_t p = (uint32_t)A.part[v], t = (uint32_t)A.target[v];
+        const uint32_t p = (uint32_t)q.x, t = (uint32_t)q.y;
         WMove mv;
         if (threadIdx.x == 0) ap_mover(A, v, p, t, mv);
         wmove_flush(A, mv);
@@ -1197,13 +1226,13 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
 // weight-delta stripes into w (all written by the previous launch) and, with
 // has_end, runs the StepEnd epilogue: nothing it reads is written by the
 // other workgroups of this launch, so no cross-workgroup ordering is needed.
-__global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part,
-                                                     const int32_t *target, const uint8_t *moved,
+__global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part, const int2 *pn,
+                                                     const uint8_t *moved,
                                                      int32_t nstripes, int64_t *wst, int has_end,
                                                      StepEnd E) {
   extern __shared__ int64_t wl[];
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && moved[v]) part[v] = target[v];
+  if (v < n && moved[v]) part[v] = pn[v].y;
   if (blockIdx.x == 0) {
     step_epilogue(E, wst, nstripes, wl, has_end != 0);
     if (has_end && E.body_ctr && threadIdx.x == 0) *E.body_ctr += 1;
@@ -1230,14 +1259,19 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, hipStream_t s,
-                 uint8_t *dirty) {
+                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, int2 *pn,
+                 hipStream_t s, uint8_t *dirty) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   const int nstripes = weight_stripes(h, g.n);
-  ApplyArgs A{g, tc, h, part, target, moved, lock, wst, nstripes, dj_stripes, dirty};
+  ApplyArgs A{g, tc, h, moved, lock, wst, nstripes, dj_stripes, dirty, pn};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
+  if (target && g.n > 0) {
+    hipLaunchKernelGGL(k_pack_moves, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
+                       moved, pn);
+    PM_LAUNCH_CHECK();
+  }
   if (nwg > 0) {
     hipEvent_t ta = nullptr, tb = nullptr;
     if (tl_timer) {
@@ -1255,7 +1289,7 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
   E.h = h;
   E.w = w;
   hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), sizeof(int64_t) << h.bits, s,
-                     g.n, part, target, moved, nstripes, wst, end ? 1 : 0, E);
+                     g.n, part, pn, moved, nstripes, wst, end ? 1 : 0, E);
   PM_LAUNCH_CHECK();
 }
 
