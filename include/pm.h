@@ -167,8 +167,8 @@ typedef struct pm_map_stats {
    *   [2] 16 per active arc (neighbour id, weight, and the neighbour's
    *       block and target-or-none) + 20 per mover (row offsets, block,
    *       target, weight)
-   *   [3] 16 per active arc (neighbour id, weight, its match, its weight)
-   *       + 12 per tiled vertex (match, preference, weight)
+   *   [3] 12 per active arc (neighbour id, weight, and its weight-or-
+   *       matched word) + 12 per tiled vertex (match, preference, weight)
    *   [4] 12 per active arc + 24 per source (row offsets, block, weight,
    *       key, destination) */
   int64_t kernel_launches[PM_TIMED_KERNELS];

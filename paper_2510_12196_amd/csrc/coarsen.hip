@@ -66,10 +66,12 @@ struct HemArgs {
   uint64_t hseed;
   const int32_t *match;
   int32_t *pref;
+  const int32_t *cm;  // per vertex: its weight while unmatched, -1 once matched
 };
 
+// one gather per arc: the neighbour's weight-or-matched word
 struct HemN {
-  int32_t u, mu, cu, w;
+  int32_t u, cmu, w;
 };
 
 // Whether v must (re)compute its preference this round.  Candidates only
@@ -95,7 +97,7 @@ __device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) 
   group_tiles<G, V>(
       A.g.xadj, A.g.adj, A.cl, cls, local,
       [&](int32_t v, bool &act) { return hem_vertex(A, v, act); },
-      [&](int32_t u, int64_t e) { return HemN{u, A.match[u], A.g.c[u], A.g.w[e]}; },
+      [&](int32_t u, int64_t e) { return HemN{u, A.cm[u], A.g.w[e]}; },
       [&](int, bool ok, int32_t v, const HemV &hv, bool act, int, bool valid, const HemN &a) {
         if (!ok) return;
         const int lane = threadIdx.x % G;
@@ -105,9 +107,9 @@ __device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) 
           return;
         }
         Cand c{-1, 0, 1, 0};
-        if (valid && a.mu < 0 && (int64_t)a.cu + cv <= A.lmax) {
+        if (valid && a.cmu >= 0 && (int64_t)a.cmu + cv <= A.lmax) {
           const uint32_t lo = (uint32_t)(a.u < v ? a.u : v), hi = (uint32_t)(a.u < v ? v : a.u);
-          c = Cand{a.u, a.w, a.cu, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+          c = Cand{a.u, a.w, a.cmu, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
         }
         cand_reduce<G>(c, v);
         if (lane == 0) A.pref[v] = c.u;
@@ -148,12 +150,12 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
             A.g.xadj[v], A.g.xadj[v + 1],
             [&](int64_t e) {
               const int32_t u = A.g.adj[e];
-              return make_int4(u, A.match[u], A.g.c[u], A.g.w[e]);
+              return make_int3(u, A.cm[u], A.g.w[e]);
             },
-            [&](int64_t, int4 a) {
-              if (a.y >= 0 || (int64_t)a.z + cv > A.lmax) return;
+            [&](int64_t, int3 a) {
+              if (a.y < 0 || (int64_t)a.y + cv > A.lmax) return;
               const uint32_t lo = (uint32_t)(a.x < v ? a.x : v), hi = (uint32_t)(a.x < v ? v : a.x);
-              const Cand c{a.x, a.w, a.z, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+              const Cand c{a.x, a.z, a.y, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
               if (cand_better(c, best, v)) best = c;
             });
         cand_reduce<64>(best, v);
@@ -174,12 +176,12 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
             A.g.xadj[v], A.g.xadj[v + 1],
             [&](int64_t e) {
               const int32_t u = A.g.adj[e];
-              return make_int4(u, A.match[u], A.g.c[u], A.g.w[e]);
+              return make_int3(u, A.cm[u], A.g.w[e]);
             },
-            [&](int64_t, int4 a) {
-              if (a.y >= 0 || (int64_t)a.z + cv > A.lmax) return;
+            [&](int64_t, int3 a) {
+              if (a.y < 0 || (int64_t)a.y + cv > A.lmax) return;
               const uint32_t lo = (uint32_t)(a.x < v ? a.x : v), hi = (uint32_t)(a.x < v ? v : a.x);
-              const Cand c{a.x, a.w, a.z, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
+              const Cand c{a.x, a.z, a.y, mix_hash(A.hseed, ((uint64_t)lo << 32) | hi)};
               if (cand_better(c, best, v)) best = c;
             });
         cand_reduce<64>(best, v);
@@ -200,12 +202,12 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
 }
 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
-                const int32_t *match, int32_t *pref, hipStream_t s) {
+                const int32_t *match, int32_t *pref, const int32_t *cm, hipStream_t s) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  HemArgs A{g, tc, lmax, hseed, match, pref};
+  HemArgs A{g, tc, lmax, hseed, match, pref, cm};
   auto kern = V == 2 ? k_hem_prefer<2> : k_hem_prefer<1>;
   if (tl_timer) count_units(cl, g.xadj, CU_HEM_ACTIVE, CountArgs{nullptr, nullptr, nullptr, nullptr, match,
                                                                  pref},
@@ -285,8 +287,9 @@ void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
 // needed, and no address sees more than 64 atomics.
 constexpr int kHemLeaves = 64;
 __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
-                                                         int32_t *match, uint64_t *counter,
-                                                         Status *st, int32_t *count_out) {
+                                                         int32_t *match, int32_t *cm,
+                                                         uint64_t *counter, Status *st,
+                                                         int32_t *count_out) {
   __shared__ BlockScratch sc;
   int64_t hits = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
     const int32_t u = pref[v];
     if (u >= 0 && pref[u] == (int32_t)v) {
       match[v] = u;
+      cm[v] = -1;
       ++hits;
     }
   }
@@ -318,11 +322,11 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
   if (count_out) *count_out = (int32_t)(r & 0xFFFFFFFFull);
 }
 
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, uint64_t *counter, Status *st,
-                int32_t *count_out, hipStream_t s) {
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int32_t *cm, uint64_t *counter,
+                Status *st, int32_t *count_out, hipStream_t s) {
   unsigned g = grid_for(n > 0 ? n : 1);
   if (g > kMaxGrid) g = kMaxGrid;
-  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, counter, st,
+  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, cm, counter, st,
                      count_out);
   PM_LAUNCH_CHECK();
 }
