@@ -251,7 +251,8 @@ def main():
                          "total_ms": round(kms[j], 3), "avg_us": round(kms[j] * 1e3 / kl[j], 3),
                          "bytes_per_launch": round(kbytes[j] / kl[j], 1),
                          "units_per_launch": [round(x / kl[j], 1) for x in kunits[j]],
-                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                         "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": read_traffic(KERNEL_NAMES[name], w.name)}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     kd = kernels[dom]
     rb = sum(kbytes[j] for j, n in enumerate(pm.TIMED_KERNELS) if n in REFINEMENT)
