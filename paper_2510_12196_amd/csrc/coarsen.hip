@@ -40,23 +40,18 @@ __device__ __forceinline__ bool cand_better(const Cand &a, const Cand &b, int32_
   return ahi < bhi;
 }
 
-template <int G>
-__device__ __forceinline__ Cand cand_xor(const Cand &c, int m) {
-  Cand o;
-  o.u = __shfl_xor(c.u, m, G);
-  o.w = __shfl_xor(c.w, m, G);
-  o.cu = __shfl_xor(c.cu, m, G);
-  o.h = (uint64_t)gxor64<G>((int64_t)c.h, m);
-  return o;
-}
-
+// The best candidate of the group (a total order, so the pairing of the
+// reduction steps does not matter); every lane gets it.
 template <int G>
 __device__ __forceinline__ void cand_reduce(Cand &c, int32_t v) {
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) {
-    const Cand o = cand_xor<G>(c, m);
+  xsteps<G>([&](auto st) {
+    Cand o;
+    o.u = st(c.u);
+    o.w = st(c.w);
+    o.cu = st(c.cu);
+    o.h = st(c.h);
     if (cand_better(o, c, v)) c = o;
-  }
+  });
 }
 
 struct HemArgs {

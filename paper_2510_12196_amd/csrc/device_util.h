@@ -22,30 +22,71 @@ __device__ __forceinline__ int64_t gxor64(int64_t x, int m) {
   int32_t hi = __shfl_xor((int32_t)((uint64_t)x >> 32), m, G);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
+// Step K (1, 2, 4, ..., 32) of a group reduction: the value held by the other
+// half of this lane's aligned 2K-lane block.  The steps run in increasing K,
+// so every lane of a K-block already holds the same value and any pairing of
+// the two halves works: DPP quad permutations for K = 1, 2 and the row
+// mirrors for K = 4, 8 (VALU operand modifiers, no LDS round trip), a
+// swizzle (xor 16 within 32 lanes) for K = 16, two lane reads for K = 32.
+// Only lanes of the same group are read, so groups may differ in activity.
+template <int K>
+__device__ __forceinline__ int32_t xstep32(int32_t x) {
+  if constexpr (K == 1) return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+  else if constexpr (K == 2) return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+  else if constexpr (K == 4) return __builtin_amdgcn_update_dpp(0, x, 0x141, 0xF, 0xF, false);
+  else if constexpr (K == 8) return __builtin_amdgcn_update_dpp(0, x, 0x140, 0xF, 0xF, false);
+  else if constexpr (K == 16) return __builtin_amdgcn_ds_swizzle(x, 0x401F);
+  else {
+    static_assert(K == 32, "reduction step");
+    const int32_t a = __builtin_amdgcn_readlane(x, 0), b = __builtin_amdgcn_readlane(x, 32);
+    return (threadIdx.x & 32) ? a : b;
+  }
+}
+template <int K>
+__device__ __forceinline__ int64_t xstep64(int64_t x) {
+  const int32_t lo = xstep32<K>((int32_t)(uint32_t)(uint64_t)x);
+  const int32_t hi = xstep32<K>((int32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int K> __device__ __forceinline__ int32_t xstep_any(int32_t x) { return xstep32<K>(x); }
+template <int K> __device__ __forceinline__ uint32_t xstep_any(uint32_t x) {
+  return (uint32_t)xstep32<K>((int32_t)x);
+}
+template <int K> __device__ __forceinline__ int64_t xstep_any(int64_t x) { return xstep64<K>(x); }
+template <int K> __device__ __forceinline__ uint64_t xstep_any(uint64_t x) {
+  return (uint64_t)xstep64<K>((int64_t)x);
+}
+// Runs f(step) for the steps of a G-lane group reduction, K = 1 upwards.
+template <int G, class F>
+__device__ __forceinline__ void xsteps(F f) {
+  if constexpr (G >= 2) f([](auto x) { return xstep_any<1>(x); });
+  if constexpr (G >= 4) f([](auto x) { return xstep_any<2>(x); });
+  if constexpr (G >= 8) f([](auto x) { return xstep_any<4>(x); });
+  if constexpr (G >= 16) f([](auto x) { return xstep_any<8>(x); });
+  if constexpr (G >= 32) f([](auto x) { return xstep_any<16>(x); });
+  if constexpr (G >= 64) f([](auto x) { return xstep_any<32>(x); });
+}
 template <int G>
 __device__ __forceinline__ int64_t gsum64(int64_t x) {
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) x += gxor64<G>(x, m);
+  xsteps<G>([&](auto st) { x += st(x); });
   return x;
 }
 template <int G>
 __device__ __forceinline__ int32_t gor(int32_t x) {
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) x |= __shfl_xor(x, m, G);
+  xsteps<G>([&](auto st) { x |= st(x); });
   return x;
 }
 // (value desc, key asc) argmax over the group; every lane gets the result.
 template <int G>
 __device__ __forceinline__ void gargmax(int64_t &val, uint32_t &key) {
-#pragma unroll
-  for (int m = G / 2; m > 0; m >>= 1) {
-    int64_t ov = gxor64<G>(val, m);
-    uint32_t ok = (uint32_t)__shfl_xor((int32_t)key, m, G);
+  xsteps<G>([&](auto st) {
+    const int64_t ov = st(val);
+    const uint32_t ok = st(key);
     if (ov > val || (ov == val && ok < key)) {
       val = ov;
       key = ok;
     }
-  }
+  });
 }
 
 // ---- whole workgroup (kThreads = 256, four waves) --------------------------
