@@ -65,7 +65,8 @@ int64_t footprint(const pm_graph *g, const pm_hierarchy *h) {
   const int64_t codes = int64_t(1) << (bits < kMaxCodeBits ? bits : kMaxCodeBits);
   // coarse levels (at most the input again), sort buffers, refinement state,
   // rebalancing tables; the arena hands out at least one 64 MiB chunk
-  const int64_t est = 72 * g->nnz + 128 * (int64_t)g->n + codes * 64 * 8 * 9 + (int64_t(8) << 20);
+  const int64_t est = 72 * g->nnz + 128 * (int64_t)g->n +
+                      codes * kBuckets * 8 * (kBucketStripes + 1) + (int64_t(8) << 20);
   const int64_t chunk = int64_t(64) << 20;
   return est > chunk ? est : chunk;
 }

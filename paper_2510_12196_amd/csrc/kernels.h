@@ -199,6 +199,11 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
                  uint8_t *dirty = nullptr);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
+// Rebalancing loss buckets per block, and the stripes of the bucket-weight
+// and accepted-weight accumulators (a stripe per workgroup index modulo the
+// count: their atomics are bound by contention on hot counters).
+constexpr int kBuckets = 64;
+constexpr int kBucketStripes = 32;
 struct RebalanceBuffers {
   int32_t *key;        // n: (block << 6 | bucket) for sources, -1 otherwise
   int32_t *dest;       // n: chosen destination
@@ -208,8 +213,8 @@ struct RebalanceBuffers {
   int64_t *resid;      // 2^bits: residual capacity per code
   int32_t *elig_weak;  // 2^bits: blocks within sigma, ascending
   int32_t *elig_strong;// 2^bits: blocks within L_max, ascending
-  int64_t *bw;         // 8 x 2^bits x 64 bucket weights (kept zero between rounds)
-  int64_t *acc;        // 8 x 2^bits accepted weights (kept zero between rounds)
+  int64_t *bw;         // 32 x 2^bits x 64 bucket weights (kept zero between rounds)
+  int64_t *acc;        // 32 x 2^bits accepted weights (kept zero between rounds)
   int32_t *crit;       // 2^bits
   int64_t *need;       // 2^bits
   int32_t *tcrit;      // 2^bits

@@ -1239,13 +1239,13 @@ __global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part, c
   }
 }
 
-// Weight-delta stripes: at most kWeightStripes, and at most 8192 words in all
+// Weight-delta stripes: at most kWeightStripes, and at most 16384 words in all
 // so that one workgroup folds them quickly.
 int weight_stripes(const Hier &h, int64_t n) {
   // one stripe per 2048 vertices (the adds of a small graph's few
   // workgroups hardly collide, and the step epilogue folds every stripe)
   int sc = kWeightStripes;
-  while (sc > 1 && ((int64_t)sc << h.bits) > 8192) sc >>= 1;
+  while (sc > 1 && ((int64_t)sc << h.bits) > 16384) sc >>= 1;
   while (sc > 1 && (int64_t)sc * 2048 > n) sc >>= 1;
   return sc;
 }
@@ -1313,8 +1313,6 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
 // into per-tile sums (tiles of consecutive ids), a critical tile per key,
 // and an in-tile scan.  Every size stays on the device.
 // ===========================================================================
-constexpr int kBuckets = 64;
-constexpr int kBucketStripes = 8;
 
 struct RebArgs {
   DGraph g;
@@ -1710,11 +1708,18 @@ __global__ __launch_bounds__(kThreads) void k_kp_crit(KPArgs A) {
   } else {
     budget = A.lmax - A.w[K] + 1;
   }
+  // eight stripes' loads in flight before their clears (a clear may not
+  // pass a load of another stripe the compiler cannot tell apart)
   int64_t x = 0;
-  for (int s = 0; s < kBucketStripes; ++s) {
-    int64_t *p = &A.bw[((size_t)s * A.ncodes + K) * kBuckets + lane];
-    x += *p;
-    *p = 0;
+  for (int s0 = 0; s0 < kBucketStripes; s0 += 8) {
+    int64_t sv[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) sv[s] = A.bw[((size_t)(s0 + s) * A.ncodes + K) * kBuckets + lane];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      x += sv[s];
+      A.bw[((size_t)(s0 + s) * A.ncodes + K) * kBuckets + lane] = 0;
+    }
   }
   // inclusive scan over the 64 buckets
   int64_t incl = x;
@@ -2020,9 +2025,15 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place_rejects(
   const int hi = lo + per < ncodes ? lo + per : ncodes;
   for (int c = lo; c < hi; ++c) {
     int64_t a = 0;
-    for (int s = 0; s < kBucketStripes; ++s) {
-      a += acc[(size_t)s * ncodes + c];
-      acc[(size_t)s * ncodes + c] = 0;
+    for (int s0 = 0; s0 < kBucketStripes; s0 += 8) {
+      int64_t sv[8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) sv[s] = acc[(size_t)(s0 + s) * ncodes + c];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        a += sv[s];
+        acc[(size_t)(s0 + s) * ncodes + c] = 0;
+      }
     }
     resid[c] = code_valid(h, (uint32_t)c) ? lmax - w[c] - a : 0;
     got[c] = 0;
