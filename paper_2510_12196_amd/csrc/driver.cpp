@@ -255,8 +255,11 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
     if (!bg.x) {
       PM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       try {
+        // the commit publishes; its sequence number comes from the device
+        // counter (the host's count advances per launch, below)
+        E.pub = Pub{cx.mirror_dev, cx.seq_dev, 0, cx.seq_ctr};
         body();
-        publish_status(cx.dev, cx.mirror_dev, cx.seq_dev, 0, s, cx.seq_ctr);
+        E.pub = Pub{};
       } catch (...) {
         hipGraph_t dead = nullptr;
         (void)hipStreamEndCapture(s, &dead);
@@ -285,8 +288,9 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       if (use_graphs) {
         pub = replay(bgs[0], body);
       } else {
+        E.pub = pub = cx.next_pub();  // published by the commit's step end
         body();
-        pub = cx.publish();
+        E.pub = Pub{};
       }
       iw = 0;
       ++R.st.lp_iterations;
@@ -313,10 +317,11 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
           apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
         });
       } else {
+        E.pub = pub = cx.next_pub();  // published by the commit's step end
         rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, rtarget, moved,
                         rb, cx.dev, s, var);
         apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
-        pub = cx.publish();
+        E.pub = Pub{};
       }
       if (strong) {
         iw = 0;

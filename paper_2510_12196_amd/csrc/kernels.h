@@ -49,6 +49,7 @@ struct StepEnd {
   int32_t *elig_strong;  // blocks with w <= L_max, ascending
   Status *st;
   int64_t *body_ctr = nullptr;  // loop bodies done (incremented by each step end)
+  Pub pub{};  // publication of the status at the end (host == nullptr: none)
 };
 // StepEnd alone, as one workgroup (the start of a level).
 void step_status(const StepEnd &E, hipStream_t s);

@@ -512,6 +512,8 @@ __device__ __forceinline__ void step_epilogue(const StepEnd &E, int64_t *wst, in
       E.st->dj = S.dj;
       E.st->n_elig_weak = S.n_elig_weak;
       E.st->n_elig_strong = S.n_elig_strong;
+      // the step's publication, without a launch of its own
+      if (E.pub.host) publish_dev(E.st, E.pub);
     }
   }
   if (wst) {
