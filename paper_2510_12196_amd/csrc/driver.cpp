@@ -283,7 +283,7 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       auto body = [&] {
         lp_phase1(g, cl, h, cur, lock, rec, s, var, dirty);
         lp_phase2(g, cl, h, rec, moved, pn, s);
-        apply_moves(g, cl, h, cur, nullptr, moved, lock, w, wst, cx.sp.a, &E, pn, s, dirty);
+        apply_moves(g, cl, h, cur, moved, lock, w, wst, cx.sp.a, &E, pn, s, dirty);
       };
       if (use_graphs) {
         pub = replay(bgs[0], body);
@@ -313,14 +313,14 @@ static RefineResult refine_level(Ctx &cx, const DGraph &g, const Classes &cl, co
       if (use_graphs && !strong) {
         pub = replay(bgs[1], [&] {
           rebalance_round(ar, g, rcl, h, false, lmax, sigma, total, reb_seed, cur, w, rtarget,
-                          moved, rb, cx.dev, s, var, body_ctr);
-          apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
+                          moved, pn, rb, cx.dev, s, var, body_ctr);
+          apply_moves(g, rcl, h, cur, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
         });
       } else {
         E.pub = pub = cx.next_pub();  // published by the commit's step end
         rebalance_round(ar, g, rcl, h, strong, lmax, sigma, total, hseed, cur, w, rtarget, moved,
-                        rb, cx.dev, s, var);
-        apply_moves(g, rcl, h, cur, rtarget, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
+                        pn, rb, cx.dev, s, var);
+        apply_moves(g, rcl, h, cur, moved, nullptr, w, wst, cx.sp.a, &E, pn, s, dirty);
         E.pub = Pub{};
       }
       if (strong) {
@@ -740,8 +740,8 @@ int pm_lp_round_ex(const pm_graph *g, const pm_hierarchy *h, int32_t *part, uint
     lp_phase1(dg, cl, hh, codes, lock, rec, s, var);
     unpack_lp(rec, target_out, gain_out, dg.n, s);
     lp_phase2(dg, cl, hh, rec, moved_out, pn, s);
-    apply_moves(dg, cl, hh, codes, nullptr, moved_out, lock, w,
-                alloc_weight_stripes(*lease, hh, s), cx.sp.a, nullptr, pn, s);
+    apply_moves(dg, cl, hh, codes, moved_out, lock, w, alloc_weight_stripes(*lease, hh, s),
+                cx.sp.a, nullptr, pn, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     codes_to_ids(hh, target_out, target_out, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
@@ -785,10 +785,11 @@ int pm_rebalance_ex(const pm_graph *g, const pm_hierarchy *h, int32_t strong, in
     step_status(StepEnd{hh, w, nullptr, sigma, lmax, rb.elig_weak, rb.elig_strong, cx.dev}, s);
     const uint64_t hseed =
         mix_hash(mix_hash(seed ^ kTagRebalance, (uint64_t)(int64_t)level), (uint64_t)(int64_t)iter);
+    int2 *pn = ar.alloc_n<int2>(n);
     rebalance_round(ar, dg, cl, hh, strong != 0, lmax, sigma, total, hseed, codes, w, target,
-                    moved_out, rb, cx.dev, s, var);
-    apply_moves(dg, cl, hh, codes, target, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s),
-                cx.sp.a, nullptr, ar.alloc_n<int2>(dg.n), s);
+                    moved_out, pn, rb, cx.dev, s, var);
+    apply_moves(dg, cl, hh, codes, moved_out, nullptr, w, alloc_weight_stripes(ar, hh, s), cx.sp.a,
+                nullptr, pn, s);
     codes_to_ids(hh, codes, part, dg.n, s);
     PM_HIP(hipStreamSynchronize(s));
     return PM_OK;

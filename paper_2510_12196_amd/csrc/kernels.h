@@ -192,11 +192,11 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 // dirty != nullptr: marks every mover and every neighbour of a mover (the
 // result caching of label propagation)
 // pn: g.n records {block, moved ? target : -1} gathered for the neighbours of
-// movers; with target != nullptr they are first written from (part, target,
-// moved), with target == nullptr they are phase 2's.
+// movers (written by label propagation's phase 2, or by the rebalancing
+// round); the commit takes the targets from them.
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
-                 const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, int2 *pn, hipStream_t s,
+                 const uint8_t *moved, uint8_t *lock, int64_t *w, int64_t *wst,
+                 int64_t *dj_stripes, const StepEnd *end, const int2 *pn, hipStream_t s,
                  uint8_t *dirty = nullptr);
 
 // ---- rebalancing (Algorithm 5) --------------------------------------------
@@ -228,7 +228,7 @@ struct RebalanceBuffers {
 };
 RebalanceBuffers alloc_rebalance(Arena &ar, int64_t n, const Hier &h, hipStream_t s);
 // One weak/strong rebalancing round: writes moved/target for every vertex,
-// ready for apply_moves.  The eligible destinations (rb.elig_*, counts in
+// and pn (apply's records), ready for apply_moves.  The eligible destinations (rb.elig_*, counts in
 // *st_dev) must be those of the current weights (StepEnd / step_status).  No
 // host synchronisation.
 // Rebalancing sources on large levels: the vertices of blocks heavier than
@@ -242,7 +242,7 @@ void reb_sources(Arena &ar, const Classes &cl, int32_t n, const int32_t *part, c
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
-                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
+                     int2 *pn, const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
                      const Variants &var = Variants{}, const int64_t *body_ctr = nullptr);
 
 // ---- induced subgraphs (Section 4.1, Algorithm 1) ----------------------------

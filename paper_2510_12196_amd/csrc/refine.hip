@@ -1067,7 +1067,7 @@ struct ApplyArgs {
   int32_t nstripes;
   int64_t *dj;
   uint8_t *dirty;  // label-propagation result caching (nullptr: off)
-  const int2 *pn;  // per vertex {block, moved ? target : -1} (k_pack_moves)
+  const int2 *pn;  // per vertex {block, moved ? target : -1}
 };
 
 // Block-weight deltas of one mover (+c to its target, -c to its block): added
@@ -1140,16 +1140,6 @@ __device__ __forceinline__ int64_t apply_group(const ApplyArgs &A, int cls, int 
 #pragma unroll
   for (int r = 0; r < V; ++r) wmove_flush(A, mv[r]);
   return x;
-}
-
-// The record k_apply gathers for every neighbour of a mover: block and, for
-// a moved vertex, its target (else -1), so that an arc costs one gather
-// instead of three (block, target, moved flag).
-__global__ __launch_bounds__(kThreads) void k_pack_moves(int64_t n, const int32_t *part,
-                                                         const int32_t *target,
-                                                         const uint8_t *moved, int2 *pn) {
-  const int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (v < n) pn[v] = make_int2(part[v], moved[v] ? target[v] : -1);
 }
 
 // One class tile per workgroup; no LDS and no workgroup barrier, so that a
@@ -1260,20 +1250,15 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s) {
 }
 
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
-                 const int32_t *target, const uint8_t *moved, uint8_t *lock, int64_t *w,
-                 int64_t *wst, int64_t *dj_stripes, const StepEnd *end, int2 *pn,
-                 hipStream_t s, uint8_t *dirty) {
+                 const uint8_t *moved, uint8_t *lock, int64_t *w, int64_t *wst,
+                 int64_t *dj_stripes, const StepEnd *end, const int2 *pn, hipStream_t s,
+                 uint8_t *dirty) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   const int nstripes = weight_stripes(h, g.n);
   ApplyArgs A{g, tc, h, moved, lock, wst, nstripes, dj_stripes, dirty, pn};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
-  if (target && g.n > 0) {
-    hipLaunchKernelGGL(k_pack_moves, dim3(grid_for(g.n)), dim3(kThreads), 0, s, g.n, part, target,
-                       moved, pn);
-    PM_LAUNCH_CHECK();
-  }
   if (nwg > 0) {
     hipEvent_t ta = nullptr, tb = nullptr;
     if (tl_timer) {
@@ -1679,6 +1664,8 @@ struct KPArgs {
   uint8_t *moved;
   int32_t *target;
   uint8_t *reject;
+  const int32_t *part;
+  int2 *pn;           // apply's records {block, moved ? target : -1}
 };
 
 // element of the current pass?  (key K, bucket b)
@@ -1808,11 +1795,12 @@ __global__ __launch_bounds__(kThreads) void k_kp_tilecrit(KPArgs A) {
 // bucket weights of the destination, in an acceptance the accepted weight.
 __device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t K, int32_t b,
                                            bool pass, bool &has, uint32_t &akey, int64_t &aval) {
-  if (A.pass == KP_SELECT) {
+  if (A.pass == KP_SELECT) {  // (K is v's block)
     if (pass) {
       const int32_t d = A.dest[v];
       A.moved[v] = 1;
       A.target[v] = d;
+      A.pn[v] = make_int2((int32_t)K, d);
       if (A.strong) {
         has = true;
         akey = ((uint32_t)d << 6) | (uint32_t)b;
@@ -1820,6 +1808,7 @@ __device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t 
       }
     } else {
       A.moved[v] = 0;
+      A.pn[v] = make_int2((int32_t)K, -1);
     }
   } else {
     if (pass) {
@@ -1829,6 +1818,7 @@ __device__ __forceinline__ void kp_outcome(const KPArgs &A, int32_t v, uint32_t 
       aval = A.vwgt[v];
     } else {
       A.moved[v] = 0;
+      A.pn[v].y = -1;
       A.reject[v] = 1;
     }
   }
@@ -1862,7 +1852,10 @@ __device__ __forceinline__ void kp_decide(const KPArgs &A, int blk) {
     // non-element here; it must then be left alone.)
     if (A.pass == KP_SELECT) A.reject[v] = 0;
     if (!kp_element(A, (int32_t)v, K, b)) {
-      if (A.pass == KP_SELECT) A.moved[v] = 0;
+      if (A.pass == KP_SELECT) {
+        A.moved[v] = 0;
+        A.pn[v] = make_int2(A.part[v], -1);
+      }
     } else {
       const int32_t cb = A.crit[K];
       if (b != cb) {
@@ -2011,7 +2004,7 @@ __device__ __forceinline__ int64_t place_excl_scan64(int64_t x, int64_t *wsum, i
 __global__ __launch_bounds__(kPlaceThreads) void k_place_rejects(
     Hier h, const int64_t *w, int64_t *acc, int64_t lmax, const int32_t *list,
     const int32_t *count, const int32_t *vwgt, int32_t *rw, int64_t *gresid, int64_t *gstart,
-    int32_t *target, uint8_t *moved) {
+    int32_t *target, uint8_t *moved, int2 *pn) {
   extern __shared__ int64_t place_lds[];
   __shared__ uint32_t wsum[kPlaceThreads / 64];
   __shared__ int64_t wsum64[kPlaceThreads / 64];
@@ -2126,6 +2119,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_place_rejects(
           const int32_t v = list[i0 + i];
           target[v] = a;
           moved[v] = 1;
+          pn[v].y = a;
           atomicAdd(&got[a], cw[i]);
         }
         R += cw[i];
@@ -2213,7 +2207,7 @@ void reb_sources(Arena &ar, const Classes &cl, int32_t n, const int32_t *part, c
 void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &h, bool strong,
                      int64_t lmax, int64_t sigma, int64_t total, uint64_t hseed,
                      const int32_t *part, const int64_t *w, int32_t *target, uint8_t *moved,
-                     const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
+                     int2 *pn, const RebalanceBuffers &rb, Status *st_dev, hipStream_t s,
                      const Variants &var, const int64_t *body_ctr) {
   const int V = group_v();
   const bool whist = h.bits <= 10;  // as in lp_phase1
@@ -2274,6 +2268,8 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
   K.tneed = rb.tneed;
   K.moved = moved;
   K.target = target;
+  K.part = part;
+  K.pn = pn;
   K.reject = rb.reject;
   keyed_prefix(K, s);
   if (!strong) return;
@@ -2283,7 +2279,8 @@ void rebalance_round(Arena &ar, const DGraph &g, const Classes &cl, const Hier &
   select_indices(ar, rb.reject, rb.rlist, rb.rcount, n, s);
   const size_t plds = ncodes <= kPlaceLdsCodes ? (size_t)ncodes * 20 : (size_t)ncodes * 4;
   hipLaunchKernelGGL(k_place_rejects, dim3(1), dim3(kPlaceThreads), plds, s, h, w, rb.acc, lmax,
-                     rb.rlist, rb.rcount, g.c, rb.rweight, rb.resid, rb.rstart, target, moved);
+                     rb.rlist, rb.rcount, g.c, rb.rweight, rb.resid, rb.rstart, target, moved,
+                     pn);
   PM_LAUNCH_CHECK();
 }
 
