@@ -700,8 +700,8 @@ __device__ __forceinline__ void merge_row(const RowArgs &A, int cls, int local) 
   for (int k = 2; k <= G; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint32_t pk = (uint32_t)__shfl_xor((int32_t)key, j, G);
-      const int32_t pw = __shfl_xor(w, j, G);
+      const uint32_t pk = (uint32_t)xor_lane((int32_t)key, j);
+      const int32_t pw = xor_lane(w, j);
       const bool up = (lane & k) == 0, low = (lane & j) == 0;
       if (low == up ? pk < key : pk > key) {
         key = pk;
@@ -781,8 +781,8 @@ __device__ __forceinline__ void wave_merge_row(int32_t c, int64_t beg, int ub, u
 #pragma unroll
         for (int q = 0; q < E; ++q) {
           const int i = lane * E + q;
-          const uint32_t pk = (uint32_t)__shfl_xor((int32_t)k[q], j / E, 64);
-          const int32_t pw = __shfl_xor(w[q], j / E, 64);
+          const uint32_t pk = (uint32_t)xor_lane((int32_t)k[q], j / E);
+          const int32_t pw = xor_lane(w[q], j / E);
           const bool up = (i & kk) == 0, low = (i & j) == 0;
           if (low == up ? pk < k[q] : pk > k[q]) {
             k[q] = pk;

@@ -56,6 +56,20 @@ template <int K> __device__ __forceinline__ int64_t xstep_any(int64_t x) { retur
 template <int K> __device__ __forceinline__ uint64_t xstep_any(uint64_t x) {
   return (uint64_t)xstep64<K>((int64_t)x);
 }
+// The value of lane (lane xor m) for m = 1, 2 (DPP quad permutations), 4, 8,
+// 16 (swizzles within 32 lanes) or 32 (LDS permute): an exact exchange, for
+// sorting networks.  m must fold to a constant (unrolled loops).
+__device__ __forceinline__ int32_t xor_lane(int32_t x, int m) {
+  switch (m) {
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0xB1, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x4E, 0xF, 0xF, false);
+    case 4: return __builtin_amdgcn_ds_swizzle(x, 0x101F);
+    case 8: return __builtin_amdgcn_ds_swizzle(x, 0x201F);
+    case 16: return __builtin_amdgcn_ds_swizzle(x, 0x401F);
+    default: return __shfl_xor(x, m, 64);
+  }
+}
+
 // Runs f(step) for the steps of a G-lane group reduction, K = 1 upwards.
 template <int G, class F>
 __device__ __forceinline__ void xsteps(F f) {
