@@ -70,7 +70,9 @@ def read_traffic(kernel, workload):
 
 def summarize_pmc(d, kernel):
     """Reduce rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE, KiB per dispatch)
-    for `kernel` and the calibration copy kernel to bytes per launch."""
+    for `kernel` and the calibration copy kernel to bytes per launch; SQ_*
+    counters of `kernel` are reported per launch, with the wave-cycle shares
+    of waiting and of VALU and LDS issue."""
     import csv
     import glob
     import re
@@ -107,6 +109,17 @@ def summarize_pmc(d, kernel):
                   f"{res[ctr]:.0f} B")
     if len(res) == 2:
         print(f"hbm_bytes_per_launch: {res['FETCH_SIZE'] + res['WRITE_SIZE']:.0f}")
+    # shader-sequencer counters (summed over the SEs): where the waves' time goes
+    sq = {ctr: out[("k", ctr)] for (kind, ctr) in out if kind == "k" and ctr.startswith("SQ_")}
+    for ctr in sorted(sq):
+        tot, n = sq[ctr]
+        print(f"{ctr}: {tot / n:.4g} per launch over {n} launches")
+    if "SQ_WAVE_CYCLES" in sq and sq["SQ_WAVE_CYCLES"][0] > 0:
+        wc = sq["SQ_WAVE_CYCLES"][0]
+        for ctr in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+                    "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_MISC"):
+            if ctr in sq:
+                print(f"{ctr} / SQ_WAVE_CYCLES: {sq[ctr][0] / wc:.3f}")
     print(f"source_digest: {source_digest()}")
 
 
