@@ -62,6 +62,7 @@ struct HemArgs {
   const int32_t *match;
   int32_t *pref;
   const int32_t *cm;  // per vertex: its weight while unmatched, -1 once matched
+  const uint8_t *hact;  // per vertex: looks for a partner this round (written by the commit)
 };
 
 // one gather per arc: the neighbour's weight-or-matched word
@@ -72,8 +73,10 @@ struct HemN {
 // Whether v must (re)compute its preference this round.  Candidates only
 // leave (neighbours get matched, weights are fixed), so the best candidate
 // of the previous round stays the best while it is unmatched, and a vertex
-// without candidates keeps none: only a vertex whose preferred partner was
-// matched since, or that has none yet (kPrefUnknown), looks again.  A
+// without candidates keeps none: only an unmatched vertex whose preferred
+// partner was matched since, or that has none yet (kPrefUnknown), looks
+// again.  The commit of the previous round decides this (hact), so that a
+// tile does not wait for the match word of every preferred partner.  A
 // matched vertex gets -1 (its stale preference must not pair it again).
 constexpr int32_t kPrefUnknown = -2;
 struct HemV {
@@ -81,10 +84,8 @@ struct HemV {
   bool matched;
 };
 __device__ __forceinline__ HemV hem_vertex(const HemArgs &A, int32_t v, bool &act) {
-  const int32_t m = A.match[v];
-  const int32_t p = A.pref[v];
-  act = m < 0 && (p == kPrefUnknown || (p >= 0 && A.match[p] >= 0));
-  return HemV{A.g.c[v], m >= 0};
+  act = A.hact[v] != 0;
+  return HemV{A.g.c[v], A.match[v] >= 0};
 }
 
 template <int G, int V>
@@ -197,12 +198,13 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
 }
 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
-                const int32_t *match, int32_t *pref, const int32_t *cm, hipStream_t s) {
+                const int32_t *match, int32_t *pref, const int32_t *cm, const uint8_t *hact,
+                hipStream_t s) {
   const int V = group_v();
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   if (nwg == 0) return;
-  HemArgs A{g, tc, lmax, hseed, match, pref, cm};
+  HemArgs A{g, tc, lmax, hseed, match, pref, cm, hact};
   auto kern = V == 2 ? k_hem_prefer<2> : k_hem_prefer<1>;
   if (tl_timer) count_units(cl, g.xadj, CU_HEM_ACTIVE, CountArgs{nullptr, nullptr, nullptr, nullptr, match,
                                                                  pref},
@@ -224,14 +226,11 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
 // per position of the class list, a stable selection of the flagged
 // positions (class order kept), then the new class offsets and the list of
 // vertex ids.
-__global__ void k_hem_active_flags(int32_t n, const int32_t *list, const int32_t *match,
-                                   const int32_t *pref, uint8_t *flag) {
+__global__ void k_hem_active_flags(int32_t n, const int32_t *list, const uint8_t *hact,
+                                   uint8_t *flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int32_t v = list[i];
-  const int32_t m = match[v];
-  const int32_t p = pref[v];
-  flag[i] = m < 0 && (p == kPrefUnknown || (p >= 0 && match[p] >= 0)) ? 1 : 0;
+  flag[i] = hact[list[i]];
 }
 
 // off_out[c] = first compacted position of class c (classes by the offsets
@@ -259,14 +258,14 @@ void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int3
   PM_LAUNCH_CHECK();
 }
 
-void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
-                 const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s) {
+void hem_compact(Arena &ar, const Classes &cl, int32_t n, const uint8_t *hact,
+                 int32_t *list_out, int32_t *off_out, hipStream_t s) {
   uint8_t *flag = ar.alloc_n<uint8_t>((size_t)n + 1);
   int32_t *pos = ar.alloc_n<int32_t>((size_t)n + 1);
   int32_t *count = ar.alloc_n<int32_t>(1);
   if (n > 0) {
     hipLaunchKernelGGL(k_hem_active_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, n, cl.list,
-                       match, pref, flag);
+                       hact, flag);
     PM_LAUNCH_CHECK();
   }
   select_indices(ar, flag, pos, count, n, s);
@@ -281,21 +280,32 @@ void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
 // atomic that carries both the data and the completion, so no fence is
 // needed, and no address sees more than 64 atomics.
 constexpr int kHemLeaves = 64;
+// It also decides which unmatched vertices look again in the next round
+// (hact): those whose preferred partner u is matched after this commit,
+// that is, matched before (its match word; read while u's own thread may
+// write it, but then u is matched now and the second test holds too) or now
+// (u and its preferred partner prefer each other).
 __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_t *pref,
                                                          int32_t *match, int32_t *cm,
-                                                         uint64_t *counter, Status *st,
-                                                         int32_t *count_out) {
+                                                         uint8_t *hact, uint64_t *counter,
+                                                         Status *st, int32_t *count_out) {
   __shared__ BlockScratch sc;
   int64_t hits = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    if (match[v] >= 0) continue;
+    if (match[v] >= 0) continue;  // (its flag went to 0 when it was matched)
     const int32_t u = pref[v];
-    if (u >= 0 && pref[u] == (int32_t)v) {
+    const int32_t pu = u >= 0 ? pref[u] : -1;
+    if (u >= 0 && pu == (int32_t)v) {
       match[v] = u;
       cm[v] = -1;
+      hact[v] = 0;
       ++hits;
+      continue;
     }
+    bool again = u == kPrefUnknown;
+    if (u >= 0) again = match[u] >= 0 || (pu >= 0 && pref[pu] == u);
+    hact[v] = again ? 1 : 0;
   }
   hits = block_sum64(hits, sc);
   if (threadIdx.x != 0) return;
@@ -317,12 +327,12 @@ __global__ __launch_bounds__(kThreads) void k_hem_commit(int32_t n, const int32_
   if (count_out) *count_out = (int32_t)(r & 0xFFFFFFFFull);
 }
 
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int32_t *cm, uint64_t *counter,
-                Status *st, int32_t *count_out, hipStream_t s) {
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int32_t *cm, uint8_t *hact,
+                uint64_t *counter, Status *st, int32_t *count_out, hipStream_t s) {
   unsigned g = grid_for(n > 0 ? n : 1);
   if (g > kMaxGrid) g = kMaxGrid;
-  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, cm, counter, st,
-                     count_out);
+  hipLaunchKernelGGL(k_hem_commit, dim3(g), dim3(kThreads), 0, s, n, pref, match, cm, hact,
+                     counter, st, count_out);
   PM_LAUNCH_CHECK();
 }
 

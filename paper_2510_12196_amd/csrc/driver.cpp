@@ -405,6 +405,8 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   const size_t mark = cx.ar.mark();
   int32_t *cm = cx.ar.alloc_n<int32_t>(g.n);  // weights; -1 marks a matched vertex
   if (g.n > 0) PM_HIP(hipMemcpyAsync(cm, g.c, sizeof(int32_t) * g.n, hipMemcpyDeviceToDevice, s));
+  uint8_t *hact = cx.ar.alloc_n<uint8_t>(g.n);  // looks for a partner this round
+  fill_u8(hact, 1, g.n, s);
   int32_t *clist = compact ? cx.ar.alloc_n<int32_t>(g.n) : nullptr;
   int32_t *coff = compact ? cx.ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
   int32_t *hoff = cx.aux();
@@ -412,10 +414,10 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   if (compact) {
     while (rounds < 64) {
       ++rounds;
-      hem_prefer(g, cur, lmax, hseed, match, pref, cm, s);
-      hem_commit(g.n, pref, match, cm, cx.counter, cx.dev, nullptr, s);
+      hem_prefer(g, cur, lmax, hseed, match, pref, cm, hact, s);
+      hem_commit(g.n, pref, match, cm, hact, cx.counter, cx.dev, nullptr, s);
       const size_t round_mark = cx.ar.mark();
-      hem_compact(cx.ar, L.cl, g.n, match, pref, clist, coff, s);
+      hem_compact(cx.ar, L.cl, g.n, hact, clist, coff, s);
       PM_HIP(hipMemcpyAsync(hoff, coff, sizeof(int32_t) * (NCLS + 1), hipMemcpyDeviceToHost, s));
       cx.pull();  // the round's work is done: its scratch can go
       cx.ar.rewind(round_mark);
@@ -435,8 +437,8 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
     while (!done && rounds < 64) {
       const int k = 64 - rounds < kHemRoundsPerRead ? 64 - rounds : kHemRoundsPerRead;
       for (int j = 0; j < k; ++j) {
-        hem_prefer(g, cur, lmax, hseed, match, pref, cm, s);
-        hem_commit(g.n, pref, match, cm, cx.counter, cx.dev, counts + rounds + j, s);
+        hem_prefer(g, cur, lmax, hseed, match, pref, cm, hact, s);
+        hem_commit(g.n, pref, match, cm, hact, cx.counter, cx.dev, counts + rounds + j, s);
       }
       PM_HIP(hipMemcpyAsync(hoff, counts + rounds, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
       cx.pull();

@@ -288,8 +288,11 @@ void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, 
 // ---- matching and contraction ---------------------------------------------
 // cm: per vertex its weight while unmatched, -1 once matched (kept by
 // hem_commit), so that a neighbour costs one gather
+// hact: per vertex 1 if it looks for a partner this round (all at the
+// first round of a level; then written by hem_commit).
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
-                const int32_t *match, int32_t *pref, const int32_t *cm, hipStream_t s);
+                const int32_t *match, int32_t *pref, const int32_t *cm, const uint8_t *hact,
+                hipStream_t s);
 // st->count = new matches.  counter: 65 64-bit completion counters, zero
 // between launches.
 // Given the positions pos[0..*count) (ascending) of selected entries of the
@@ -300,12 +303,12 @@ void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int3
 // Compacts the vertices that must recompute their preference: list_out
 // (device int32[n]) gets their ids in class order, off_out (device
 // int32[NCLS + 1]) the class offsets into it.
-void hem_compact(Arena &ar, const Classes &cl, int32_t n, const int32_t *match,
-                 const int32_t *pref, int32_t *list_out, int32_t *off_out, hipStream_t s);
+void hem_compact(Arena &ar, const Classes &cl, int32_t n, const uint8_t *hact,
+                 int32_t *list_out, int32_t *off_out, hipStream_t s);
 // One matching commit; the number of new pairs goes to st->count and, if
 // count_out is not null, to *count_out (device).
-void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int32_t *cm, uint64_t *counter,
-                Status *st, int32_t *count_out, hipStream_t s);
+void hem_commit(int32_t n, const int32_t *pref, int32_t *match, int32_t *cm, uint8_t *hact,
+                uint64_t *counter, Status *st, int32_t *count_out, hipStream_t s);
 // Two-hop matching step (TWOHOP_LEAF / _TWIN / _RELATIVE): groups unmatched
 // vertices and pairs each group in id order.  Returns the vertices matched.
 // Synchronises the stream.
