@@ -168,7 +168,9 @@ typedef struct pm_map_stats {
    *       block and target-or-none) + 20 per mover (row offsets, block,
    *       target, weight)
    *   [3] 12 per active arc (neighbour id, weight, and its weight-or-
-   *       matched word) + 12 per tiled vertex (match, preference, weight)
+   *       matched word) + 12 per tiled vertex (look-again flag, match
+   *       word and weight, rounded up; the row offsets and preference
+   *       of the vertices that look are left out)
    *   [4] 12 per active arc + 24 per source (row offsets, block, weight,
    *       key, destination) */
   int64_t kernel_launches[PM_TIMED_KERNELS];
