@@ -165,8 +165,8 @@ typedef struct pm_map_stats {
    *       + 16 per active vertex (row offsets, block, target) + 9 per tiled
    *       vertex (gain, moved flag)
    *   [2] 16 per active arc (neighbour id, weight, and the neighbour's
-   *       block and target-or-none) + 20 per mover (row offsets, block,
-   *       target, weight)
+   *       block and target-or-none) + 24 per mover (row offsets, block,
+   *       target, weight, and its new block written)
    *   [3] 12 per active arc (neighbour id, weight, and its weight-or-
    *       matched word) + 12 per tiled vertex (look-again flag, match
    *       word and weight, rounded up; the row offsets and preference

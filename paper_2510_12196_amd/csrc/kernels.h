@@ -193,7 +193,8 @@ int64_t *alloc_weight_stripes(Arena &ar, const Hier &h, hipStream_t s);
 // result caching of label propagation)
 // pn: g.n records {block, moved ? target : -1} gathered for the neighbours of
 // movers (written by label propagation's phase 2, or by the rebalancing
-// round); the commit takes the targets from them.
+// round); every mover must be in cl, and its target goes to part[] where it
+// is handled (no tile reads part[] meanwhile).
 void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *part,
                  const uint8_t *moved, uint8_t *lock, int64_t *w, int64_t *wst,
                  int64_t *dj_stripes, const StepEnd *end, const int2 *pn, hipStream_t s,

@@ -1068,6 +1068,7 @@ struct ApplyArgs {
   int64_t *dj;
   uint8_t *dirty;  // label-propagation result caching (nullptr: off)
   const int2 *pn;  // per vertex {block, moved ? target : -1}
+  int32_t *part;   // written for the movers only (read by no tile of this launch)
 };
 
 // Block-weight deltas of one mover (+c to its target, -c to its block): added
@@ -1107,9 +1108,12 @@ __device__ __forceinline__ int64_t ap_delta(const ApplyArgs &A, uint32_t p, uint
   if (a.w) return (int64_t)a.x * (dist(A.h, t, (uint32_t)a.z) - dist(A.h, p, old_u));
   return 2 * (int64_t)a.x * (dist(A.h, t, old_u) - dist(A.h, p, old_u));
 }
-// The mover's own record: block-weight deltas, and its mark.
+// The mover's own record: its new block, block-weight deltas, and its mark.
+// (Every tile reads the blocks from the packed records, never from part[],
+// so the move is committed here.)
 __device__ __forceinline__ void ap_mover(const ApplyArgs &A, int32_t v, uint32_t p, uint32_t t,
                                          WMove &mv) {
+  A.part[v] = (int32_t)t;
   mv.has = true;
   mv.p = p;
   mv.t = t;
@@ -1214,21 +1218,14 @@ __global__ __launch_bounds__(kThreads) void k_apply(ApplyArgs A) {
   if ((threadIdx.x & 63) == 0) stripe_add(A.dj, x);
 }
 
-// part <- target for the moved vertices.  Workgroup 0 also folds the
-// weight-delta stripes into w (all written by the previous launch) and, with
-// has_end, runs the StepEnd epilogue: nothing it reads is written by the
-// other workgroups of this launch, so no cross-workgroup ordering is needed.
-__global__ __launch_bounds__(kThreads) void k_commit(int32_t n, int32_t *part, const int2 *pn,
-                                                     const uint8_t *moved,
-                                                     int32_t nstripes, int64_t *wst, int has_end,
+// The step's end, one workgroup after k_apply (which has written the movers'
+// blocks): folds the weight-delta stripes into w and, with has_end, runs the
+// StepEnd epilogue.
+__global__ __launch_bounds__(kThreads) void k_commit(int32_t nstripes, int64_t *wst, int has_end,
                                                      StepEnd E) {
   extern __shared__ int64_t wl[];
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && moved[v]) part[v] = pn[v].y;
-  if (blockIdx.x == 0) {
-    step_epilogue(E, wst, nstripes, wl, has_end != 0);
-    if (has_end && E.body_ctr && threadIdx.x == 0) *E.body_ctr += 1;
-  }
+  step_epilogue(E, wst, nstripes, wl, has_end != 0);
+  if (has_end && E.body_ctr && threadIdx.x == 0) *E.body_ctr += 1;
 }
 
 // Weight-delta stripes: at most kWeightStripes, and at most 16384 words in all
@@ -1257,7 +1254,7 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
   const Classes tc = tiled(cl, V);
   const unsigned nwg = classed_grid(tc);
   const int nstripes = weight_stripes(h, g.n);
-  ApplyArgs A{g, tc, h, moved, lock, wst, nstripes, dj_stripes, dirty, pn};
+  ApplyArgs A{g, tc, h, moved, lock, wst, nstripes, dj_stripes, dirty, pn, part};
   auto kern = V == 2 ? k_apply<2> : k_apply<1>;
   if (nwg > 0) {
     hipEvent_t ta = nullptr, tb = nullptr;
@@ -1275,8 +1272,8 @@ void apply_moves(const DGraph &g, const Classes &cl, const Hier &h, int32_t *par
   if (end) E = *end;
   E.h = h;
   E.w = w;
-  hipLaunchKernelGGL(k_commit, dim3(grid_for(g.n)), dim3(kThreads), sizeof(int64_t) << h.bits, s,
-                     g.n, part, pn, moved, nstripes, wst, end ? 1 : 0, E);
+  hipLaunchKernelGGL(k_commit, dim3(1), dim3(kThreads), sizeof(int64_t) << h.bits, s, nstripes,
+                     wst, end ? 1 : 0, E);
   PM_LAUNCH_CHECK();
 }
 

@@ -58,7 +58,7 @@ double algorithmic_bytes(int id, const int64_t *u) {
   switch (id) {
     case KT_LP1: return 12.0 * ar + 25.0 * nt;
     case KT_LP2: return 24.0 * ar + 16.0 * na + 9.0 * nt;
-    case KT_APPLY: return 16.0 * ar + 20.0 * na;
+    case KT_APPLY: return 16.0 * ar + 24.0 * na;
     case KT_HEM: return 12.0 * ar + 12.0 * nt;
     default: return 12.0 * ar + 24.0 * na;  // KT_REB
   }
