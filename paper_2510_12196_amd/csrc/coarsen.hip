@@ -88,10 +88,10 @@ __device__ __forceinline__ HemV hem_vertex(const HemArgs &A, int32_t v, bool &ac
   return HemV{A.g.c[v], A.match[v] >= 0};
 }
 
-template <int G, int V>
-__device__ __forceinline__ void hem_group(const HemArgs &A, int cls, int local) {
+template <int G, int V, class CL>
+__device__ __forceinline__ void hem_group(const HemArgs &A, const CL &cl, int cls, int local) {
   group_tiles<G, V>(
-      A.g.xadj, A.g.adj, A.cl, cls, local,
+      A.g.xadj, A.g.adj, cl, cls, local,
       [&](int32_t v, bool &act) { return hem_vertex(A, v, act); },
       [&](int32_t u, int64_t e) { return HemN{u, A.cm[u], A.g.w[e]}; },
       [&](int, bool ok, int32_t v, const HemV &hv, bool act, int, bool valid, const HemN &a) {
@@ -116,24 +116,24 @@ struct CandScratch {
   Cand c[kThreads / 64];
 };
 
-template <int V>
-__global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
-  __shared__ CandScratch sc;
-  {  // one class tile per workgroup
-    const int blk = blockIdx.x;
-    const int cls = find_class(A.cl, blk);
-    const int local = blk - A.cl.wg[cls];
+// One class tile (blk) of the class list cl.
+template <int V, class CL>
+__device__ __forceinline__ void hem_tile(const HemArgs &A, const CL &cl, CandScratch &sc,
+                                         int blk) {
+  {
+    const int cls = find_class(cl, blk);
+    const int local = blk - cl.wg[cls];
     switch (cls) {
       case CLS_ISO:
-        iso_tiles<V>(A.cl, local, [&](int32_t v) { A.pref[v] = -1; });
+        iso_tiles<V>(cl, local, [&](int32_t v) { A.pref[v] = -1; });
         break;
-      case CLS_G8: hem_group<8, V>(A, cls, local); break;
-      case CLS_G16: hem_group<16, V>(A, cls, local); break;
-      case CLS_G32: hem_group<32, V>(A, cls, local); break;
-      case CLS_G64: hem_group<64, V>(A, cls, local); break;
+      case CLS_G8: hem_group<8, V>(A, cl, cls, local); break;
+      case CLS_G16: hem_group<16, V>(A, cl, cls, local); break;
+      case CLS_G32: hem_group<32, V>(A, cl, cls, local); break;
+      case CLS_G64: hem_group<64, V>(A, cl, cls, local); break;
       case CLS_W: {
         int32_t v;
-        if (!w_vertex(A.cl, local, v)) break;
+        if (!w_vertex(cl, local, v)) break;
         bool act;
         const HemV hv = hem_vertex(A, v, act);
         if (!act) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
         break;
       }
       default: {
-        const int32_t v = A.cl.list[A.cl.off[CLS_BIG] + local];
+        const int32_t v = cl.list[cl.off[CLS_BIG] + local];
         bool act;
         const HemV hv = hem_vertex(A, v, act);
         if (!act) {
@@ -195,6 +195,65 @@ __global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
       }
     }
   }
+}
+
+template <int V>
+__global__ __launch_bounds__(kThreads) void k_hem_prefer(HemArgs A) {
+  __shared__ CandScratch sc;
+  hem_tile<V>(A, A.cl, sc, blockIdx.x);  // one class tile per workgroup
+}
+
+// The same over a class list whose offsets are on the device (dev_off,
+// NCLS + 1 entries, written by the active-set compaction of the previous
+// round): every workgroup loads them (uniform loads) and derives the tile
+// bounds, then walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ...  No
+// read-back of the compacted sizes is needed between rounds.
+// Class view of the device-offset launch: the offsets in LDS, the list
+// pointer the kernel argument's (read back from LDS it would lose its
+// address space, and a per-thread copy of the offsets would be indexed
+// dynamically).
+struct ClassesView {
+  const int32_t *list;
+  const int32_t *off;
+  const int32_t *wg;
+};
+
+template <int V>
+__global__ __launch_bounds__(kThreads) void k_hem_prefer_dev(HemArgs A, const int32_t *dev_off) {
+  __shared__ CandScratch sc;
+  __shared__ int32_t soff[NCLS + 1], swg[NCLS + 1];
+  if (threadIdx.x == 0) {
+    swg[0] = 0;
+    for (int c = 0; c <= NCLS; ++c) soff[c] = dev_off[c];
+    for (int c = 0; c < NCLS; ++c) {
+      const int per = class_per_wg(c) * (c == CLS_BIG || c == CLS_W ? 1 : V);
+      swg[c + 1] = swg[c] + (soff[c + 1] - soff[c] + per - 1) / per;
+    }
+  }
+  __syncthreads();
+  const ClassesView cl{A.cl.list, soff, swg};
+  const int ntiles = swg[NCLS];
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) hem_tile<V>(A, cl, sc, t);
+}
+
+// Grid of the device-offset launch: at most this many workgroups, which
+// walk the tiles (at most those of the full class list).
+constexpr unsigned kHemDevGrid = 4096;
+
+void hem_prefer_dev(const DGraph &g, const Classes &cl, const int32_t *list,
+                    const int32_t *dev_off, int64_t lmax, uint64_t hseed, const int32_t *match,
+                    int32_t *pref, const int32_t *cm, const uint8_t *hact, hipStream_t s) {
+  const int V = group_v();
+  const Classes tc = tiled(cl, V);  // upper bound of the tiles
+  unsigned nwg = classed_grid(tc);
+  if (nwg == 0) return;
+  if (nwg > kHemDevGrid) nwg = kHemDevGrid;
+  Classes dc{};
+  dc.list = list;
+  HemArgs A{g, dc, lmax, hseed, match, pref, cm, hact};
+  auto kern = V == 2 ? k_hem_prefer_dev<2> : k_hem_prefer_dev<1>;
+  hipLaunchKernelGGL(kern, dim3(nwg), dim3(kThreads), 0, s, A, dev_off);
+  PM_LAUNCH_CHECK();
 }
 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,

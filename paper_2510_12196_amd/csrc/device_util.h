@@ -267,15 +267,17 @@ __device__ __forceinline__ void wave_keyed_add(bool has, uint32_t key, int64_t v
 // Classed kernels run a capped grid; every workgroup walks the class tiles
 // blockIdx.x, blockIdx.x + gridDim.x, ...
 constexpr int kMaxGrid = 2048;
-__device__ __forceinline__ int find_class(const Classes &cl, int b) {
+// (CL: Classes, or any view with the members list, off[] and wg[])
+template <class CL>
+__device__ __forceinline__ int find_class(const CL &cl, int b) {
   int c = 0;
   while (c < NCLS - 1 && b >= cl.wg[c + 1]) ++c;
   return c;
 }
 
 // Vertex handled by this lane group (G lanes per vertex) in class cls.
-template <int G>
-__device__ __forceinline__ bool group_vertex(const Classes &cl, int cls, int local, int32_t &v) {
+template <int G, class CL>
+__device__ __forceinline__ bool group_vertex(const CL &cl, int cls, int local, int32_t &v) {
   const int idx = local * (kThreads / G) + (int)threadIdx.x / G;
   const int cnt = cl.off[cls + 1] - cl.off[cls];
   if (idx >= cnt) return false;
@@ -284,7 +286,8 @@ __device__ __forceinline__ bool group_vertex(const Classes &cl, int cls, int loc
 }
 
 // W tiles: one vertex per wave, kThreads / 64 vertices per tile.
-__device__ __forceinline__ bool w_vertex(const Classes &cl, int local, int32_t &v) {
+template <class CL>
+__device__ __forceinline__ bool w_vertex(const CL &cl, int local, int32_t &v) {
   const int idx = local * (kThreads / 64) + (int)(threadIdx.x >> 6);
   if (idx >= cl.off[CLS_W + 1] - cl.off[CLS_W]) return false;
   v = cl.list[cl.off[CLS_W] + idx];
@@ -315,8 +318,8 @@ __device__ __forceinline__ void wave_arcs(int64_t beg, int64_t end, L load, U us
 }
 
 // ISO tiles: V vertices per thread.
-template <int V, class F>
-__device__ __forceinline__ void iso_tiles(const Classes &cl, int local, F f) {
+template <int V, class CL, class F>
+__device__ __forceinline__ void iso_tiles(const CL &cl, int local, F f) {
   const int cnt = cl.off[CLS_ISO + 1] - cl.off[CLS_ISO];
 #pragma unroll
   for (int r = 0; r < V; ++r) {
@@ -335,9 +338,9 @@ __device__ __forceinline__ void iso_tiles(const Classes &cl, int local, F f) {
 // ok, v, vv, act, deg, valid, nv) runs per slot r with ok = the slot holds a
 // vertex, valid = this lane holds an arc of an active vertex; every lane of
 // the workgroup reaches it for every slot (group shuffles are allowed).
-template <int G, int V, class VL, class NL, class U>
+template <int G, int V, class CL, class VL, class NL, class U>
 __device__ __forceinline__ void group_tiles(const int64_t *xadj, const int32_t *adj,
-                                            const Classes &cl, int cls, int local, VL vload,
+                                            const CL &cl, int cls, int local, VL vload,
                                             NL nload, U use) {
   constexpr int GPW = kThreads / G;
   const int lane = threadIdx.x % G, grp = threadIdx.x / G;

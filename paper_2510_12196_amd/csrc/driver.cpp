@@ -411,7 +411,9 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
   int32_t *coff = compact ? cx.ar.alloc_n<int32_t>(NCLS + 1) : nullptr;
   int32_t *hoff = cx.aux();
   Classes cur = L.cl;
-  if (compact) {
+  if (compact && tl_timer) {
+    // (counted and timed runs: the compacted sizes are read back each round,
+    // for the host-side unit counts)
     while (rounds < 64) {
       ++rounds;
       hem_prefer(g, cur, lmax, hseed, match, pref, cm, hact, s);
@@ -426,6 +428,33 @@ static int32_t run_hem(Ctx &cx, const Level &L, int64_t lmax, uint64_t seed, int
       if (added == 0) break;
       cur.list = clist;
       for (int c = 0; c <= NCLS; ++c) cur.off[c] = hoff[c];
+    }
+  } else if (compact) {
+    // After each commit the vertices that look again are compacted on the
+    // device (list and class offsets), and the next round's launch reads the
+    // offsets there: rounds go in groups of kHemRoundsPerRead between
+    // read-backs of their match counts, as on small levels (a round after
+    // one that added no pair is a no-op).  The compaction's scratch is
+    // stream-ordered, so the arena is rewound after each group.
+    int32_t *counts = cx.ar.alloc_n<int32_t>(64);
+    bool done = false;
+    while (!done && rounds < 64) {
+      const int k = 64 - rounds < kHemRoundsPerRead ? 64 - rounds : kHemRoundsPerRead;
+      const size_t group_mark = cx.ar.mark();
+      for (int j = 0; j < k; ++j) {
+        if (rounds + j == 0) hem_prefer(g, L.cl, lmax, hseed, match, pref, cm, hact, s);
+        else hem_prefer_dev(g, L.cl, clist, coff, lmax, hseed, match, pref, cm, hact, s);
+        hem_commit(g.n, pref, match, cm, hact, cx.counter, cx.dev, counts + rounds + j, s);
+        if (j + 1 < k || rounds + k < 64) hem_compact(cx.ar, L.cl, g.n, hact, clist, coff, s);
+      }
+      PM_HIP(hipMemcpyAsync(hoff, counts + rounds, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+      cx.pull();
+      cx.ar.rewind(group_mark);
+      for (int j = 0; j < k && !done; ++j) {
+        ++rounds;
+        matched += hoff[j];
+        done = hoff[j] == 0;
+      }
     }
   } else {
     // Rounds go in groups of kHemRoundsPerRead between status read-backs:

@@ -294,6 +294,12 @@ void validate_graph(Arena &ar, const DGraph &g, bool full, int64_t *total_vwgt, 
 void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed,
                 const int32_t *match, int32_t *pref, const int32_t *cm, const uint8_t *hact,
                 hipStream_t s);
+// The same over the compacted class list (list, with its NCLS + 1 class
+// offsets dev_off on the device) of a level whose full class list is cl
+// (whose tiles bound the grid); nothing is read back.
+void hem_prefer_dev(const DGraph &g, const Classes &cl, const int32_t *list,
+                    const int32_t *dev_off, int64_t lmax, uint64_t hseed, const int32_t *match,
+                    int32_t *pref, const int32_t *cm, const uint8_t *hact, hipStream_t s);
 // st->count = new matches.  counter: 65 64-bit completion counters, zero
 // between launches.
 // Given the positions pos[0..*count) (ascending) of selected entries of the
