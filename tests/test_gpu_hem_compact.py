@@ -59,3 +59,22 @@ def test_map_with_compacted_matching_parity(pm, pmo, name):
     assert rc_d == rc_h and st_d.j_final == st_h.j_final
     assert list(st_d.level_hem_rounds[: st_d.levels]) == list(st_h.level_hem_rounds[: st_h.levels])
     assert np.array_equal(host(part_d), part_h)
+
+
+@pytest.mark.parametrize("name", ["rmat14", "rgg14"])
+def test_timed_and_counted_maps_equal_plain_with_compaction(pm, name):
+    # Compacted rounds read their class offsets on the device in plain runs
+    # and read them back every round in timed or counted runs (for the
+    # host-side unit counts): both must give the same matchings and maps.
+    w = gen.get(name)
+    g = w.graph()
+    dg = pm.DeviceGraph.from_host(g)
+    say("compacted matching, plain / timed / counted", name)
+    rc0, p0, s0 = pm.pm_map(dg, w.a, w.d, w.eps, 3)
+    rc1, p1, s1 = pm.pm_map(dg, w.a, w.d, w.eps, 3, kernel_times=True)
+    rc2, p2, s2 = pm.pm_map(dg, w.a, w.d, w.eps, 3, kernel_counts=True)
+    assert rc0 == rc1 == rc2
+    assert s0.j_final == s1.j_final == s2.j_final
+    r0 = list(s0.level_hem_rounds[: s0.levels])
+    assert r0 == list(s1.level_hem_rounds[: s1.levels]) == list(s2.level_hem_rounds[: s2.levels])
+    assert np.array_equal(host(p0), host(p1)) and np.array_equal(host(p0), host(p2))
