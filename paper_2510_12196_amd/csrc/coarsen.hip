@@ -281,17 +281,10 @@ void hem_prefer(const DGraph &g, const Classes &cl, int64_t lmax, uint64_t hseed
 // ---- active-set compaction between matching rounds ---------------------------
 // After the first rounds few vertices must look again (those whose preferred
 // partner was matched), but a launch over all class tiles still visits every
-// vertex.  On large levels the active ones are therefore compacted: a flag
-// per position of the class list, a stable selection of the flagged
-// positions (class order kept), then the new class offsets and the list of
-// vertex ids.
-__global__ void k_hem_active_flags(int32_t n, const int32_t *list, const uint8_t *hact,
-                                   uint8_t *flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  flag[i] = hact[list[i]];
-}
-
+// vertex.  On large levels the active ones are therefore compacted: a stable
+// selection of the class-list positions whose vertex has its look-again flag
+// (read through the list; class order kept), then the new class offsets and
+// the list of vertex ids.
 // off_out[c] = first compacted position of class c (classes by the offsets
 // off[] of the full list); list_out[j] = list[pos[j]].
 __global__ void k_compact_bounds(int32_t n, Classes cl, const int32_t *pos, const int32_t *count,
@@ -319,15 +312,9 @@ void compact_bounds(int32_t n, const Classes &cl, const int32_t *pos, const int3
 
 void hem_compact(Arena &ar, const Classes &cl, int32_t n, const uint8_t *hact,
                  int32_t *list_out, int32_t *off_out, hipStream_t s) {
-  uint8_t *flag = ar.alloc_n<uint8_t>((size_t)n + 1);
   int32_t *pos = ar.alloc_n<int32_t>((size_t)n + 1);
   int32_t *count = ar.alloc_n<int32_t>(1);
-  if (n > 0) {
-    hipLaunchKernelGGL(k_hem_active_flags, dim3(grid_for(n)), dim3(kThreads), 0, s, n, cl.list,
-                       hact, flag);
-    PM_LAUNCH_CHECK();
-  }
-  select_indices(ar, flag, pos, count, n, s);
+  select_list_flagged(ar, hact, cl.list, pos, count, n, s);  // positions whose vertex looks again
   compact_bounds(n, cl, pos, count, list_out, off_out, s);
 }
 

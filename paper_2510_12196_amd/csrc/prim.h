@@ -25,6 +25,9 @@ void scan_excl_masked(Arena &ar, const uint8_t *flags, const int32_t *vwgt, int6
 // *count_dev receives the number selected.
 void select_indices(Arena &ar, const uint8_t *flags, int32_t *out, int32_t *count_dev,
                     int64_t n, hipStream_t s);
+// The same with flags[i] = flag[list[i]] (a gather through the list).
+void select_list_flagged(Arena &ar, const uint8_t *flag, const int32_t *list, int32_t *out,
+                         int32_t *count_dev, int64_t n, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 void sort_pairs(Arena &ar, const uint32_t *kin, uint32_t *kout, const int32_t *vin,

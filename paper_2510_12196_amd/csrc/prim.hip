@@ -39,6 +39,13 @@ struct Widen {
   __host__ __device__ int64_t operator()(int32_t x) const { return (int64_t)x; }
 };
 
+// flag of the vertex at position i of a list
+struct ListFlag {
+  const uint8_t *flag;
+  const int32_t *list;
+  __host__ __device__ uint8_t operator()(int32_t i) const { return flag[list[i]]; }
+};
+
 }  // namespace
 
 void scan_excl(Arena &ar, const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
@@ -103,6 +110,20 @@ void select_indices(Arena &ar, const uint8_t *flags, int32_t *out, int32_t *coun
   rocprim::counting_iterator<int32_t> ids(0);
   run_two_phase(ar, [&](void *t, size_t &b) {
     return rocprim::select(t, b, ids, flags, out, count_dev, (size_t)n, s);
+  });
+}
+
+void select_list_flagged(Arena &ar, const uint8_t *flag, const int32_t *list, int32_t *out,
+                         int32_t *count_dev, int64_t n, hipStream_t s) {
+  if (n <= 0) {
+    PM_HIP(hipMemsetAsync(count_dev, 0, sizeof(int32_t), s));
+    return;
+  }
+  rocprim::counting_iterator<int32_t> ids(0);
+  rocprim::transform_iterator<rocprim::counting_iterator<int32_t>, ListFlag, uint8_t> fl(
+      ids, ListFlag{flag, list});
+  run_two_phase(ar, [&](void *t, size_t &b) {
+    return rocprim::select(t, b, ids, fl, out, count_dev, (size_t)n, s);
   });
 }
 
