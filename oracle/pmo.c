@@ -16,8 +16,8 @@
  *
  * Parity unpinned (fixed only by this file; no closed form or printed value
  * reaches them): the breadth-first split used as initial partitioner (beyond
- * a closed-form path), and the coarsening stop on stalls (the 8k threshold
- * itself is pinned).
+ * its closed-form cases: a path, a star, two interleaved components), and the
+ * coarsening stop on stalls (the 8k threshold itself is pinned).
  */
 #include "pmo.h"
 
