@@ -31,6 +31,23 @@ def graph_from_fixture(fx):
     return gen.from_edges(n, e[:, 0], e[:, 1], e[:, 2], vw)
 
 
+def ip_fixture_graph(fx):
+    """Graph of an initial-partitioning fixture: a path, a star (centre 0) or
+    two interleaved paths (evens and odds), unit weights."""
+    import gen
+
+    n = fx["n"]
+    if "star" in fx["what"]:
+        u = np.zeros(n - 1, np.int64)
+        v = np.arange(1, n)
+    elif "interleaved" in fx["what"]:
+        u = np.concatenate([np.arange(0, n - 2, 2), np.arange(1, n - 2, 2)])
+        v = u + 2
+    else:
+        return gen.path_graph(n)
+    return gen.from_edges(n, u, v, np.ones(len(u), np.int32), np.ones(n, np.int32))
+
+
 @pytest.fixture(scope="session")
 def pmo():
     import oracle

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import gen
-from conftest import golden, graph_from_fixture
+from conftest import golden, graph_from_fixture, ip_fixture_graph
 
 pytestmark = pytest.mark.gpu
 
@@ -310,6 +310,16 @@ def test_initial_partition_parity(pm, pmo, name, a, d):
     g = gen.get(name).graph()
     assert np.array_equal(host(pm.pm_initial_partition(dev(pm, g), a, d)),
                           pmo.initial_partition(g, a))
+
+
+@pytest.mark.parametrize("fixture", ["ip_path16.json", "ip_star16.json", "ip_two_paths16.json"])
+def test_initial_partition_closed_forms(pm, fixture):
+    # the hand-derived partitions of tests/golden (path, star, two
+    # interleaved components), on the library's own initial partitioner
+    fx = golden(fixture)
+    g = ip_fixture_graph(fx)
+    say("initial_partition closed form", fixture)
+    assert host(pm.pm_initial_partition(dev(pm, g), fx["a"], fx["d"])).tolist() == fx["part"]
 
 
 # ---------------------------------------------------------------------------

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import gen
-from conftest import golden, graph_from_fixture
+from conftest import golden, graph_from_fixture, ip_fixture_graph
 
 
 # ----------------------------------------------------------------------------
@@ -683,24 +683,13 @@ def test_initial_partition_path_closed_form(pmo):
     assert pmo.comm_cost(g, part, fx["a"], fx["d"]) == fx["J_ordered"]
 
 
-def _fixture_graph(fx):
-    n = fx["n"]
-    if "star" in fx["what"]:
-        u = np.zeros(n - 1, np.int64)
-        v = np.arange(1, n)
-    else:  # two interleaved paths: evens and odds
-        u = np.concatenate([np.arange(0, n - 2, 2), np.arange(1, n - 2, 2)])
-        v = u + 2
-    return gen.graphs.from_edges(n, u, v, np.ones(len(u), np.int32), np.ones(n, np.int32))
-
-
 @pytest.mark.parametrize("fixture", ["ip_star16.json", "ip_two_paths16.json"])
 def test_initial_partition_restart_closed_forms(pmo, fixture):
     # the breadth-first order visits neighbours in ascending order and
     # restarts at the smallest unvisited id (a half without inner edges, a
     # second component); every cut is at the exact proportional weight
     fx = golden(fixture)
-    g = _fixture_graph(fx)
+    g = ip_fixture_graph(fx)
     part = pmo.initial_partition(g, fx["a"])
     assert part.tolist() == fx["part"]
     assert pmo.comm_cost(g, part, fx["a"], fx["d"]) == fx["J_ordered"]
